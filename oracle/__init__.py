@@ -1,0 +1,198 @@
+"""FP64 CPU oracle for the Friedkin-Johnsen equilibrium z = (I+L)^{-1} s.
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library and never imports it.
+
+What it computes (arXiv 2507.14864):
+  * ``dense_solve``      - the definition, z = (I+L)^{-1} s (Lemma 1), by LU
+                           (numpy.linalg.solve) for small graphs;
+  * ``exact``            - the same z to ||s-(I+L)z||_inf <= 1e-12 by Jacobi-PCG
+                           (undirected) or Gauss-Seidel (directed, Eq. (gauss)),
+                           which bounds |z - z_exact| entrywise by the same
+                           number because (I+L)^{-1} is nonnegative and
+                           row-stochastic (Sec. 3.3);
+  * ``push``             - ImprovedBLISOR (Alg. 2 around Alg. 3; Alg. 1 when
+                           omega = 1), sequential FIFO, FP64;
+  * ``metrics``          - P, D, I, C of Table 1, compensated FP64 sums;
+  * ``certificate``      - max_v |r_v| / h_v for a candidate z, the stopping
+                           rule of Alg. 3 with the shift of Alg. 2 (Lemma 7);
+  * ``mpnn``             - the warm-start network's forward/backward in FP64.
+"""
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(path)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        lib.oracle_threads.restype = i32
+        lib.oracle_degrees.argtypes = [i64, vp, vp, vp]
+        lib.oracle_transpose.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+        lib.oracle_residual.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+        lib.oracle_cg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, i32]
+        lib.oracle_cg.restype = i32
+        lib.oracle_gs.argtypes = [i64, vp, vp, vp, vp, vp, dbl, i32]
+        lib.oracle_gs.restype = i32
+        lib.oracle_push.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, vp, i64, i64, vp, vp, vp]
+        lib.oracle_push.restype = i32
+        lib.oracle_metrics.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp]
+        _LIB = lib
+    return _LIB
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _graph_arrays(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    w = None if g.w is None else np.ascontiguousarray(g.w, dtype=np.float32)
+    return rp, col, w
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops (residual, CG) use."""
+    return int(_lib().oracle_threads())
+
+
+def degrees(g) -> np.ndarray:
+    """d_i = sum_j a_ij (Sec. 3.2)."""
+    rp, col, w = _graph_arrays(g)
+    d = np.empty(g.n, dtype=np.float64)
+    _lib().oracle_degrees(g.n, _p(rp), _p(w), _p(d))
+    return d
+
+
+def transpose(g):
+    """CSR of A^T: row v lists u with a_uv > 0."""
+    rp, col, w = _graph_arrays(g)
+    trp = np.empty(g.n + 1, dtype=np.int32)
+    tcol = np.empty(max(g.nnz, 1), dtype=np.int32)
+    tw = np.empty(max(g.nnz, 1), dtype=np.float32)
+    _lib().oracle_transpose(g.n, _p(rp), _p(col), _p(w), _p(trp), _p(tcol), _p(tw))
+    return trp, tcol[:g.nnz], tw[:g.nnz]
+
+
+def residual(g, b: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """r = b - (I+L) z in FP64 (Lemma 4: z_exact - z = (I+L)^{-1} r)."""
+    rp, col, w = _graph_arrays(g)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    r = np.empty(g.n, dtype=np.float64)
+    _lib().oracle_residual(g.n, _p(rp), _p(col), _p(w), _p(b), _p(z), _p(r))
+    return r
+
+
+def dense_matrix(g) -> np.ndarray:
+    """I + L = I + D - A as a dense FP64 matrix (Sec. 3.2)."""
+    n = g.n
+    M = np.zeros((n, n), dtype=np.float64)
+    for i in range(n):
+        for k in range(int(g.row_ptr[i]), int(g.row_ptr[i + 1])):
+            j = int(g.col[k])
+            a = 1.0 if g.w is None else float(g.w[k])
+            M[i, j] -= a
+            M[i, i] += a
+    M[np.diag_indices(n)] += 1.0
+    return M
+
+
+def dense_solve(g, s: np.ndarray) -> np.ndarray:
+    """z = (I+L)^{-1} s by LU with partial pivoting (Lemma 1)."""
+    return np.linalg.solve(dense_matrix(g), np.asarray(s, dtype=np.float64))
+
+
+def cg(g, s, tol: float = 1e-12, maxit: int = 100000, z0=None):
+    """Jacobi-PCG on (I+L) z = s, undirected only.  Returns (z, iterations)."""
+    if g.directed:
+        raise ValueError("CG needs a symmetric I+L; use gs() for directed graphs")
+    rp, col, w = _graph_arrays(g)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    z = np.zeros(g.n) if z0 is None else np.array(z0, dtype=np.float64)
+    it = _lib().oracle_cg(g.n, _p(rp), _p(col), _p(w), _p(s), _p(z), tol, maxit)
+    if it < 0:
+        raise RuntimeError("oracle CG did not reach the tolerance")
+    return z, it
+
+
+def gs(g, s, tol: float = 1e-12, maxsweeps: int = 100000, z0=None):
+    """Natural-order Gauss-Seidel (Eq. (gauss)).  Returns (z, sweeps)."""
+    rp, col, w = _graph_arrays(g)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    z = np.zeros(g.n) if z0 is None else np.array(z0, dtype=np.float64)
+    sw = _lib().oracle_gs(g.n, _p(rp), _p(col), _p(w), _p(s), _p(z), tol, maxsweeps)
+    if sw < 0:
+        raise RuntimeError("oracle Gauss-Seidel did not reach the tolerance")
+    return z, sw
+
+
+def exact(g, s, tol: float = 1e-12) -> np.ndarray:
+    """z = (I+L)^{-1} s: dense LU for n <= 4096, else PCG (undirected) or
+    Gauss-Seidel (directed) until ||s - (I+L) z||_inf <= tol."""
+    if g.n <= 4096:
+        return dense_solve(g, s)
+    if g.directed:
+        return gs(g, s, tol)[0]
+    return cg(g, s, tol)[0]
+
+
+def push(g, s, eps: float, sigma: float = 1e-5, c: float = 1e-5, omega: float = 1.0,
+         z0=None, max_pops: int = 0, max_edge_visits: int = 0):
+    """Sequential ImprovedBLISOR (Alg. 2 + Alg. 3).
+
+    Returns dict(z=zhat, r=tracked residual of the shifted system, pops,
+    edge_visits, capped, diverged)."""
+    rp, col, w = _graph_arrays(g)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    zz = None if z0 is None else np.ascontiguousarray(z0, dtype=np.float64)
+    z = np.empty(g.n)
+    r = np.empty(g.n)
+    st = np.zeros(2, dtype=np.int64)
+    capped = _lib().oracle_push(g.n, _p(rp), _p(col), _p(w), _p(s), eps, sigma, c, omega,
+                                _p(zz), max_pops, max_edge_visits, _p(z), _p(r), _p(st))
+    return dict(z=z, r=r, pops=int(st[0]), edge_visits=int(st[1]), capped=capped == 1,
+                diverged=capped == 2)
+
+
+def metrics(g, s, z) -> dict:
+    """Table 1: P, D, I, C (+ mean of z), compensated FP64."""
+    rp, col, w = _graph_arrays(g)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty(5)
+    _lib().oracle_metrics(g.n, _p(rp), _p(col), _p(w), 1 if g.directed else 0, _p(s), _p(z), _p(out))
+    return dict(P=out[0], D=out[1], I=out[2], C=out[3], mean=out[4])
+
+
+def certificate(g, s, z, eps: float, sigma: float = 1e-5, c: float = 1e-5) -> float:
+    """max_v |r_v| / h_v with r = s' - (I+L)(z + c) = s - (I+L) z and
+    h = eps' (s + c), eps' = sigma eps / (c + sigma) (Alg. 2, Alg. 3).
+    A value <= 1 certifies |z - z_exact| <= eps' (z_exact + c) entrywise
+    (Lemma 7 with the shift of Alg. 2)."""
+    r = residual(g, s, z)
+    h = sigma * eps / (c + sigma) * (np.asarray(s, dtype=np.float64) + c)
+    return float(np.max(np.abs(r) / h)) if g.n else 0.0
+
+
+def max_rel_error(z_est, z_true, floor: float = 1e-5) -> float:
+    """max over v with z_true_v >= floor of |z_est_v - z_true_v| / z_true_v
+    (the error measure of Sec. 6 restricted as in the ImprovedBLI lemma)."""
+    z_est = np.asarray(z_est, dtype=np.float64)
+    z_true = np.asarray(z_true, dtype=np.float64)
+    m = z_true >= floor
+    if not np.any(m):
+        return 0.0
+    return float(np.max(np.abs(z_est[m] - z_true[m]) / z_true[m]))
