@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: time to a certified relative error of 1e-4 for the FJ equilibrium
+of a 10M-node undirected power-law graph on one MI355X, plus the Table 1
+measures.
+
+One step = the whole hot path over the resident synthetic input: shift and
+init (Alg. 2), over-relaxed sweeps or push rounds (Alg. 1/3), FP64
+certificate, unshift, and the P/D/I/C reductions.  Graph ingest (validation,
+degrees, colouring, relabelling) happens once before the timed region and is
+reported separately.
+
+Prints one JSON line (rank 0).  Diagnostics go to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (n, edge samples, gamma, directed, weighted, seed, opinion kind, eps, default omega)
+    "cl10m": dict(n=10_000_000, m=100_000_000, gamma=2.3, directed=False, weighted=False, seed=3,
+                  s_kind="bimodal", eps=1e-4, omega=1.5,
+                  desc="undirected Chung-Lu n=10M, 100M edge samples (~200M stored arcs), gamma=2.3, "
+                       "unit weights, s=0.5Beta(2,8)+0.5Beta(8,2)"),
+    "cl1m_directed": dict(n=1_000_000, m=10_000_000, gamma=2.1, directed=True, weighted=True, seed=2,
+                          s_kind="uniform", eps=1e-4, omega=1.0,
+                          desc="directed Chung-Lu n=1M, 10M arcs, out/in exponent 2.1, weights U[0.5,1.5], "
+                               "s~U[0,1]"),
+    "ba2000": dict(n=2000, m=3, gamma=0.0, directed=False, weighted=False, seed=1, s_kind="uniform", eps=1e-8,
+                   omega=1.0, desc="Barabasi-Albert n=2000 m=3, s~U[0,1], FP64"),
+}
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_input(wl):
+    import synth
+    if wl["gamma"] == 0.0:
+        g = synth.barabasi_albert(wl["n"], wl["m"], wl["seed"])
+    else:
+        g = synth.chung_lu(wl["n"], wl["m"], wl["gamma"], wl["seed"], directed=wl["directed"],
+                           weighted=wl["weighted"])
+    s = synth.opinions(g.n, wl["s_kind"], wl["seed"])
+    return g, s
+
+
+def algorithmic_bytes(schedule, stats, n, nnz, weighted):
+    """Bytes the iteration kernel must move, without cache reuse.
+
+    SOR class sweep (pull): per row scanned 36 B (row_ptr 4, s' 8, 1+d 8,
+    zhat' read 8, 1/(1+d) 8 folded in as read), per updated row 8 B (zhat'
+    write), per arc 12 B (col 4 + FP64 gather 8), +4 B with weights.
+    Push round: per node scanned 8 B (r, h), per push 44 B (row_ptr 8, r
+    exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + r atomic
+    RMW 8), +4 B with weights."""
+    per_arc = 16 if weighted else 12
+    if schedule == "sor":
+        rows = stats["rounds"] * n
+        return 36 * rows + 8 * stats["pushes"] + per_arc * stats["edge_visits"]
+    return 8 * stats["rounds"] * n + 44 * stats["pushes"] + per_arc * stats["edge_visits"]
+
+
+def cpu_baseline(wl, budget_s):
+    """The oracle's sequential ImprovedBLISOR (FIFO, FP64, one core) on a
+    bounded sample: a graph of the same law at 1/10 of the node and edge
+    count, solved to the same eps; time scaled by the arc-count ratio."""
+    import oracle
+    import synth
+    frac = 10
+    n, m = wl["n"] // frac, wl["m"] // frac
+    if wl["gamma"] == 0.0:
+        return None
+    g = synth.chung_lu(n, m, wl["gamma"], wl["seed"], directed=wl["directed"], weighted=wl["weighted"])
+    s = synth.opinions(g.n, wl["s_kind"], wl["seed"])
+    omega = wl["omega"] if not wl["directed"] else 1.0
+    t0 = time.perf_counter()
+    p = oracle.push(g, s, wl["eps"], omega=omega, max_edge_visits=int(budget_s * 8e7))
+    dt = time.perf_counter() - t0
+    full_nnz_estimate = g.nnz * frac
+    scale = full_nnz_estimate / g.nnz
+    if p["capped"]:
+        # still running when the budget ran out: extrapolate from the visit rate
+        return dict(value=None, unit="s", cores=1, kind="oracle",
+                    sample=f"sequential ImprovedBLISOR omega={omega} on {g.n} nodes/{g.nnz} arcs hit the "
+                           f"{budget_s}s budget after {p['edge_visits']} edge visits")
+    return dict(value=dt * scale, unit="s", cores=1, kind="oracle",
+                sample=f"sequential FIFO ImprovedBLISOR (omega={omega}, eps={wl['eps']}) fully solved on a "
+                       f"{g.n}-node/{g.nnz}-arc graph of the same law in {dt:.2f}s "
+                       f"({p['edge_visits']} edge visits); scaled x{scale:.1f} by arc count")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cl10m", choices=sorted(WORKLOADS))
+    ap.add_argument("--schedule", default="sor", choices=["sor", "push"])
+    ap.add_argument("--omega", type=float, default=None)
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2507_14864_amd as fj
+
+    wl = WORKLOADS[args.workload]
+    omega = args.omega if args.omega is not None else (wl["omega"] if args.schedule == "sor" else 1.0)
+    precision = args.precision or ("fp64" if wl["eps"] < 1e-6 else "fp32")
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    g, s = make_input(wl)
+    log(f"input: n={g.n} nnz={g.nnz} generated in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    G = fj.Graph.from_host(g, dev, colour=(args.schedule == "sor"))
+    torch.cuda.synchronize()
+    ingest_s = time.perf_counter() - t0
+    info = G.info()
+    log(f"ingest {ingest_s:.2f}s info={info}")
+    sd = torch.from_numpy(s).to(dev)
+    z = torch.empty(g.n, dtype=torch.float64, device=dev)
+
+    def step(profile=False):
+        zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
+                          out=z, profile=profile)
+        m = fj.metrics(G, sd, zz)
+        return st, m
+
+    for _ in range(args.warmup):
+        st, m = step()
+        log(f"warmup: {st}")
+    torch.cuda.synchronize()
+    times = []
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        ta = time.perf_counter()
+        st, m = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ta)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    ms_per_step = 1000.0 * total / max(args.steps, 1)
+    log(f"steps: {[round(t * 1000, 2) for t in times]} ms; last stats {st}; metrics {m}")
+
+    roofline = None
+    if not args.no_profile:
+        # same step with every launch of the iteration kernel bracketed by HIP
+        # events on the library's stream
+        stp, _ = step(profile=True)
+        bytes_total = algorithmic_bytes(args.schedule, stp, g.n, g.nnz, g.w is not None)
+        launches = max(stp["kernel_launches"], 1)
+        avg_ms = stp["kernel_ms"] / launches
+        achieved = bytes_total / (stp["kernel_ms"] * 1e-3) / 1e9
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                        kernel="k_sor_class" if args.schedule == "sor" else "k_push_round",
+                        bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
+                        launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))
+        log(f"profiled step: {stp}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_budget)
+        log(f"cpu baseline: {cpu}")
+
+    value = ms_per_step / 1000.0
+    out = {
+        "metric": "time to rel. err 1e-4 on 10M-node graph, HBM GB/s; warm vs cold-start speedup",
+        "value": round(value, 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": g.n, "nnz": g.nnz, "eps": wl["eps"], "omega": omega,
+                   "schedule": args.schedule, "precision": precision, "colours": info["num_colours"],
+                   "sweeps_or_rounds": st["rounds"], "certified": st["certified"],
+                   "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),
+                   "metrics": {k: m[k] for k in ("P", "D", "I", "C")}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * fj.h -- C ABI of libfj.so: the Friedkin-Johnsen equilibrium z = (I+L)^{-1} s
+ * by residual push with over-relaxation on MI355X (gfx950), and the Table 1
+ * measures over z.
+ *
+ * Method: "Efficient Algorithms for Relevant Quantities of Friedkin-Johnsen
+ * Opinion Dynamics Model" (arXiv 2507.14864): Lemma 1 (definition of z),
+ * Alg. 1-3 (BoundLocalIter, ImprovedBLI, BoundLocalIterSOR), Lemma 4
+ * (residual invariant), Lemma 7 (relative-error certificate), Thm. 8 (push
+ * equals Gauss-Seidel), Eqs. (sor1)-(sor3), Table 1 (measures).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *    tensor's data_ptr) unless the comment says [host].
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *  - The library never allocates device memory.  Callers query the workspace
+ *    size of each call and pass a buffer of at least that many bytes, aligned
+ *    to 256 bytes.  A graph workspace must stay alive and untouched while the
+ *    graph handle exists.  A solve/metrics workspace may be reused between
+ *    calls but not by two concurrent calls.
+ *  - Graph: CSR of the adjacency matrix A.  Row i lists the nodes j with
+ *    a_ij > 0, i.e. the nodes node i listens to (the sum of Eq. (1)).
+ *    d_i = sum_j a_ij and L = D - A (Sec. 3.2).  Rows must be strictly
+ *    increasing in column, without self-loops; weights (optional) finite and
+ *    > 0.  An undirected graph stores every edge in both rows with equal
+ *    weights.  Indices are int32, so nnz < 2^31.
+ *  - Every call returns an fj_status; no exception crosses the ABI.  On an
+ *    error other than FJ_ERR_NOT_CONVERGED, outputs are left untouched;
+ *    fj_last_error() returns a message for the calling thread.
+ */
+#ifndef FJ_H
+#define FJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fj_status;
+#define FJ_OK 0
+#define FJ_ERR_INVALID_ARGUMENT 1
+#define FJ_ERR_WORKSPACE_TOO_SMALL 2
+#define FJ_ERR_NOT_CONVERGED 3
+#define FJ_ERR_HIP 4
+#define FJ_ERR_UNSUPPORTED 5
+
+/* Thread-local message for the last non-OK status returned on this thread. */
+const char* fj_last_error(void);
+
+/* Library version, for the Python binding's sanity check. */
+int32_t fj_version(void);
+
+/* ------------------------------------------------------------------ graph */
+
+typedef struct fj_graph fj_graph; /* opaque host object referencing device buffers */
+
+typedef struct {
+    int64_t n;              /* nodes */
+    int64_t nnz;            /* stored arcs = row_ptr[n] */
+    const int32_t* row_ptr; /* device [n+1], row_ptr[0] = 0, nondecreasing */
+    const int32_t* col;     /* device [nnz] */
+    const float* w;         /* device [nnz] weights a_ij, or NULL for unit weights */
+    int32_t directed;       /* 0: A must be symmetric (checked by fj_graph_create) */
+} fj_graph_desc;
+
+/* fj_graph_create flags */
+#define FJ_GRAPH_COLOUR 1 /* also build the colour-ordered copy used by FJ_SCHED_SOR */
+
+/* Bytes of graph workspace fj_graph_create needs for this desc and flags. */
+size_t fj_graph_workspace_bytes(const fj_graph_desc* desc, int32_t flags);
+
+/* Validate the CSR (indices in range, rows strictly increasing, no self-loops,
+ * positive finite weights, symmetry when undirected), then build what the
+ * solver needs in `ws`: d and 1/(1+d) (Sec. 3.2); for directed graphs the CSR
+ * of A^T (a push at v feeds every u with a_uv > 0, the column of A in the
+ * proof of Lemma 4); with FJ_GRAPH_COLOUR a colouring of the symmetrised
+ * pattern A + A^T and a relabelled copy of A whose colour classes are
+ * contiguous (the order the SOR sweeps visit, Thm. 8 with Eq. (sor1)).
+ * The caller's row_ptr/col/w must outlive the handle.  Synchronizes `stream`.
+ * Errors: FJ_ERR_INVALID_ARGUMENT (bad desc or CSR), FJ_ERR_WORKSPACE_TOO_SMALL,
+ * FJ_ERR_UNSUPPORTED (more colours than supported), FJ_ERR_HIP. */
+fj_status fj_graph_create(const fj_graph_desc* desc, int32_t flags, void* ws, size_t ws_bytes,
+                          void* stream, fj_graph** out);
+
+/* Free the host object (the caller frees the workspace). NULL is accepted. */
+fj_status fj_graph_destroy(fj_graph* g);
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t directed, weighted;
+    int32_t max_degree;    /* longest row of A */
+    int32_t max_in_degree; /* longest row of A^T */
+    int32_t num_colours;   /* 0 when built without FJ_GRAPH_COLOUR */
+    int32_t colour_rounds; /* parallel colouring rounds used */
+} fj_graph_info;
+
+/* [host] out. */
+fj_status fj_graph_get_info(const fj_graph* g, fj_graph_info* out);
+
+/* Colour classes: sizes[k] for k < num_colours, [host] out with room for
+ * num_colours entries.  FJ_ERR_INVALID_ARGUMENT if the graph has no colouring. */
+fj_status fj_graph_colour_sizes(const fj_graph* g, int64_t* sizes);
+
+/* Device copy of the colour of every node (original labels), int32 [n]. */
+fj_status fj_graph_colours(const fj_graph* g, int32_t* colours, void* stream);
+
+/* ------------------------------------------------------------------ solve */
+
+#define FJ_FP32 0 /* FP32 residual pushes; FP64 estimate, certificate and measures */
+#define FJ_FP64 1 /* FP64 throughout */
+
+#define FJ_SCHED_AUTO 0 /* SOR when the graph has a colouring, else PUSH */
+#define FJ_SCHED_PUSH 1 /* frontier push rounds (Alg. 1 order relaxed to rounds), omega in (0,1] */
+#define FJ_SCHED_SOR 2  /* colour-ordered over-relaxed sweeps, omega in (0,2); needs FJ_GRAPH_COLOUR */
+
+typedef struct {
+    double eps;   /* relative error target eps in (0,1) (Alg. 2 input) */
+    double omega; /* relaxation factor (Alg. 3 input); 1 = BoundLocalIter */
+    double c;     /* opinion shift of Alg. 2, >= 0 (paper: 1e-5) */
+    double sigma; /* threshold of Alg. 2, > 0 (paper: 1e-5); eps' = sigma eps / (c + sigma) */
+    int32_t precision; /* FJ_FP32 or FJ_FP64 */
+    int32_t schedule;  /* FJ_SCHED_* */
+    int64_t max_edge_visits; /* work cap; 0 selects 4096 * (nnz + n) */
+    int32_t max_refinements; /* FP64 re-seeding passes after a failed certificate; <0 selects 8 */
+    int32_t check_every;     /* rounds/sweeps between host checks of progress; <=0 selects 8 */
+    const double* z0;        /* device [n] warm start (any vector, Lemma 4), or NULL */
+    int32_t profile;         /* nonzero: time every launch of the iteration kernel with HIP
+                                events on `stream` (adds small gaps between launches) */
+} fj_solve_opts;
+
+typedef struct {
+    int64_t pushes;       /* node updates (pushes / row relaxations) */
+    int64_t edge_visits;  /* arcs read by those updates */
+    int64_t rounds;       /* push rounds or full sweeps */
+    int64_t launches;     /* kernel launches of the iteration */
+    int32_t refinements;  /* certificate failures that re-seeded the residual */
+    int32_t certified;    /* 1 if max_v |r_v| / h_v <= 1 in FP64 at return */
+    double max_ratio;     /* max_v |r_v| / h_v of the FP64 residual of the returned z */
+    double seconds;       /* host wall time of the call */
+    double kernel_ms;     /* profile mode: summed event time of the iteration kernel launches */
+    int64_t kernel_launches; /* profile mode: launches timed */
+    int32_t num_colours;  /* colour classes swept (SOR), 0 for push */
+} fj_solve_stats;
+
+/* Bytes of solve workspace for this graph and options. */
+size_t fj_solve_workspace_bytes(const fj_graph* g, const fj_solve_opts* opts);
+
+/* ImprovedBLISOR (Alg. 2 around Alg. 3; Alg. 1 when omega = 1) on the GPU.
+ * s: device [n] internal opinions, finite and >= 0 (Sec. 3.3; Lemma 6 needs
+ * s >= 0); c = 0 needs min s > 0 (Sec. 5.1.3).  z: device [n] output.
+ * On return with FJ_OK the FP64 residual r = s - (I+L) z satisfies
+ * |r_v| <= eps' (s_v + c) for every v, which by Lemma 7 (with the shift of
+ * Alg. 2) bounds |z - z_exact| <= eps' (z_exact + c) entrywise, hence relative
+ * error <= eps wherever z_exact >= sigma.
+ * FJ_ERR_NOT_CONVERGED: the work cap was hit, the iteration diverged (SOR with
+ * omega > 1 on a directed graph is not guaranteed to converge), or the
+ * refinement budget ran out; z then holds the last estimate and
+ * stats->certified = 0.  stats: [host] or NULL.  Synchronizes `stream`. */
+fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve_opts* opts, double* z,
+                   void* ws, size_t ws_bytes, fj_solve_stats* stats, void* stream);
+
+/* --------------------------------------------------------------- measures */
+
+typedef struct {
+    double P;    /* polarization  sum_i (z_i - mean)^2                      (Table 1) */
+    double D;    /* disagreement  sum over edges of a_ij (z_i - z_j)^2; an undirected
+                    edge counts once, a directed arc once                  (Table 1) */
+    double I;    /* internal conflict sum_i (z_i - s_i)^2                    (Table 1) */
+    double C;    /* controversy   sum_i z_i^2                                (Table 1) */
+    double mean; /* 1^T z / n, the centring of Sec. 3.4 */
+} fj_metrics_out;
+
+size_t fj_metrics_workspace_bytes(const fj_graph* g);
+
+/* FP64 reductions in a fixed order: bitwise reproducible for the same inputs.
+ * s, z: device [n].  out: [host].  Synchronizes `stream`. */
+fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* FP64 certificate of an arbitrary z: max_v |s_v - ((I+L) z)_v| / (eps' (s_v + c)).
+ * out_max_ratio: [host].  Synchronizes `stream`.  Uses the metrics workspace. */
+fj_status fj_certify(const fj_graph* g, const double* s, const double* z, double eps, double c,
+                     double sigma, double* out_max_ratio, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FJ_H */

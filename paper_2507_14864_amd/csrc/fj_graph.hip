@@ -1,0 +1,583 @@
+// Graph ingest: validation, degrees, CSR(A^T), colouring of A + A^T and the
+// colour-ordered relabelled copy of A.
+//
+// d_i = sum_j a_ij and L = D - A (Sec. 3.2).  A push at v hands residual to
+// every u with a_uv > 0, which is column v of A (proof of Lemma 4), so directed
+// graphs also get CSR(A^T).  Over-relaxed sweeps need an order in which
+// simultaneously updated rows do not read each other; colour classes of the
+// symmetrised pattern give such an order, and within a class the simultaneous
+// row updates equal the sequential Gauss-Seidel updates of Thm. 8.
+#include <algorithm>
+#include <cstring>
+
+#include "fj_device.h"
+#include "fj_internal.h"
+
+namespace fj {
+
+// ------------------------------------------------------------------- scan
+namespace {
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ int block_excl_scan_int(int v, int* lds /*[kScanThreads/64]*/, int* total) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    int incl = wave_incl_scan(v);
+    if (lane == 63) lds[w] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < kScanThreads / 64; ++i) {
+        int t = lds[i];
+        if (i < w) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(const int32_t* in, int64_t n, int32_t* bsum) {
+    __shared__ int lds[kScanThreads / 64];
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    int tot;
+    block_excl_scan_int(s, lds, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_bsum(int32_t* bsum, int64_t nb) {
+    __shared__ int lds[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        const int lane = lane_id(), w = threadIdx.x >> 6;
+        int incl = wave_incl_scan(v);
+        if (lane == 63) lds[w] = incl;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            int t = lds[k];
+            if (k < w) off += t;
+            tot += t;
+        }
+        int c = carry;
+        if (i < nb) bsum[i] = c + off + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int32_t* out, int64_t n,
+                                                             const int32_t* bsum) {
+    __shared__ int lds[kScanThreads / 64];
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int off = block_excl_scan_int(s, lds, &tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = off;
+        off += v[k];
+    }
+}
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) { return sizeof(int32_t) * static_cast<size_t>((n + kScanTile - 1) / kScanTile + 1); }
+
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int32_t* bsum = static_cast<int32_t*>(tmp);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kScanThreads), 0, st, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, st, in, out, n, bsum);
+}
+
+// ------------------------------------------------------------- validation
+namespace {
+enum : int {
+    kErrRowPtr = 1, kErrColRange = 2, kErrSelfLoop = 4, kErrUnsorted = 8, kErrWeight = 16, kErrAsym = 32
+};
+
+__global__ void k_validate_rows(int64_t n, int64_t nnz, const int32_t* __restrict__ row_ptr,
+                                const int32_t* __restrict__ col, const float* __restrict__ w, int* err) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t b = row_ptr[i], e = row_ptr[i + 1];
+    if (b < 0 || e < b || e > nnz) {
+        atomicOr(err, kErrRowPtr);
+        return;
+    }
+    int prev = -1, bad = 0;
+    for (int64_t k = b; k < e; ++k) {
+        int j = col[k];
+        if (j < 0 || j >= n) { bad |= kErrColRange; break; }
+        if (j == i) bad |= kErrSelfLoop;
+        if (j <= prev) bad |= kErrUnsorted;
+        prev = j;
+        if (w) {
+            float a = w[k];
+            if (!(a > 0.0f) || !isfinite(a)) bad |= kErrWeight;
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// Only run once k_validate_rows passed: every row range is inside [0, nnz] and
+// every column is in range, so the binary search below stays in bounds.
+__global__ void k_validate_symmetry(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                    const float* __restrict__ w, int* err) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        int j = col[k];
+        int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1, found = -1;
+        while (lo <= hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int c = col[mid];
+            if (c == i) { found = mid; break; }
+            if (c < i) lo = mid + 1; else hi = mid - 1;
+        }
+        if (found < 0 || (w && w[found] != w[k])) {
+            atomicOr(err, kErrAsym);
+            return;
+        }
+    }
+}
+
+// d_i = sum_j a_ij in FP64; 1 + d_i and its reciprocal
+__global__ void k_degrees(int64_t n, const int32_t* __restrict__ row_ptr, const float* __restrict__ w,
+                          double* opd, double* inv64, float* inv32, int* max_deg) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t b = row_ptr[i], e = row_ptr[i + 1];
+    double d = 0.0;
+    if (w) {
+        for (int64_t k = b; k < e; ++k) d += static_cast<double>(w[k]);
+    } else {
+        d = static_cast<double>(e - b);
+    }
+    opd[i] = 1.0 + d;
+    double inv = 1.0 / (1.0 + d);
+    inv64[i] = inv;
+    inv32[i] = static_cast<float>(inv);
+    atomicMax(max_deg, static_cast<int>(e - b));
+}
+
+// ---------------------------------------------------------------- transpose
+__global__ void k_count_cols(int64_t nnz, const int32_t* __restrict__ col, int32_t* cnt) {
+    int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+}
+
+__global__ void k_transpose_scatter(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                    const float* __restrict__ w, int32_t* cursor, int32_t* t_col, float* t_w) {
+    // one wave per row: coalesced reads of the row, atomics spread over targets
+    int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    for (int64_t k = row_ptr[i] + lane_id(); k < row_ptr[i + 1]; k += 64) {
+        int j = col[k];
+        int p = atomicAdd(&cursor[j], 1);
+        t_col[p] = static_cast<int32_t>(i);
+        if (t_w) t_w[p] = w ? w[k] : 1.0f;
+    }
+}
+
+__global__ void k_max_row(int64_t n, const int32_t* __restrict__ row_ptr, int* mx) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(mx, row_ptr[i + 1] - row_ptr[i]);
+}
+
+// ----------------------------------------------------------------- colouring
+// Jones-Plassmann with largest-degree-first priorities: a node takes the
+// smallest colour unused by its higher-priority neighbours once all of them are
+// coloured.  The result does not depend on thread timing, because a node's
+// colour is a function of its higher-priority neighbours' colours only.
+__device__ __forceinline__ bool higher(uint64_t ku, int32_t u, uint64_t kv, int32_t v) {
+    return ku > kv || (ku == kv && u > v);
+}
+
+__global__ void k_jp_init(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ t_row_ptr,
+                          int directed, uint64_t* key, int32_t* colour, int32_t* cur1, int32_t* cur2) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t deg = static_cast<uint32_t>(row_ptr[i + 1] - row_ptr[i]);
+    if (directed) deg += static_cast<uint32_t>(t_row_ptr[i + 1] - t_row_ptr[i]);
+    key[i] = (static_cast<uint64_t>(deg) << 32) | hash32(static_cast<uint32_t>(i) * 2654435761U + 17U);
+    colour[i] = -1;
+    cur1[i] = row_ptr[i];
+    cur2[i] = directed ? t_row_ptr[i] : 0;
+}
+
+__device__ __forceinline__ bool jp_blocked(const int32_t* __restrict__ ptr, const int32_t* __restrict__ adj,
+                                           int32_t* cur, int32_t v, uint64_t kv, const uint64_t* __restrict__ key,
+                                           const int32_t* colour) {
+    int32_t e = ptr[v + 1];
+    for (int32_t k = cur[v]; k < e; ++k) {
+        int32_t u = adj[k];
+        if (higher(key[u], u, kv, v) && __atomic_load_n(&colour[u], __ATOMIC_RELAXED) < 0) {
+            cur[v] = k;
+            return true;
+        }
+    }
+    cur[v] = e;
+    return false;
+}
+
+__device__ __forceinline__ uint64_t jp_mask(const int32_t* __restrict__ ptr, const int32_t* __restrict__ adj,
+                                            int32_t v, uint64_t kv, const uint64_t* __restrict__ key,
+                                            const int32_t* colour, int base) {
+    uint64_t m = 0;
+    for (int32_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+        int32_t u = adj[k];
+        if (higher(key[u], u, kv, v)) {
+            int c = __atomic_load_n(&colour[u], __ATOMIC_RELAXED) - base;
+            if (c >= 0 && c < 64) m |= 1ull << c;
+        }
+    }
+    return m;
+}
+
+__global__ void k_jp_round(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                           const int32_t* __restrict__ t_row_ptr, const int32_t* __restrict__ t_col, int directed,
+                           const uint64_t* __restrict__ key, int32_t* colour, int32_t* cur1, int32_t* cur2,
+                           int* pending) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t v = static_cast<int32_t>(i);
+    if (colour[v] >= 0) return;
+    uint64_t kv = key[v];
+    bool blocked = jp_blocked(row_ptr, col, cur1, v, kv, key, colour);
+    if (!blocked && directed) blocked = jp_blocked(t_row_ptr, t_col, cur2, v, kv, key, colour);
+    if (blocked) {
+        if (__atomic_load_n(pending, __ATOMIC_RELAXED) == 0) __atomic_store_n(pending, 1, __ATOMIC_RELAXED);
+        return;
+    }
+    for (int base = 0;; base += 64) {
+        uint64_t m = jp_mask(row_ptr, col, v, kv, key, colour, base);
+        if (directed) m |= jp_mask(t_row_ptr, t_col, v, kv, key, colour, base);
+        if (~m) {
+            __atomic_store_n(&colour[v], base + __builtin_ctzll(~m), __ATOMIC_RELAXED);
+            return;
+        }
+    }
+}
+
+__global__ void k_colour_count(int64_t n, const int32_t* __restrict__ colour, int* max_colour) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(max_colour, colour[i]);
+}
+
+// Stable counting sort of nodes by colour: per-chunk histograms, a scan in
+// (colour, chunk) order, then an in-order scatter inside every chunk.
+constexpr int kSortChunk = 1024;
+
+__global__ __launch_bounds__(256) void k_colour_hist(int64_t n, const int32_t* __restrict__ colour, int K,
+                                                     int32_t* hist, int64_t nchunks) {
+    extern __shared__ int cnt[];
+    for (int c = threadIdx.x; c < K; c += blockDim.x) cnt[c] = 0;
+    __syncthreads();
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kSortChunk;
+    for (int t = threadIdx.x; t < kSortChunk; t += blockDim.x)
+        if (base + t < n) atomicAdd(&cnt[colour[base + t]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < K; c += blockDim.x) hist[static_cast<int64_t>(c) * nchunks + blockIdx.x] = cnt[c];
+}
+
+// one wave per chunk, 64 nodes at a time in index order
+__global__ __launch_bounds__(64) void k_colour_scatter(int64_t n, const int32_t* __restrict__ colour, int K,
+                                                       const int32_t* __restrict__ off, int64_t nchunks,
+                                                       int32_t* perm, int32_t* iperm) {
+    extern __shared__ int run[];
+    const int lane = lane_id();
+    for (int c = lane; c < K; c += 64) run[c] = 0;
+    wave_sync_lds();
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kSortChunk;
+    for (int step = 0; step < kSortChunk / 64; ++step) {
+        int64_t v = base + step * 64 + lane;
+        bool valid = v < n;
+        int c = valid ? colour[v] : -1;
+        uint64_t todo = __ballot(valid);
+        int rank = 0, grp = 0;
+        bool leader = false;
+        while (todo) {
+            int l = __builtin_ctzll(todo);
+            int lc = __shfl(c, l, 64);
+            uint64_t m = __ballot(valid && c == lc);
+            if (valid && c == lc) {
+                rank = lanes_below(m);
+                grp = __popcll(m);
+                leader = (lane == l);
+            }
+            todo &= ~m;
+        }
+        int start = valid ? run[c] : 0;
+        wave_sync_lds();
+        if (valid) {
+            int64_t pos = off[static_cast<int64_t>(c) * nchunks + blockIdx.x] + start + rank;
+            perm[pos] = static_cast<int32_t>(v);
+            iperm[v] = static_cast<int32_t>(pos);
+            if (leader) run[c] = start + grp;
+        }
+        wave_sync_lds();
+    }
+}
+
+__global__ void k_class_offsets(int K, const int32_t* __restrict__ off, int64_t nchunks, int64_t n, int64_t* class_off) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < K) class_off[c] = off[static_cast<int64_t>(c) * nchunks];
+    if (c == K) class_off[K] = n;
+}
+
+__global__ void k_perm_rowlen(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ row_ptr,
+                              int32_t* len) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) {
+        int32_t o = perm[i];
+        len[i] = row_ptr[o + 1] - row_ptr[o];
+    } else if (i == n) {
+        len[n] = 0;
+    }
+}
+
+// one wave per relabelled row
+__global__ void k_perm_copy(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+                            const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const float* __restrict__ w, const double* __restrict__ opd,
+                            const double* __restrict__ inv64, const int32_t* __restrict__ prow_ptr, int32_t* pcol,
+                            float* pw, double* popd, double* pinv64) {
+    int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (i >= n) return;
+    int32_t o = perm[i];
+    int32_t b = row_ptr[o], e = row_ptr[o + 1], pb = prow_ptr[i];
+    for (int32_t k = b + lane_id(); k < e; k += 64) {
+        pcol[pb + (k - b)] = iperm[col[k]];
+        if (pw) pw[pb + (k - b)] = w[k];
+    }
+    if (lane_id() == 0) {
+        popd[i] = opd[o];
+        pinv64[i] = inv64[o];
+    }
+}
+
+inline unsigned grid1d(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+struct GraphLayout {
+    double* opd; double* inv64; float* inv32;
+    int32_t* t_row_ptr; int32_t* t_col; float* t_w; int32_t* t_cursor;
+    int32_t* colour; uint64_t* key; int32_t* cur1; int32_t* cur2; int32_t* perm; int32_t* iperm;
+    int32_t* hist; int64_t* class_off; int32_t* prow_ptr; int32_t* pcol; float* pw; double* popd; double* pinv64;
+    int* flags; void* scan_tmp;
+};
+
+constexpr int kMaxJpRounds = 1 << 16;
+
+GraphLayout carve_graph(Carver& cv, const fj_graph_desc* d, int32_t flags) {
+    GraphLayout L{};
+    const int64_t n = d->n, nnz = d->nnz;
+    const bool weighted = d->w != nullptr;
+    L.opd = cv.take<double>(n);
+    L.inv64 = cv.take<double>(n);
+    L.inv32 = cv.take<float>(n);
+    if (d->directed) {
+        L.t_row_ptr = cv.take<int32_t>(n + 1);
+        L.t_col = cv.take<int32_t>(nnz);
+        L.t_w = weighted ? cv.take<float>(nnz) : nullptr;
+        L.t_cursor = cv.take<int32_t>(n + 1);
+    }
+    L.flags = cv.take<int>(kMaxJpRounds + 64);
+    int64_t scan_n = n + 1;
+    if (flags & FJ_GRAPH_COLOUR) {
+        int64_t nchunks = (n + kSortChunk - 1) / kSortChunk;
+        L.colour = cv.take<int32_t>(n);
+        L.key = cv.take<uint64_t>(n);
+        L.cur1 = cv.take<int32_t>(n);
+        L.cur2 = cv.take<int32_t>(n);
+        L.perm = cv.take<int32_t>(n);
+        L.iperm = cv.take<int32_t>(n);
+        L.hist = cv.take<int32_t>(static_cast<size_t>(kMaxColours) * nchunks);
+        L.class_off = cv.take<int64_t>(kMaxColours + 1);
+        L.prow_ptr = cv.take<int32_t>(n + 1);
+        L.pcol = cv.take<int32_t>(nnz);
+        L.pw = weighted ? cv.take<float>(nnz) : nullptr;
+        L.popd = cv.take<double>(n);
+        L.pinv64 = cv.take<double>(n);
+        scan_n = std::max<int64_t>(scan_n, static_cast<int64_t>(kMaxColours) * nchunks);
+    }
+    L.scan_tmp = cv.take<char>(scan_tmp_bytes(scan_n));
+    return L;
+}
+
+}  // namespace
+
+size_t graph_ws_bytes(const fj_graph_desc* d, int32_t flags) {
+    Carver cv(nullptr);
+    carve_graph(cv, d, flags);
+    return cv.bytes();
+}
+
+fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* ws, size_t ws_bytes, hipStream_t st) {
+    const int64_t n = d->n, nnz = d->nnz;
+    Carver cv(ws);
+    GraphLayout L = carve_graph(cv, d, flags);
+    if (cv.bytes() > ws_bytes) {
+        set_error("graph workspace too small: need " + std::to_string(cv.bytes()) + " bytes");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    g->n = n;
+    g->nnz = nnz;
+    g->directed = d->directed ? 1 : 0;
+    g->weighted = d->w ? 1 : 0;
+    g->row_ptr = d->row_ptr;
+    g->col = d->col;
+    g->w = d->w;
+
+    int* err = L.flags;  // flags[0..63] scratch scalars; JP round flags after
+    FJ_HIP(hipMemsetAsync(L.flags, 0, sizeof(int) * 64, st));
+    int32_t ends[2] = {0, 0};
+    FJ_HIP(hipMemcpyAsync(&ends[0], d->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipMemcpyAsync(&ends[1], d->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (ends[0] != 0 || ends[1] != nnz) {
+        set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const int bs = 256;
+    if (n > 0) hipLaunchKernelGGL(k_validate_rows, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, nnz, d->row_ptr, d->col, d->w, err);
+    int herr = 0;
+    FJ_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (herr == 0 && !d->directed && n > 0) {
+        hipLaunchKernelGGL(k_validate_symmetry, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, d->row_ptr, d->col, d->w, err);
+        FJ_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+    }
+    if (herr) {
+        std::string m = "invalid CSR:";
+        if (herr & kErrRowPtr) m += " row_ptr not nondecreasing within [0,nnz];";
+        if (herr & kErrColRange) m += " column index out of range;";
+        if (herr & kErrSelfLoop) m += " self-loop;";
+        if (herr & kErrUnsorted) m += " row not strictly increasing (duplicate or unsorted);";
+        if (herr & kErrWeight) m += " weight not finite and > 0;";
+        if (herr & kErrAsym) m += " undirected graph is not symmetric;";
+        set_error(m);
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+
+    // degrees
+    g->opd = L.opd;
+    g->inv64 = L.inv64;
+    g->inv32 = L.inv32;
+    int* maxdeg = err + 1;
+    int* maxin = err + 2;
+    int* maxcol = err + 3;
+    if (n > 0) hipLaunchKernelGGL(k_degrees, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, d->row_ptr, d->w, L.opd, L.inv64, L.inv32, maxdeg);
+
+    // CSR(A^T)
+    if (d->directed) {
+        FJ_HIP(hipMemsetAsync(L.t_row_ptr, 0, sizeof(int32_t) * (n + 1), st));
+        if (nnz > 0) hipLaunchKernelGGL(k_count_cols, dim3(grid1d(nnz, bs)), dim3(bs), 0, st, nnz, d->col, L.t_row_ptr);
+        exclusive_scan_i32(L.t_row_ptr, L.t_row_ptr, n + 1, L.scan_tmp, st);
+        FJ_HIP(hipMemcpyAsync(L.t_cursor, L.t_row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
+        if (n > 0)
+            hipLaunchKernelGGL(k_transpose_scatter, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, d->row_ptr, d->col,
+                               d->w, L.t_cursor, L.t_col, L.t_w);
+        if (n > 0) hipLaunchKernelGGL(k_max_row, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, L.t_row_ptr, maxin);
+        g->t_row_ptr = L.t_row_ptr;
+        g->t_col = L.t_col;
+        g->t_w = L.t_w;
+    } else {
+        g->t_row_ptr = d->row_ptr;
+        g->t_col = d->col;
+        g->t_w = d->w;
+    }
+    int hdeg[2] = {0, 0};
+    FJ_HIP(hipMemcpyAsync(hdeg, maxdeg, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    g->max_degree = hdeg[0];
+    g->max_in_degree = d->directed ? hdeg[1] : hdeg[0];
+
+    if (!(flags & FJ_GRAPH_COLOUR) || n == 0) return FJ_OK;
+
+    // Jones-Plassmann colouring, rounds until no node is pending
+    hipLaunchKernelGGL(k_jp_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, d->row_ptr, g->t_row_ptr, g->directed,
+                       L.key, L.colour, L.cur1, L.cur2);
+    int* round_flags = L.flags + 64;
+    FJ_HIP(hipMemsetAsync(round_flags, 0, sizeof(int) * kMaxJpRounds, st));
+    int rounds = 0;
+    const int batch = 8;
+    bool done = false;
+    while (!done) {
+        if (rounds + batch > kMaxJpRounds) {
+            set_error("colouring did not finish within the round limit");
+            return FJ_ERR_UNSUPPORTED;
+        }
+        for (int b = 0; b < batch; ++b)
+            hipLaunchKernelGGL(k_jp_round, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, d->row_ptr, d->col, g->t_row_ptr,
+                               g->t_col, g->directed, L.key, L.colour, L.cur1, L.cur2, round_flags + rounds + b);
+        int hf[batch];
+        FJ_HIP(hipMemcpyAsync(hf, round_flags + rounds, sizeof(hf), hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+        for (int b = 0; b < batch; ++b) {
+            if (!done && hf[b] == 0) {
+                done = true;
+                rounds += b + 1;
+            }
+        }
+        if (!done) rounds += batch;
+    }
+    g->colour_rounds = rounds;
+    hipLaunchKernelGGL(k_colour_count, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, L.colour, maxcol);
+    int hmax = 0;
+    FJ_HIP(hipMemcpyAsync(&hmax, maxcol, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    const int K = hmax + 1;
+    if (K > kMaxColours) {
+        set_error("graph needs " + std::to_string(K) + " colours; at most " + std::to_string(kMaxColours) +
+                  " are supported");
+        return FJ_ERR_UNSUPPORTED;
+    }
+    g->num_colours = K;
+    g->colour = L.colour;
+
+    // stable counting sort by colour -> perm (new -> old), iperm (old -> new)
+    const int64_t nchunks = (n + kSortChunk - 1) / kSortChunk;
+    hipLaunchKernelGGL(k_colour_hist, dim3(nchunks), dim3(256), sizeof(int) * K, st, n, L.colour, K, L.hist, nchunks);
+    exclusive_scan_i32(L.hist, L.hist, static_cast<int64_t>(K) * nchunks, L.scan_tmp, st);
+    hipLaunchKernelGGL(k_colour_scatter, dim3(nchunks), dim3(64), sizeof(int) * K, st, n, L.colour, K, L.hist,
+                       nchunks, L.perm, L.iperm);
+    hipLaunchKernelGGL(k_class_offsets, dim3(grid1d(K + 1, 256)), dim3(256), 0, st, K, L.hist, nchunks, n, L.class_off);
+    g->class_off.assign(K + 1, 0);
+    FJ_HIP(hipMemcpyAsync(g->class_off.data(), L.class_off, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, st));
+
+    // relabelled CSR(A): row i is old row perm[i], columns mapped through iperm
+    hipLaunchKernelGGL(k_perm_rowlen, dim3(grid1d(n + 1, bs)), dim3(bs), 0, st, n, L.perm, d->row_ptr, L.prow_ptr);
+    exclusive_scan_i32(L.prow_ptr, L.prow_ptr, n + 1, L.scan_tmp, st);
+    hipLaunchKernelGGL(k_perm_copy, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, L.perm, L.iperm, d->row_ptr, d->col,
+                       d->w, L.opd, L.inv64, L.prow_ptr, L.pcol, L.pw, L.popd, L.pinv64);
+    FJ_HIP(hipStreamSynchronize(st));
+    g->perm = L.perm;
+    g->iperm = L.iperm;
+    g->prow_ptr = L.prow_ptr;
+    g->pcol = L.pcol;
+    g->pw = L.pw;
+    g->popd = L.popd;
+    g->pinv64 = L.pinv64;
+    return FJ_OK;
+}
+
+}  // namespace fj

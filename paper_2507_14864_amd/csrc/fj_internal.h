@@ -1,0 +1,90 @@
+// Internal declarations shared by the libfj translation units (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fj.h"
+
+namespace fj {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per block for the tile kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kStripes = 64;       // striped global counters (one 128 B line each)
+constexpr int kStripeStride = 16;  // u64 per stripe line
+constexpr int kMaxColours = 2048;  // colour classes supported by the permutation pass
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+fj_status hip_fail(hipError_t e, const char* what);
+#define FJ_HIP(call)                                                   \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ::fj::hip_fail(e_, #call);        \
+    } while (0)
+
+// ------------------------------------------------------ workspace carving
+struct Carver {
+    char* base;       // nullptr for a size query
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+}  // namespace fj
+
+// Host object behind fj_graph*.
+struct fj_graph {
+    int64_t n = 0, nnz = 0;
+    int directed = 0, weighted = 0;
+    int32_t max_degree = 0, max_in_degree = 0;
+    // CSR(A), caller-owned
+    const int32_t* row_ptr = nullptr;
+    const int32_t* col = nullptr;
+    const float* w = nullptr;
+    // CSR(A^T): aliases CSR(A) when undirected
+    const int32_t* t_row_ptr = nullptr;
+    const int32_t* t_col = nullptr;
+    const float* t_w = nullptr;
+    // per node, original labels
+    double* opd = nullptr;   // 1 + d_i
+    double* inv64 = nullptr; // 1 / (1 + d_i)
+    float* inv32 = nullptr;
+    // colour-ordered copy (FJ_GRAPH_COLOUR)
+    int32_t num_colours = 0, colour_rounds = 0;
+    std::vector<int64_t> class_off;  // [num_colours + 1] host copy
+    int32_t* colour = nullptr;       // [n] original labels
+    int32_t* perm = nullptr;         // new -> old
+    int32_t* iperm = nullptr;        // old -> new
+    int32_t* prow_ptr = nullptr;     // relabelled CSR(A)
+    int32_t* pcol = nullptr;
+    float* pw = nullptr;
+    double* popd = nullptr;          // 1 + d, relabelled
+    double* pinv64 = nullptr;
+};
+
+namespace fj {
+
+// Kernel launchers (fj_graph.hip)
+fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* ws, size_t ws_bytes,
+                      hipStream_t st);
+size_t graph_ws_bytes(const fj_graph_desc* d, int32_t flags);
+
+// Scan helper (fj_graph.hip): exclusive scan of int32 in -> out (may alias), n entries,
+// returns total through *total_dev (device int64) when not null. tmp: scan_tmp_bytes(n).
+size_t scan_tmp_bytes(int64_t n);
+size_t certify_ws_bytes(int64_t n);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t st);
+
+}  // namespace fj

@@ -1,0 +1,182 @@
+// Table 1 measures over z in FP64 with fixed-order reductions (bitwise
+// reproducible): C = z^T z, I = sum (z - s)^2, P = sum (z - mean)^2 with the
+// mean-centred vector of Sec. 3.4 (two passes, because the mean subtraction
+// cancels), D = sum over edges of a_ij (z_i - z_j)^2 (undirected: each edge
+// once, i.e. half of the sum over the stored arcs; directed: each arc once).
+#include <cmath>
+
+#include "fj_device.h"
+#include "fj_internal.h"
+#include "fj_tile.h"
+
+namespace fj {
+namespace {
+
+constexpr int kNodeItems = 8;
+constexpr int kNodeTile = kBlock * kNodeItems;
+
+inline unsigned nblocks_nodes(int64_t n) { return static_cast<unsigned>((n + kNodeTile - 1) / kNodeTile); }
+inline unsigned nblocks_tiles(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+// pass 1: sum z, sum z^2, sum (z - s)^2 per block
+__global__ __launch_bounds__(kBlock) void k_metrics_nodes(int64_t n, const double* __restrict__ s,
+                                                          const double* __restrict__ z, double* part) {
+    __shared__ double lds[kWavesPerBlock];
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kNodeTile + threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNodeItems; ++k) {
+        int64_t i = base + static_cast<int64_t>(k) * kBlock;
+        if (i < n) {
+            double zi = z[i], d = zi - s[i];
+            a += zi;
+            b += zi * zi;
+            c += d * d;
+        }
+    }
+    a = block_sum<kBlock>(a, lds);
+    b = block_sum<kBlock>(b, lds);
+    c = block_sum<kBlock>(c, lds);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// pass 2: sum (z - mean)^2, mean read from device
+__global__ __launch_bounds__(kBlock) void k_metrics_centred(int64_t n, const double* __restrict__ z,
+                                                            const double* __restrict__ mean, double* part) {
+    __shared__ double lds[kWavesPerBlock];
+    const double m = *mean;
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kNodeTile + threadIdx.x;
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNodeItems; ++k) {
+        int64_t i = base + static_cast<int64_t>(k) * kBlock;
+        if (i < n) {
+            double d = z[i] - m;
+            a += d * d;
+        }
+    }
+    a = block_sum<kBlock>(a, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+// edges: each lane accumulates its own arcs; wave tiles of 64 rows
+__global__ __launch_bounds__(kBlock) void k_metrics_edges(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                          const double* __restrict__ z, double* part) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_z[kWavesPerBlock][64];
+    __shared__ double lds[kWavesPerBlock];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64;
+    const int nrows = static_cast<int>(row0 < n ? (n - row0 < 64 ? n - row0 : 64) : 0);
+    if (lane < nrows) s_z[wid][lane] = z[row0 + lane];
+    double acc = 0.0;
+    tile_for_each_arc(row_ptr, row0, nrows, s_pre[wid], [&](int k, int slot) {
+        double d = s_z[wid][slot] - z[col[k]];
+        double a = w ? static_cast<double>(w[k]) : 1.0;
+        acc += a * d * d;
+    });
+    acc = block_sum<kBlock>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// single block: fixed-order sum of `cnt` partials with stride `stride` starting at `off`
+__device__ double reduce_parts(const double* part, int64_t cnt, int stride, int off, double* lds) {
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < cnt; i += 1024) a += part[i * stride + off];
+    a = wave_sum(a);
+    if (lane_id() == 0) lds[threadIdx.x >> 6] = a;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 16; ++k) t += lds[k];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(1024) void k_metrics_mean(const double* part, int64_t nb, int64_t n, double* out) {
+    __shared__ double lds[16];
+    double sz = reduce_parts(part, nb, 3, 0, lds);
+    double sc = reduce_parts(part, nb, 3, 1, lds);
+    double si = reduce_parts(part, nb, 3, 2, lds);
+    if (threadIdx.x == 0) {
+        out[4] = n ? sz / static_cast<double>(n) : 0.0;  // mean
+        out[3] = sc;                                      // C
+        out[2] = si;                                      // I
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_metrics_final(const double* part_p, int64_t nbp, const double* part_d,
+                                                        int64_t nbd, int directed, double* out) {
+    __shared__ double lds[16];
+    double p = reduce_parts(part_p, nbp, 1, 0, lds);
+    double d = reduce_parts(part_d, nbd, 1, 0, lds);
+    if (threadIdx.x == 0) {
+        out[0] = p;
+        out[1] = directed ? d : 0.5 * d;
+    }
+}
+
+struct MetricsLayout {
+    double* part1; double* part2; double* part_d; double* out;
+};
+
+MetricsLayout carve_metrics(Carver& cv, int64_t n) {
+    MetricsLayout L{};
+    L.part1 = cv.take<double>(3 * (nblocks_nodes(n) + 1));
+    L.part2 = cv.take<double>(nblocks_nodes(n) + 1);
+    L.part_d = cv.take<double>(nblocks_tiles(n) + 1);
+    L.out = cv.take<double>(8);
+    return L;
+}
+
+}  // namespace
+}  // namespace fj
+
+using namespace fj;
+
+extern "C" size_t fj_metrics_workspace_bytes(const fj_graph* g) {
+    if (!g) return 0;
+    Carver cv(nullptr);
+    carve_metrics(cv, g->n);
+    size_t cert = certify_ws_bytes(g->n);  // fj_certify shares this workspace
+    return cv.bytes() > cert ? cv.bytes() : cert;
+}
+
+extern "C" fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out, void* ws,
+                                size_t ws_bytes, void* stream) {
+    if (!g || !out || !ws || ((!s || !z) && g->n > 0)) {
+        set_error("fj_metrics: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (ws_bytes < fj_metrics_workspace_bytes(g)) {
+        set_error("fj_metrics: workspace too small");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    Carver cv(ws);
+    MetricsLayout L = carve_metrics(cv, g->n);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = g->n;
+    double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (n > 0) {
+        const unsigned nbn = nblocks_nodes(n), nbt = nblocks_tiles(n);
+        hipLaunchKernelGGL(k_metrics_nodes, dim3(nbn), dim3(kBlock), 0, st, n, s, z, L.part1);
+        hipLaunchKernelGGL(k_metrics_edges, dim3(nbt), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w, z, L.part_d);
+        hipLaunchKernelGGL(k_metrics_mean, dim3(1), dim3(1024), 0, st, L.part1, static_cast<int64_t>(nbn), n, L.out);
+        hipLaunchKernelGGL(k_metrics_centred, dim3(nbn), dim3(kBlock), 0, st, n, z, L.out + 4, L.part2);
+        hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(1024), 0, st, L.part2, static_cast<int64_t>(nbn), L.part_d,
+                           static_cast<int64_t>(nbt), g->directed, L.out);
+        FJ_HIP(hipMemcpyAsync(h, L.out, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+    }
+    out->P = h[0];
+    out->D = h[1];
+    out->I = h[2];
+    out->C = h[3];
+    out->mean = h[4];
+    return FJ_OK;
+}

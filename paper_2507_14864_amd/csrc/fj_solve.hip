@@ -1,0 +1,665 @@
+// ImprovedBLISOR on the GPU: shift (Alg. 2), push rounds (Alg. 1/3 with the
+// FIFO relaxed to bulk rounds) or colour-ordered over-relaxed sweeps (Thm. 8
+// with Eqs. (sor1)-(sor3)), FP64 certificate (Lemma 7), refinement, unshift.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fj_device.h"
+#include "fj_internal.h"
+#include "fj_tile.h"
+
+namespace fj {
+namespace {
+
+constexpr int kMaxRounds = 1 << 20;
+
+inline unsigned grid1d(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+inline unsigned tile_blocks(int64_t rows) { return static_cast<unsigned>((rows + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ void flag_set(int* f) {
+    if (__atomic_load_n(f, __ATOMIC_RELAXED) == 0) __atomic_store_n(f, 1, __ATOMIC_RELAXED);
+}
+__device__ __forceinline__ void stripe_add(unsigned long long* stats, int slot, unsigned long long v) {
+    atomicAdd(&stats[(blockIdx.x % kStripes) * kStripeStride + slot], v);
+}
+
+// ------------------------------------------------------------------- init
+// Alg. 2: s' = s + c, h = eps' s', zhat' = 0, r = s'.  The FP32 threshold is
+// rounded down so that |r| <= h32 implies |r| <= h in FP64.
+template <typename T>
+__global__ void k_init_cold(int64_t n, const double* __restrict__ s, double c, double epsp, T* r, T* h,
+                            double* zh, int* bad) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double si = s[i];
+    if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
+    double sp = si + c;
+    r[i] = static_cast<T>(sp);
+    double hv = epsp * sp;
+    if constexpr (sizeof(T) == 4) h[i] = __double2float_rd(hv); else h[i] = hv;
+    zh[i] = 0.0;
+}
+
+// warm start (any zhat' is a valid start, Lemma 4): zhat' = z0 + c
+template <typename T>
+__global__ void k_init_warm(int64_t n, const double* __restrict__ s, const double* __restrict__ z0, double c,
+                            double epsp, T* h, double* zh, int* bad) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double si = s[i], zi = z0[i];
+    if (!(si >= 0.0) || !isfinite(si) || !isfinite(zi)) flag_set(bad);
+    double hv = epsp * (si + c);
+    if constexpr (sizeof(T) == 4) h[i] = __double2float_rd(hv); else h[i] = hv;
+    zh[i] = zi + c;
+}
+
+// ------------------------------------------------------------ certificate
+// r = s' - (I+L) zhat' in FP64 over CSR(A): r_i = s'_i - (1+d_i) zhat'_i +
+// sum_j a_ij zhat'_j.  Per block: max |r_i| / h_i and the count of rows with
+// |r_i| > h_i (Alg. 3's stopping test).  refine != 0 also stores fl(r) as the
+// new tracked residual, which resets FP32 drift (Lemma 4 holds for any zhat').
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_certify(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                    const double* __restrict__ s, double c_res, double c_thr,
+                                                    double epsp, const double* __restrict__ zh,
+                                                    const double* __restrict__ opd, T* r_out, double* part_max,
+                                                    long long* part_viol) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    __shared__ double s_mx[kWavesPerBlock];
+    __shared__ long long s_vi[kWavesPerBlock];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64;
+    const int nrows = static_cast<int>(row0 < n ? (n - row0 < 64 ? n - row0 : 64) : 0);
+    double sum = tile_row_sums(row_ptr, row0, nrows, s_pre[wid], s_acc[wid], [&](int k) {
+        double a = w ? static_cast<double>(w[k]) : 1.0;
+        return a * zh[col[k]];
+    });
+    double ratio = 0.0;
+    int viol = 0;
+    if (lane < nrows) {
+        int64_t i = row0 + lane;
+        double ri = (s[i] + c_res) - opd[i] * zh[i] + sum;
+        ratio = fabs(ri) / (epsp * (s[i] + c_thr));
+        if (!(ratio <= 1.0)) viol = 1;  // NaN counts as a violation
+        if (!isfinite(ratio)) ratio = INFINITY;
+        if (r_out) r_out[i] = static_cast<T>(ri);
+    }
+    double mx = wave_max(ratio);
+    long long vc = __popcll(__ballot(viol));
+    if (lane == 0) { s_mx[wid] = mx; s_vi[wid] = vc; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0; long long v = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) { m = fmax(m, s_mx[k]); v += s_vi[k]; }
+        part_max[blockIdx.x] = m;
+        part_viol[blockIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_certify_final(const double* part_max, const long long* part_viol, int64_t nb,
+                                                        double* out_max, long long* out_viol) {
+    __shared__ double sm[16];
+    __shared__ long long sv[16];
+    double m = 0.0; long long v = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 1024) { m = fmax(m, part_max[i]); v += part_viol[i]; }
+    m = wave_max(m);
+    v = wave_sum_ll(v);
+    if (lane_id() == 0) { sm[threadIdx.x >> 6] = m; sv[threadIdx.x >> 6] = v; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 16; ++k) { m = fmax(sm[0], sm[k]); sm[0] = m; sv[0] += sv[k]; }
+        *out_max = sm[0];
+        *out_viol = sv[0];
+    }
+}
+
+// ---------------------------------------------------------------- push round
+// One bulk round of pushes (Alg. 1 / Alg. 3 with the FIFO order relaxed: the
+// nodes above threshold at the start of the round are pushed concurrently).
+// Lemma 4 holds for any pushed amount, so concurrent pushes keep the invariant;
+// with omega = 1 the residual stays >= 0 from a cold start.
+//
+// Wave w owns nodes [64w, 64w+64).  Active nodes (|r_v| > h_v) take their
+// residual with an atomic exchange, add omega x / (1+d_v) to zhat'_v
+// (Eq. (sor1)), leave (1-omega) x at v (Eq. (sor2)), and scatter
+// a_uv omega x / (1+d_v) to every u in row v of CSR(A^T) (Eq. (sor3)) with
+// hardware float atomics.  The arcs of the active nodes are compacted with a
+// ballot + mbcnt prefix into LDS and streamed 64 at a time (merge-path split).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push_round(int64_t n, const int32_t* __restrict__ t_row_ptr,
+                                                       const int32_t* __restrict__ t_col,
+                                                       const float* __restrict__ t_w, T* r, const T* __restrict__ h,
+                                                       const T* __restrict__ inv, const double* __restrict__ inv64,
+                                                       double* zh, double omega, const int* __restrict__ prev_active,
+                                                       int* this_active, unsigned long long* stats) {
+    __shared__ int s_beg[kWavesPerBlock][64];
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ T s_cf[kWavesPerBlock][64];
+    if (__atomic_load_n(prev_active, __ATOMIC_RELAXED) == 0) return;  // previous round changed nothing
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t v = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64 + lane;
+    bool act = false;
+    if (v < n) act = fabs(r[v]) > h[v];
+    const uint64_t m = __ballot(act);
+    if (m == 0) return;
+    int beg = 0, deg = 0;
+    T cf = 0;
+    if (act) {
+        T x = atomic_exch(&r[v], static_cast<T>(0));
+        if (omega != 1.0) atomic_add_noret(&r[v], static_cast<T>((1.0 - omega) * static_cast<double>(x)));
+        zh[v] += omega * static_cast<double>(x) * inv64[v];
+        cf = static_cast<T>(omega) * x * inv[v];
+        beg = t_row_ptr[v];
+        deg = t_row_ptr[v + 1] - beg;
+    }
+    const int slot = lanes_below(m);
+    const int cnt = __popcll(m);
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, 63, 64);
+    if (act) {
+        s_beg[wid][slot] = beg;
+        s_pre[wid][slot] = incl - deg;
+        s_cf[wid][slot] = cf;
+    }
+    wave_sync_lds();
+    for (int e = lane; e < total; e += 64) {
+        int k = tile_find(s_pre[wid], cnt, e);
+        int idx = s_beg[wid][k] + (e - s_pre[wid][k]);
+        int u = t_col[idx];
+        T a = t_w ? static_cast<T>(t_w[idx]) : static_cast<T>(1);
+        atomic_add_noret(&r[u], a * s_cf[wid][k]);
+    }
+    if (lane == 0) {
+        flag_set(this_active);
+        stripe_add(stats, 0, static_cast<unsigned long long>(cnt));
+        stripe_add(stats, 1, static_cast<unsigned long long>(total));
+    }
+}
+
+// ---------------------------------------------------------- colour-ordered SOR
+// Relabelled graph: colour class k occupies rows [class_off[k], class_off[k+1]).
+// Rows of one class are not adjacent in A + A^T, so updating them together is
+// exactly the sequential Gauss-Seidel update of each (Thm. 8), over-relaxed by
+// omega (Eq. (sor1)).  Pull form: r_i = s'_i - (1+d_i) zhat'_i + sum_j a_ij zhat'_j
+// is recomputed from the current estimate (equal to the tracked residual by
+// Lemma 4), and row i is updated iff |r_i| > h_i = eps' s'_i (Alg. 3's test).
+__global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ s,
+                           const double* __restrict__ z0, double c, double* sp, double* zh, int* bad) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t o = perm[i];
+    double si = s[o];
+    if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
+    sp[i] = si + c;
+    if (z0) {
+        double zi = z0[o];
+        if (!isfinite(zi)) flag_set(bad);
+        zh[i] = zi + c;
+    } else {
+        zh[i] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sor_class(int64_t row_begin, int64_t row_end,
+                                                      const int32_t* __restrict__ prow_ptr,
+                                                      const int32_t* __restrict__ pcol, const float* __restrict__ pw,
+                                                      const double* __restrict__ sp, const double* __restrict__ popd,
+                                                      const double* __restrict__ pinv, double* zh, double omega,
+                                                      double epsp, int* updated, int* bad,
+                                                      unsigned long long* stats) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t row0 = row_begin + (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64;
+    const int nrows = static_cast<int>(row0 < row_end ? (row_end - row0 < 64 ? row_end - row0 : 64) : 0);
+    if (nrows <= 0) return;
+    double sum = tile_row_sums(prow_ptr, row0, nrows, s_pre[wid], s_acc[wid], [&](int k) {
+        double a = pw ? static_cast<double>(pw[k]) : 1.0;
+        return a * zh[pcol[k]];
+    });
+    bool upd = false, nonfinite = false;
+    if (lane < nrows) {
+        int64_t i = row0 + lane;
+        double z = zh[i];
+        double ri = sp[i] - popd[i] * z + sum;
+        // a margin of 1e-6 h keeps a quiet sweep certified under the FP64 rounding
+        // of the standalone certificate (different summation order)
+        if (fabs(ri) > epsp * sp[i] * (1.0 - 1e-6)) {
+            zh[i] = z + omega * ri * pinv[i];
+            upd = true;
+        }
+        nonfinite = !isfinite(ri);
+    }
+    uint64_t um = __ballot(upd);
+    if (__ballot(nonfinite) && lane == 0) flag_set(bad);
+    if (um && lane == 0) {
+        flag_set(updated);
+        stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
+    }
+}
+
+__global__ void k_sor_unshift(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ zh, double c,
+                              double* z, double* zh_orig) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t o = perm[i];
+    z[o] = zh[i] - c;
+    if (zh_orig) zh_orig[o] = zh[i];
+}
+
+__global__ void k_unshift(int64_t n, const double* __restrict__ zh, double c, double* z) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = zh[i] - c;
+}
+
+// --------------------------------------------------------------- workspace
+struct SolveLayout {
+    void* r; void* h; double* zh; double* zh2; double* sp;
+    int* flags; int* one; int* bad; unsigned long long* stats;
+    double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
+};
+
+SolveLayout carve_solve(Carver& cv, int64_t n, int precision) {
+    SolveLayout L{};
+    size_t tsz = precision == FJ_FP64 ? sizeof(double) : sizeof(float);
+    L.r = cv.take<char>(tsz * n);
+    L.h = cv.take<char>(tsz * n);
+    L.zh = cv.take<double>(n);
+    L.zh2 = cv.take<double>(n);
+    L.sp = cv.take<double>(n);
+    L.flags = cv.take<int>(kMaxRounds);
+    L.one = cv.take<int>(1);
+    L.bad = cv.take<int>(1);
+    L.stats = cv.take<unsigned long long>(kStripes * kStripeStride);
+    int64_t nb = tile_blocks(n) + 1;
+    L.part_max = cv.take<double>(nb);
+    L.part_viol = cv.take<long long>(nb);
+    L.cert_max = cv.take<double>(1);
+    L.cert_viol = cv.take<long long>(1);
+    return L;
+}
+
+// Optional per-launch timing of the iteration kernel with HIP events.
+struct LaunchTimer {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    fj_status before() { return on ? record() : FJ_OK; }
+    fj_status after() { return on ? record() : FJ_OK; }
+    fj_status record() {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            FJ_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        FJ_HIP(hipEventRecord(ev[used++], st));
+        return FJ_OK;
+    }
+    fj_status total_ms(double* ms, int64_t* launches) {
+        *ms = 0.0;
+        *launches = static_cast<int64_t>(used / 2);
+        if (!on || used == 0) return FJ_OK;
+        FJ_HIP(hipEventSynchronize(ev[used - 1]));
+        for (size_t k = 0; k + 1 < used; k += 2) {
+            float t = 0.0f;
+            FJ_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            *ms += t;
+        }
+        return FJ_OK;
+    }
+    ~LaunchTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+struct HostStats {
+    unsigned long long pushes = 0, visits = 0;
+};
+
+fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
+    std::vector<unsigned long long> buf(kStripes * kStripeStride);
+    FJ_HIP(hipMemcpyAsync(buf.data(), L.stats, sizeof(unsigned long long) * buf.size(), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    hs->pushes = hs->visits = 0;
+    for (int k = 0; k < kStripes; ++k) {
+        hs->pushes += buf[k * kStripeStride + 0];
+        hs->visits += buf[k * kStripeStride + 1];
+    }
+    return FJ_OK;
+}
+
+// c_res: shift already inside zh (residual of the shifted system); c_thr: shift
+// of the threshold h = eps' (s + c_thr)
+template <typename T>
+fj_status certify(const fj_graph* g, const double* s, double c_res, double c_thr, double epsp, const double* zh,
+                  T* r_out, const SolveLayout& L, hipStream_t st, double* max_ratio, long long* viol) {
+    const int64_t n = g->n;
+    unsigned nb = tile_blocks(n);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_certify<T>, dim3(nb), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w, s, c_res, c_thr,
+                           epsp, zh, g->opd, r_out, L.part_max, L.part_viol);
+        hipLaunchKernelGGL(k_certify_final, dim3(1), dim3(1024), 0, st, L.part_max, L.part_viol,
+                           static_cast<int64_t>(nb), L.cert_max, L.cert_viol);
+    } else {
+        FJ_HIP(hipMemsetAsync(L.cert_max, 0, sizeof(double), st));
+        FJ_HIP(hipMemsetAsync(L.cert_viol, 0, sizeof(long long), st));
+    }
+    FJ_HIP(hipMemcpyAsync(max_ratio, L.cert_max, sizeof(double), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipMemcpyAsync(viol, L.cert_viol, sizeof(long long), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    return FJ_OK;
+}
+
+template <typename T>
+fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o, double epsp, double* z,
+                     const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
+    const int64_t n = g->n;
+    T* r = static_cast<T*>(L.r);
+    T* h = static_cast<T*>(L.h);
+    const T* inv = sizeof(T) == 4 ? reinterpret_cast<const T*>(g->inv32) : reinterpret_cast<const T*>(g->inv64);
+    const int bs = 256;
+    if (o->z0) {
+        hipLaunchKernelGGL(k_init_warm<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->z0, o->c, epsp, h, L.zh, L.bad);
+        double mr; long long vi;
+        fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &mr, &vi);
+        if (rc) return rc;
+    } else {
+        hipLaunchKernelGGL(k_init_cold<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->c, epsp, r, h, L.zh, L.bad);
+    }
+    int hbad = 0;
+    FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+        set_error("s must be finite and >= 0, and z0 finite");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const int K = o->check_every > 0 ? o->check_every : 8;
+    const int max_ref = o->max_refinements >= 0 ? o->max_refinements : 8;
+    const unsigned nb = tile_blocks(n);
+    int64_t rounds = 0, launches = 0;
+    int refinements = 0;
+    bool converged = false, capped = false;
+    double max_ratio = 0.0;
+    std::vector<int> hf(K);
+    HostStats hs;
+    LaunchTimer timer;
+    timer.on = o->profile != 0;
+    timer.st = st;
+    while (true) {
+        // rounds until one finds no node above threshold
+        bool quiet = false;
+        const int* prev = L.one;
+        while (!quiet) {
+            if (rounds + K > kMaxRounds) { capped = true; break; }
+            FJ_HIP(hipMemsetAsync(L.flags + rounds, 0, sizeof(int) * K, st));
+            for (int b = 0; b < K; ++b) {
+                int* cur = L.flags + rounds + b;
+                if (n > 0) {
+                    fj_status rc0 = timer.before();
+                    if (rc0) return rc0;
+                    hipLaunchKernelGGL(k_push_round<T>, dim3(nb), dim3(kBlock), 0, st, n, g->t_row_ptr, g->t_col,
+                                       g->t_w, r, h, inv, g->inv64, L.zh, o->omega, prev, cur, L.stats);
+                    rc0 = timer.after();
+                    if (rc0) return rc0;
+                }
+                prev = cur;
+                ++launches;
+            }
+            FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + rounds, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            fj_status rc = read_stats(L, st, &hs);
+            if (rc) return rc;
+            int used = K;
+            for (int b = 0; b < K; ++b)
+                if (hf[b] == 0) { used = b; quiet = true; break; }
+            rounds += used;
+            if (n == 0) quiet = true;
+            if (static_cast<int64_t>(hs.visits) > cap) { capped = true; break; }
+        }
+        if (capped) break;
+        long long viol = 0;
+        fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &max_ratio, &viol);
+        if (rc) return rc;
+        if (viol == 0) { converged = true; break; }
+        if (!std::isfinite(max_ratio) || refinements >= max_ref) break;
+        ++refinements;  // r now holds the FP64 residual rounded to T; resume pushing
+    }
+    if (!converged) {
+        long long viol = 0;
+        fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, static_cast<T*>(nullptr), L, st, &max_ratio, &viol);
+        if (rc) return rc;
+    }
+    if (n > 0) hipLaunchKernelGGL(k_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, L.zh, o->c, z);
+    FJ_HIP(hipStreamSynchronize(st));
+    {
+        fj_status rc0 = timer.total_ms(&out->kernel_ms, &out->kernel_launches);
+        if (rc0) return rc0;
+    }
+    out->pushes = static_cast<int64_t>(hs.pushes);
+    out->edge_visits = static_cast<int64_t>(hs.visits);
+    out->rounds = rounds;
+    out->launches = launches;
+    out->refinements = refinements;
+    out->certified = converged ? 1 : 0;
+    out->max_ratio = max_ratio;
+    if (!converged) {
+        set_error(capped ? "work cap reached before the certificate held"
+                         : "certificate failed after the refinement budget (or the iteration diverged)");
+        return FJ_ERR_NOT_CONVERGED;
+    }
+    return FJ_OK;
+}
+
+fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, double epsp, double* z,
+                    const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
+    const int64_t n = g->n;
+    const int bs = 256;
+    if (n > 0)
+        hipLaunchKernelGGL(k_sor_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, s, o->z0, o->c, L.sp, L.zh,
+                           L.bad);
+    int hbad = 0;
+    FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+        set_error("s must be finite and >= 0, and z0 finite");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const int K = o->check_every > 0 ? o->check_every : 8;
+    const int max_ref = o->max_refinements >= 0 ? o->max_refinements : 8;
+    const int nc = g->num_colours;
+    int64_t sweeps = 0, launches = 0;
+    int refinements = 0;
+    bool converged = false, capped = false, diverged = false;
+    double max_ratio = 0.0;
+    std::vector<int> hf(K);
+    LaunchTimer timer;
+    timer.on = o->profile != 0;
+    timer.st = st;
+    while (true) {
+        bool quiet = false;
+        while (!quiet) {
+            if (sweeps + K > kMaxRounds || (sweeps + K) * (g->nnz + n) > cap) { capped = true; break; }
+            FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * K, st));
+            for (int b = 0; b < K; ++b) {
+                int* cur = L.flags + sweeps + b;
+                for (int k = 0; k < nc; ++k) {
+                    int64_t rb = g->class_off[k], re = g->class_off[k + 1];
+                    if (re <= rb) continue;
+                    fj_status rc0 = timer.before();
+                    if (rc0) return rc0;
+                    hipLaunchKernelGGL(k_sor_class, dim3(tile_blocks(re - rb)), dim3(kBlock), 0, st, rb, re,
+                                       g->prow_ptr, g->pcol, g->pw, L.sp, g->popd, g->pinv64, L.zh, o->omega, epsp,
+                                       cur, L.bad, L.stats);
+                    rc0 = timer.after();
+                    if (rc0) return rc0;
+                    ++launches;
+                }
+            }
+            FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipStreamSynchronize(st));
+            if (hbad) { diverged = true; break; }
+            int used = K;
+            for (int b = 0; b < K; ++b)
+                if (hf[b] == 0) { used = b + 1; quiet = true; break; }
+            sweeps += used;
+            if (n == 0) quiet = true;
+        }
+        if (capped || diverged) break;
+        // the last sweep changed nothing, so its residuals were final; confirm in the original labels
+        if (n > 0) hipLaunchKernelGGL(k_sor_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, L.zh, o->c, z, L.zh2);
+        long long viol = 0;
+        fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L, st, &max_ratio, &viol);
+        if (rc) return rc;
+        if (viol == 0) { converged = true; break; }
+        if (refinements >= max_ref) break;
+        ++refinements;
+    }
+    if (!converged) {
+        if (n > 0) hipLaunchKernelGGL(k_sor_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, L.zh, o->c, z, L.zh2);
+        long long viol = 0;
+        fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L, st, &max_ratio, &viol);
+        if (rc) return rc;
+    }
+    HostStats hs;
+    fj_status rc = read_stats(L, st, &hs);
+    if (rc) return rc;
+    rc = timer.total_ms(&out->kernel_ms, &out->kernel_launches);
+    if (rc) return rc;
+    out->num_colours = nc;
+    out->pushes = static_cast<int64_t>(hs.pushes);
+    out->edge_visits = sweeps * g->nnz;
+    out->rounds = sweeps;
+    out->launches = launches;
+    out->refinements = refinements;
+    out->certified = converged ? 1 : 0;
+    out->max_ratio = max_ratio;
+    if (!converged) {
+        set_error(diverged ? "over-relaxed sweeps diverged (non-finite residual)"
+                           : capped ? "work cap reached before the certificate held"
+                                    : "certificate failed after the refinement budget");
+        return FJ_ERR_NOT_CONVERGED;
+    }
+    return FJ_OK;
+}
+
+struct CertLayout {
+    double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
+};
+CertLayout carve_cert(Carver& cv, int64_t n) {
+    CertLayout L{};
+    int64_t nb = tile_blocks(n) + 1;
+    L.part_max = cv.take<double>(nb);
+    L.part_viol = cv.take<long long>(nb);
+    L.cert_max = cv.take<double>(1);
+    L.cert_viol = cv.take<long long>(1);
+    return L;
+}
+
+}  // namespace
+
+size_t certify_ws_bytes(int64_t n) {
+    Carver cv(nullptr);
+    carve_cert(cv, n);
+    return cv.bytes();
+}
+
+}  // namespace fj
+
+using namespace fj;
+
+extern "C" fj_status fj_certify(const fj_graph* g, const double* s, const double* z, double eps, double c,
+                                double sigma, double* out_max_ratio, void* ws, size_t ws_bytes, void* stream) {
+    if (!g || !out_max_ratio || !ws || ((!s || !z) && g->n > 0)) {
+        set_error("fj_certify: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (!(eps > 0.0 && eps < 1.0) || !(c >= 0.0) || !(sigma > 0.0)) {
+        set_error("fj_certify: need eps in (0,1), c >= 0, sigma > 0");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (ws_bytes < certify_ws_bytes(g->n)) {
+        set_error("fj_certify: workspace too small");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    Carver cv(ws);
+    CertLayout C = carve_cert(cv, g->n);
+    SolveLayout L{};
+    L.part_max = C.part_max;
+    L.part_viol = C.part_viol;
+    L.cert_max = C.cert_max;
+    L.cert_viol = C.cert_viol;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // z is the unshifted estimate: the residual of the shifted system equals
+    // s - (I+L) z because (I+L) 1 = 1, so c enters only through the threshold.
+    const double epsp = sigma * eps / (c + sigma);
+    long long viol = 0;
+    return certify<double>(g, s, 0.0, c, epsp, z, static_cast<double*>(nullptr), L, st, out_max_ratio, &viol);
+}
+
+extern "C" size_t fj_solve_workspace_bytes(const fj_graph* g, const fj_solve_opts* opts) {
+    if (!g || !opts) return 0;
+    Carver cv(nullptr);
+    carve_solve(cv, g->n, opts->precision);
+    return cv.bytes();
+}
+
+extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve_opts* o, double* z, void* ws,
+                              size_t ws_bytes, fj_solve_stats* stats, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!g || !o || !z || !ws || (!s && g->n > 0)) {
+        set_error("fj_solve: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (!(o->eps > 0.0 && o->eps < 1.0) || !(o->omega > 0.0 && o->omega < 2.0) || !(o->c >= 0.0) ||
+        !(o->sigma > 0.0) || !std::isfinite(o->c) || !std::isfinite(o->sigma)) {
+        set_error("fj_solve: need eps in (0,1), omega in (0,2), c >= 0, sigma > 0");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (o->precision != FJ_FP32 && o->precision != FJ_FP64) {
+        set_error("fj_solve: precision must be FJ_FP32 or FJ_FP64");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    int sched = o->schedule;
+    if (sched == FJ_SCHED_AUTO) sched = g->num_colours > 0 ? FJ_SCHED_SOR : FJ_SCHED_PUSH;
+    if (sched == FJ_SCHED_SOR && g->num_colours == 0) {
+        set_error("fj_solve: FJ_SCHED_SOR needs a graph created with FJ_GRAPH_COLOUR");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (sched == FJ_SCHED_PUSH && o->omega > 1.0) {
+        set_error("fj_solve: concurrent push rounds need omega <= 1 (over-relaxation needs FJ_SCHED_SOR)");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (sched != FJ_SCHED_PUSH && sched != FJ_SCHED_SOR) {
+        set_error("fj_solve: unknown schedule");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    Carver cv(ws);
+    SolveLayout L = carve_solve(cv, g->n, o->precision);
+    if (cv.bytes() > ws_bytes) {
+        set_error("fj_solve: workspace too small: need " + std::to_string(cv.bytes()) + " bytes");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    FJ_HIP(hipMemsetAsync(L.stats, 0, sizeof(unsigned long long) * kStripes * kStripeStride, st));
+    FJ_HIP(hipMemsetAsync(L.bad, 0, sizeof(int), st));
+    const int one = 1;
+    FJ_HIP(hipMemcpyAsync(L.one, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    const double epsp = o->sigma * o->eps / (o->c + o->sigma);
+    const int64_t cap = o->max_edge_visits > 0 ? o->max_edge_visits : 4096 * (g->nnz + g->n);
+    fj_solve_stats local{};
+    fj_status rc;
+    if (sched == FJ_SCHED_SOR)
+        rc = solve_sor(g, s, o, epsp, z, L, &local, st, cap);
+    else if (o->precision == FJ_FP64)
+        rc = solve_push<double>(g, s, o, epsp, z, L, &local, st, cap);
+    else
+        rc = solve_push<float>(g, s, o, epsp, z, L, &local, st, cap);
+    local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = local;
+    return rc;
+}

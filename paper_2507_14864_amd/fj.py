@@ -1,0 +1,273 @@
+"""Python binding of libfj.so (include/fj.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels.  PyTorch supplies
+device memory (workspaces are torch uint8 tensors) and the current stream.
+There is no CPU fallback: without the built library or a GPU every call raises.
+"""
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfj.so")
+
+FJ_OK, FJ_ERR_INVALID_ARGUMENT, FJ_ERR_WORKSPACE_TOO_SMALL = 0, 1, 2
+FJ_ERR_NOT_CONVERGED, FJ_ERR_HIP, FJ_ERR_UNSUPPORTED = 3, 4, 5
+FJ_GRAPH_COLOUR = 1
+FJ_FP32, FJ_FP64 = 0, 1
+SCHEDULES = {"auto": 0, "push": 1, "sor": 2}
+PRECISIONS = {"fp32": FJ_FP32, "fp64": FJ_FP64}
+
+
+class FJError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[fj status {status}] {message}")
+        self.status = status
+
+
+class FJNotConverged(FJError):
+    """The work cap or refinement budget ran out; ``z`` and ``stats`` hold the
+    last estimate."""
+
+    def __init__(self, status, message, z=None, stats=None):
+        super().__init__(status, message)
+        self.z = z
+        self.stats = stats
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("directed", ctypes.c_int32)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("directed", ctypes.c_int32),
+                ("weighted", ctypes.c_int32), ("max_degree", ctypes.c_int32),
+                ("max_in_degree", ctypes.c_int32), ("num_colours", ctypes.c_int32),
+                ("colour_rounds", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("omega", ctypes.c_double), ("c", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("precision", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("max_edge_visits", ctypes.c_int64), ("max_refinements", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("z0", ctypes.c_void_p), ("profile", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("pushes", ctypes.c_int64), ("edge_visits", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("refinements", ctypes.c_int32), ("certified", ctypes.c_int32),
+                ("max_ratio", ctypes.c_double), ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("kernel_launches", ctypes.c_int64), ("num_colours", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MetricsOut(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_double), ("D", ctypes.c_double), ("I", ctypes.c_double),
+                ("C", ctypes.c_double), ("mean", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libfj.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+        P = ctypes.POINTER
+        L.fj_last_error.restype = ctypes.c_char_p
+        L.fj_version.restype = i32
+        L.fj_graph_workspace_bytes.argtypes = [P(GraphDesc), i32]
+        L.fj_graph_workspace_bytes.restype = sz
+        L.fj_graph_create.argtypes = [P(GraphDesc), i32, vp, sz, vp, P(vp)]
+        L.fj_graph_create.restype = i32
+        L.fj_graph_destroy.argtypes = [vp]
+        L.fj_graph_destroy.restype = i32
+        L.fj_graph_get_info.argtypes = [vp, P(GraphInfo)]
+        L.fj_graph_get_info.restype = i32
+        L.fj_graph_colour_sizes.argtypes = [vp, vp]
+        L.fj_graph_colour_sizes.restype = i32
+        L.fj_graph_colours.argtypes = [vp, vp, vp]
+        L.fj_graph_colours.restype = i32
+        L.fj_solve_workspace_bytes.argtypes = [vp, P(SolveOpts)]
+        L.fj_solve_workspace_bytes.restype = sz
+        L.fj_solve.argtypes = [vp, vp, P(SolveOpts), vp, vp, sz, P(SolveStats), vp]
+        L.fj_solve.restype = i32
+        L.fj_metrics_workspace_bytes.argtypes = [vp]
+        L.fj_metrics_workspace_bytes.restype = sz
+        L.fj_metrics.argtypes = [vp, vp, vp, P(MetricsOut), vp, sz, vp]
+        L.fj_metrics.restype = i32
+        L.fj_certify.argtypes = [vp, vp, vp, dbl, dbl, dbl, P(dbl), vp, sz, vp]
+        L.fj_certify.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != FJ_OK:
+        msg = lib().fj_last_error().decode(errors="replace")
+        raise FJError(rc, msg)
+
+
+def _stream() -> ctypes.c_void_p:
+    if not torch.cuda.is_available():
+        raise RuntimeError("libfj needs a ROCm GPU; none is visible")
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], dtype, n: int, name: str):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor of {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Graph:
+    """A graph resident on the GPU plus the library's ingest products.
+
+    ``row_ptr``/``col``/``w`` are CUDA tensors (int32, int32, float32 or None)
+    holding CSR(A): row i lists j with a_ij > 0.  They are kept alive here.
+    """
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, w: Optional[torch.Tensor] = None,
+                 directed: bool = False, colour: bool = False):
+        n = row_ptr.numel() - 1
+        nnz = col.numel()
+        self.n, self.nnz, self.directed = n, nnz, bool(directed)
+        self.row_ptr, self.col, self.w = row_ptr, col, w
+        self.device = row_ptr.device
+        desc = GraphDesc(n, nnz, _dev_ptr(row_ptr, torch.int32, n + 1, "row_ptr"),
+                         _dev_ptr(col, torch.int32, nnz, "col"),
+                         _dev_ptr(w, torch.float32, nnz, "w") if w is not None else None,
+                         1 if directed else 0)
+        flags = FJ_GRAPH_COLOUR if colour else 0
+        L = lib()
+        nbytes = L.fj_graph_workspace_bytes(ctypes.byref(desc), flags)
+        self.ws = _workspace(nbytes, self.device)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(L.fj_graph_create(ctypes.byref(desc), flags, ctypes.c_void_p(self.ws.data_ptr()),
+                                 self.ws.numel(), _stream(), ctypes.byref(h)))
+        self._h = h
+        self._solve_ws = None
+        self._metrics_ws = None
+
+    @classmethod
+    def from_host(cls, g, device="cuda", colour: bool = False) -> "Graph":
+        """From a host CSR (``synth.CSRGraph`` or anything with n, row_ptr,
+        col, w, directed)."""
+        rp = torch.from_numpy(g.row_ptr).to(device)
+        col = torch.from_numpy(g.col).to(device)
+        w = None if g.w is None else torch.from_numpy(g.w).to(device)
+        return cls(rp, col, w, directed=g.directed, colour=colour)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = GraphInfo()
+        _check(lib().fj_graph_get_info(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in out._fields_}
+
+    def colour_sizes(self):
+        k = self.info()["num_colours"]
+        buf = (ctypes.c_int64 * max(k, 1))()
+        _check(lib().fj_graph_colour_sizes(self._h, buf))
+        return [int(buf[i]) for i in range(k)]
+
+    def colours(self) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(lib().fj_graph_colours(self._h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.fj_graph_destroy(h)
+            self._h = None
+
+
+def make_opts(eps=1e-4, omega=1.0, c=1e-5, sigma=1e-5, precision="fp32", schedule="auto",
+              max_edge_visits=0, max_refinements=-1, check_every=8, z0=None, profile=False) -> SolveOpts:
+    return SolveOpts(float(eps), float(omega), float(c), float(sigma), PRECISIONS[precision],
+                     SCHEDULES[schedule], int(max_edge_visits), int(max_refinements), int(check_every),
+                     None if z0 is None else ctypes.c_void_p(z0.data_ptr()), 1 if profile else 0)
+
+
+def solve(graph: Graph, s: torch.Tensor, eps: float = 1e-4, omega: float = 1.0, c: float = 1e-5,
+          sigma: float = 1e-5, precision: str = "fp32", schedule: str = "auto", max_edge_visits: int = 0,
+          max_refinements: int = -1, check_every: int = 8, z0: Optional[torch.Tensor] = None,
+          out: Optional[torch.Tensor] = None, profile: bool = False):
+    """ImprovedBLISOR on the GPU.  Returns (z, stats dict).
+
+    Raises FJNotConverged (with .z and .stats) when the certificate could not
+    be reached."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    if z0 is not None:
+        _dev_ptr(z0, torch.float64, n, "z0")
+    z = out if out is not None else torch.empty(n, dtype=torch.float64, device=graph.device)
+    _dev_ptr(z, torch.float64, n, "out")
+    opts = make_opts(eps, omega, c, sigma, precision, schedule, max_edge_visits, max_refinements,
+                     check_every, z0, profile)
+    L = lib()
+    nbytes = L.fj_solve_workspace_bytes(graph.handle, ctypes.byref(opts))
+    if graph._solve_ws is None or graph._solve_ws.numel() < nbytes:
+        graph._solve_ws = _workspace(nbytes, graph.device)
+    ws = graph._solve_ws
+    st = SolveStats()
+    rc = L.fj_solve(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.byref(opts),
+                    ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                    ctypes.byref(st), _stream())
+    if rc == FJ_ERR_NOT_CONVERGED:
+        raise FJNotConverged(rc, L.fj_last_error().decode(errors="replace"), z, st.to_dict())
+    _check(rc)
+    return z, st.to_dict()
+
+
+def _metrics_ws(graph: Graph) -> torch.Tensor:
+    nbytes = lib().fj_metrics_workspace_bytes(graph.handle)
+    if graph._metrics_ws is None or graph._metrics_ws.numel() < nbytes:
+        graph._metrics_ws = _workspace(nbytes, graph.device)
+    return graph._metrics_ws
+
+
+def metrics(graph: Graph, s: torch.Tensor, z: torch.Tensor) -> dict:
+    """Table 1 measures P, D, I, C (and the mean of z), FP64, reproducible."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(z, torch.float64, n, "z")
+    ws = _metrics_ws(graph)
+    out = MetricsOut()
+    _check(lib().fj_metrics(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                            ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def certify(graph: Graph, s: torch.Tensor, z: torch.Tensor, eps: float, c: float = 1e-5,
+            sigma: float = 1e-5) -> float:
+    """max_v |s_v - ((I+L) z)_v| / (eps' (s_v + c)) in FP64 on the GPU."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(z, torch.float64, n, "z")
+    ws = _metrics_ws(graph)
+    out = ctypes.c_double()
+    _check(lib().fj_certify(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                            float(eps), float(c), float(sigma), ctypes.byref(out),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out.value

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every entry point include/fj.h declares.
+
+No compute call is made here (no GPU in this tier); only the pure host
+workspace-size query is exercised.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fj.h")
+LIB = os.path.join(ROOT, "paper_2507_14864_amd", "libfj.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(fj_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2507_14864_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["fj_graph_create", "fj_solve", "fj_metrics", "fj_graph_destroy",
+                     "fj_solve_workspace_bytes", "fj_graph_workspace_bytes", "fj_last_error"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_graph_workspace_query_is_host_only(lib):
+    from paper_2507_14864_amd.fj import GraphDesc
+    f = lib.fj_graph_workspace_bytes
+    f.argtypes = [ctypes.POINTER(GraphDesc), ctypes.c_int32]
+    f.restype = ctypes.c_size_t
+    dummy = ctypes.c_void_p(256)
+    d = GraphDesc(1000, 5000, dummy, dummy, None, 0)
+    plain = f(ctypes.byref(d), 0)
+    coloured = f(ctypes.byref(d), 1)
+    d2 = GraphDesc(1000, 5000, dummy, dummy, dummy, 1)
+    directed = f(ctypes.byref(d2), 0)
+    assert 0 < plain < coloured
+    assert directed > plain  # CSR(A^T) with weights
+    bad = GraphDesc(-1, 5, dummy, dummy, None, 0)
+    assert f(ctypes.byref(bad), 0) == 0
+    assert lib.fj_version() == 1
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import paper_2507_14864_amd as fj
+    with pytest.raises((RuntimeError, ValueError)):
+        fj.Graph(torch.zeros(3, dtype=torch.int32), torch.zeros(0, dtype=torch.int32))

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes are small enough for the oracle to finish in seconds while spanning many
+64-row tiles and a ragged last tile.  Tolerances follow from the method's
+certificate: with c = sigma, eps' = eps/2 and every node with z >= sigma is
+within relative error eps (Lemma 7 with Alg. 2's shift); the FP64 path is held
+to 1e-6 relative on z and the measures, the FP32 path to 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import graphs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def fjmod():
+    import paper_2507_14864_amd as fj
+    return fj
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def check_solution(g, s, z_gpu, z_true, eps, c=1e-5, sigma=1e-5):
+    """Entrywise bound of Lemma 7 after the shift, and the relative-error claim."""
+    epsp = sigma * eps / (c + sigma)
+    z = z_gpu.cpu().numpy()
+    assert np.all(np.isfinite(z))
+    bound = epsp * (z_true + c) * (1 + 1e-9) + 1e-15
+    worst = np.max(np.abs(z - z_true) - bound)
+    assert worst <= 0, f"Lemma 7 bound violated by {worst}"
+    assert oracle.max_rel_error(z, z_true, floor=sigma) <= eps
+    # the GPU certificate claim, recomputed by the oracle in FP64
+    assert oracle.certificate(g, s, z, eps, sigma=sigma, c=c) <= 1.0 + 1e-9
+
+
+# ------------------------------------------------------ config 1: BA n=2000
+@pytest.mark.parametrize("schedule,omega", [("push", 1.0), ("sor", 1.0), ("sor", 1.5)])
+def test_ba2000_fp64_against_dense(schedule, omega):
+    fj = fjmod()
+    g = synth.barabasi_albert(2000, 3, 1)
+    s = synth.opinions(g.n, "uniform", 1)
+    zt = oracle.dense_solve(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    z, st = fj.solve(G, sd, eps=1e-8, omega=omega, precision="fp64", schedule=schedule)
+    assert st["certified"] == 1 and st["max_ratio"] <= 1.0
+    check_solution(g, s, z, zt, 1e-8)
+    m = fj.metrics(G, sd, z)
+    mo = oracle.metrics(g, s, zt)
+    for k in "PDIC":
+        assert abs(m[k] - mo[k]) <= 1e-6 * abs(mo[k]), (k, m[k], mo[k])
+
+
+# --------------------------------------------- FP32 path, mid-size power law
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("schedule,omega", [("push", 1.0), ("sor", 1.0), ("sor", 1.3)])
+def test_chung_lu_fp32_against_exact(directed, schedule, omega):
+    fj = fjmod()
+    n = 30011  # ragged last tile
+    g = synth.chung_lu(n, 8 * n, 2.3 if not directed else 2.1, 7 + directed, directed=directed,
+                       weighted=directed)
+    s = synth.opinions(n, "bimodal", 8)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    z, st = fj.solve(G, sd, eps=1e-4, omega=omega, precision="fp32", schedule=schedule)
+    assert st["certified"] == 1
+    check_solution(g, s, z, zt, 1e-4)
+    m = fj.metrics(G, sd, z)
+    mo = oracle.metrics(g, s, zt)
+    for k in "PDIC":
+        assert abs(m[k] - mo[k]) <= 1e-4 * abs(mo[k]), (k, m[k], mo[k])
+
+
+@pytest.mark.parametrize("kind", ["uniform", "exp", "pareto"])
+def test_opinion_distributions(kind):
+    """The paper's three opinion laws (Sec. 6); Pareto puts many s near 0,
+    which the shift c must handle."""
+    fj = fjmod()
+    g = synth.chung_lu(20000, 100000, 2.3, 17)
+    s = synth.opinions(g.n, kind, 18)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    for sched, omega in (("push", 1.0), ("sor", 1.5)):
+        z, st = fj.solve(G, to_dev(s), eps=1e-4, omega=omega, schedule=sched)
+        check_solution(g, s, z, zt, 1e-4)
+
+
+# --------------------------------------------------------------- measures
+def test_metrics_match_oracle_on_same_z_and_are_reproducible():
+    fj = fjmod()
+    for directed in (False, True):
+        g = synth.chung_lu(50000, 300000, 2.2, 21, directed=directed, weighted=True)
+        s = synth.opinions(g.n, "uniform", 22)
+        z = synth.opinions(g.n, "beta", 23, a=2, b=2)  # any vector: the reductions are the unit under test
+        G = fj.Graph.from_host(g, DEV)
+        sd, zd = to_dev(s), to_dev(z)
+        m1 = fj.metrics(G, sd, zd)
+        m2 = fj.metrics(G, sd, zd)
+        mo = oracle.metrics(g, s, z)
+        for k in ("P", "D", "I", "C", "mean"):
+            assert m1[k] == m2[k]  # bitwise: fixed-order reductions
+            assert abs(m1[k] - mo[k]) <= 1e-12 * abs(mo[k]), (k, m1[k], mo[k])
+
+
+def test_certificate_matches_oracle():
+    fj = fjmod()
+    g = synth.chung_lu(40000, 200000, 2.3, 31, directed=True, weighted=True)
+    s = synth.opinions(g.n, "uniform", 32)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV)
+    for z in (zt, zt * (1 + 2e-4), s):
+        want = oracle.certificate(g, s, z, 1e-4)
+        got = fj.certify(G, to_dev(s), to_dev(z), 1e-4)
+        assert abs(got - want) <= 1e-9 * max(1.0, want)
+
+
+# ------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 129])
+def test_ragged_and_tiny(n):
+    fj = fjmod()
+    g = graphs.random_graph(n, min(1.0, 6.0 / max(n, 1)), 40 + n)
+    s = synth.opinions(n, "uniform", 41)
+    zt = oracle.dense_solve(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    for sched, omega in (("push", 1.0), ("sor", 1.7)):
+        z, st = fj.solve(G, to_dev(s), eps=1e-6, omega=omega, precision="fp64", schedule=sched)
+        check_solution(g, s, z, zt, 1e-6)
+
+
+def test_graph_without_edges_returns_s():
+    fj = fjmod()
+    n = 1000
+    g = synth.CSRGraph(n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), None, False)
+    s = synth.opinions(n, "uniform", 5)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    for sched in ("push", "sor"):
+        z, st = fj.solve(G, to_dev(s), eps=1e-6, precision="fp64", schedule=sched)
+        assert np.allclose(z.cpu().numpy(), s, rtol=1e-6, atol=1e-11)
+
+
+def test_constant_and_zero_opinions():
+    fj = fjmod()
+    g = synth.chung_lu(10000, 50000, 2.3, 51, directed=True, weighted=True)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    s = np.full(g.n, 0.42)
+    for sched in ("push", "sor"):
+        z, _ = fj.solve(G, to_dev(s), eps=1e-5, schedule=sched)
+        assert np.allclose(z.cpu().numpy(), 0.42, rtol=1e-5)
+    s0 = np.zeros(g.n)
+    s0[::11] = 1.0
+    zt = oracle.exact(g, s0)
+    for sched in ("push", "sor"):
+        z, _ = fj.solve(G, to_dev(s0), eps=1e-4, schedule=sched)
+        check_solution(g, s0, z, zt, 1e-4)
+
+
+def test_colouring_is_proper_and_classes_cover_nodes():
+    fj = fjmod()
+    for directed in (False, True):
+        g = synth.chung_lu(30000, 200000, 2.1, 61, directed=directed)
+        G = fj.Graph.from_host(g, DEV, colour=True)
+        col = G.colours().cpu().numpy()
+        rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        assert np.all(col[rows] != col[g.col])  # no arc joins two nodes of one class
+        sizes = G.colour_sizes()
+        assert sum(sizes) == g.n and len(sizes) == col.max() + 1
+        assert np.array_equal(np.bincount(col, minlength=len(sizes)), sizes)
+
+
+def test_warm_start_reaches_same_certificate():
+    fj = fjmod()
+    g = synth.chung_lu(30000, 150000, 2.3, 71)
+    s = synth.opinions(g.n, "bimodal", 72)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    for sched, omega in (("push", 1.0), ("sor", 1.4)):
+        z_cold, st_cold = fj.solve(G, sd, eps=1e-4, omega=omega, schedule=sched)
+        z_warm, st_warm = fj.solve(G, sd, eps=1e-4, omega=omega, schedule=sched, z0=to_dev(zt))
+        assert st_warm["pushes"] == 0
+        check_solution(g, s, z_warm, zt, 1e-4)
+        z_s, st_s = fj.solve(G, sd, eps=1e-4, omega=omega, schedule=sched, z0=sd.clone())
+        check_solution(g, s, z_s, zt, 1e-4)
+
+
+# -------------------------------------------------------------- errors
+def test_invalid_inputs_are_rejected():
+    fj = fjmod()
+    ok = graphs.from_arcs(4, [(0, 1), (1, 2), (2, 3)])
+    bad_graphs = [
+        synth.CSRGraph(3, np.array([0, 2, 2, 3], np.int32), np.array([2, 1, 0], np.int32), None, True),  # unsorted
+        synth.CSRGraph(3, np.array([0, 1, 1, 1], np.int32), np.array([0], np.int32), None, True),  # self-loop
+        synth.CSRGraph(3, np.array([0, 1, 1, 1], np.int32), np.array([7], np.int32), None, True),  # out of range
+        synth.CSRGraph(3, np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32), None, False),  # asymmetric
+        synth.CSRGraph(3, np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32),
+                       np.array([-1.0], np.float32), True),  # negative weight
+    ]
+    for bg in bad_graphs:
+        with pytest.raises(fj.FJError) as e:
+            fj.Graph.from_host(bg, DEV)
+        assert e.value.status == 1
+    G = fj.Graph.from_host(ok, DEV, colour=True)
+    with pytest.raises(fj.FJError) as e:
+        fj.solve(G, to_dev(np.array([0.1, -0.2, 0.3, 0.4])), eps=1e-4)
+    assert e.value.status == 1
+    with pytest.raises(fj.FJError):
+        fj.solve(G, to_dev(np.array([0.1, 0.2, 0.3, 0.4])), eps=1e-4, omega=1.5, schedule="push")
+    with pytest.raises(fj.FJError):
+        fj.solve(G, to_dev(np.array([0.1, 0.2, 0.3, 0.4])), eps=2.0)
+    plain = fj.Graph.from_host(ok, DEV)
+    with pytest.raises(fj.FJError):
+        fj.solve(plain, to_dev(np.array([0.1, 0.2, 0.3, 0.4])), eps=1e-4, schedule="sor")
+
+
+def test_work_cap_reports_not_converged():
+    fj = fjmod()
+    g = synth.chung_lu(20000, 100000, 2.3, 81)
+    s = synth.opinions(g.n, "uniform", 82)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    for sched in ("push", "sor"):
+        with pytest.raises(fj.FJNotConverged) as e:
+            fj.solve(G, to_dev(s), eps=1e-6, schedule=sched, max_edge_visits=1000, check_every=1)
+        assert e.value.stats["certified"] == 0
+        assert np.all(np.isfinite(e.value.z.cpu().numpy()))
