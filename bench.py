@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--persistent", action="store_true",
+                    help="SOR as one cooperative launch with grid barriers between colour classes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -137,7 +139,7 @@ def main():
 
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
-                          out=z, profile=profile)
+                          out=z, profile=profile, persistent=args.persistent)
         m = fj.metrics(G, sd, zz)
         return st, m
 

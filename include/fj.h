@@ -128,6 +128,8 @@ typedef struct {
     const double* z0;        /* device [n] warm start (any vector, Lemma 4), or NULL */
     int32_t profile;         /* nonzero: time every launch of the iteration kernel with HIP
                                 events on `stream` (adds small gaps between launches) */
+    int32_t persistent;      /* nonzero: SOR runs as one cooperative launch with a grid
+                                barrier per colour class instead of one launch per class */
 } fj_solve_opts;
 
 typedef struct {

@@ -376,12 +376,126 @@ __global__ void k_perm_copy(int64_t n, const int32_t* __restrict__ perm, const i
 
 inline unsigned grid1d(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
+// ---------------------------------------------------------------- tile sets
+__device__ __forceinline__ bool is_heavy(const int32_t* rp, int64_t i) { return rp[i + 1] - rp[i] > kArcBudget; }
+
+__global__ void k_tile_mark(int64_t n, const int32_t* __restrict__ rp, int32_t* mark, int32_t* hm, int32_t* cm) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        mark[n] = 0; hm[n] = 0; cm[n] = 0;
+        return;
+    }
+    bool hv = is_heavy(rp, i);
+    bool start = (i % 64 == 0) || hv;
+    if (i > 0) start = start || is_heavy(rp, i - 1) || (rp[i] / kArcBudget != rp[i - 1] / kArcBudget);
+    mark[i] = start ? 1 : 0;
+    hm[i] = hv ? 1 : 0;
+    cm[i] = hv ? (rp[i + 1] - rp[i] + kArcBudget - 1) / kArcBudget : 0;
+}
+
+__global__ void k_seg_mark(const int64_t* __restrict__ seg, int nseg, int64_t n, int32_t* mark) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nseg && seg[k] < n) mark[seg[k]] = 1;
+}
+
+__global__ void k_tile_fill(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ mark,
+                            const int32_t* __restrict__ tscan, const int32_t* __restrict__ hscan,
+                            const int32_t* __restrict__ cscan, int32_t* tile_start, int32_t* tile_heavy,
+                            int32_t* heavy_row, int32_t* heavy_chunk0, int32_t* chunk_heavy, int32_t* chunk_beg) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        tile_start[tscan[n]] = static_cast<int32_t>(n);
+        heavy_chunk0[hscan[n]] = cscan[n];
+        return;
+    }
+    bool hv = is_heavy(rp, i);
+    if (mark[i]) {
+        tile_start[tscan[i]] = static_cast<int32_t>(i);
+        tile_heavy[tscan[i]] = hv ? hscan[i] : -1;
+    }
+    if (hv) {
+        int32_t h = hscan[i], c0 = cscan[i];
+        heavy_row[h] = static_cast<int32_t>(i);
+        heavy_chunk0[h] = c0;
+        int32_t nch = (rp[i + 1] - rp[i] + kArcBudget - 1) / kArcBudget;
+        for (int32_t j = 0; j < nch; ++j) {
+            chunk_heavy[c0 + j] = h;
+            chunk_beg[c0 + j] = rp[i] + j * kArcBudget;
+        }
+    }
+}
+
+__global__ void k_seg_offsets(const int64_t* __restrict__ seg, int nseg, const int32_t* __restrict__ tscan,
+                              const int32_t* __restrict__ hscan, const int32_t* __restrict__ cscan, int32_t* out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nseg) return;
+    int64_t row = seg[k];
+    out[3 * k + 0] = tscan[row];
+    out[3 * k + 1] = hscan[row];
+    out[3 * k + 2] = cscan[row];
+}
+
+struct TileTemps {
+    int32_t* mark; int32_t* tscan; int32_t* hscan; int32_t* cscan; int64_t* seg; int32_t* segout; void* scan_tmp;
+};
+
+void carve_tileset(Carver& cv, TileSet& T, int64_t n, int64_t nnz) {
+    int64_t hmax = nnz / kArcBudget + 1;
+    T.d_seg_tile = cv.take<int64_t>(kMaxColours + 2);
+    T.d_seg_heavy = cv.take<int64_t>(kMaxColours + 2);
+    T.tile_start = cv.take<int32_t>(n + 1);
+    T.tile_heavy = cv.take<int32_t>(n + 1);
+    T.heavy_row = cv.take<int32_t>(hmax);
+    T.heavy_chunk0 = cv.take<int32_t>(hmax + 1);
+    T.chunk_heavy = cv.take<int32_t>(2 * hmax + 2);
+    T.chunk_beg = cv.take<int32_t>(2 * hmax + 2);
+}
+
+// segments: sorted row starts, segs.front() = 0, segs.back() = n
+fj_status build_tiles(TileSet& T, int64_t n, const int32_t* rp, const std::vector<int64_t>& segs,
+                      const TileTemps& tmp, hipStream_t st) {
+    const int bs = 256;
+    const int nseg = static_cast<int>(segs.size()) - 1;
+    FJ_HIP(hipMemcpyAsync(tmp.seg, segs.data(), sizeof(int64_t) * segs.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_tile_mark, dim3(grid1d(n + 1, bs)), dim3(bs), 0, st, n, rp, tmp.mark, tmp.hscan, tmp.cscan);
+    if (nseg > 0) hipLaunchKernelGGL(k_seg_mark, dim3(grid1d(nseg, bs)), dim3(bs), 0, st, tmp.seg, nseg, n, tmp.mark);
+    exclusive_scan_i32(tmp.mark, tmp.tscan, n + 1, tmp.scan_tmp, st);
+    exclusive_scan_i32(tmp.hscan, tmp.hscan, n + 1, tmp.scan_tmp, st);
+    exclusive_scan_i32(tmp.cscan, tmp.cscan, n + 1, tmp.scan_tmp, st);
+    hipLaunchKernelGGL(k_tile_fill, dim3(grid1d(n + 1, bs)), dim3(bs), 0, st, n, rp, tmp.mark, tmp.tscan, tmp.hscan,
+                       tmp.cscan, T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg);
+    hipLaunchKernelGGL(k_seg_offsets, dim3(grid1d(nseg + 1, bs)), dim3(bs), 0, st, tmp.seg, nseg, tmp.tscan, tmp.hscan,
+                       tmp.cscan, tmp.segout);
+    std::vector<int32_t> h(3 * (nseg + 1));
+    FJ_HIP(hipMemcpyAsync(h.data(), tmp.segout, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    T.seg_tile.resize(nseg + 1);
+    T.seg_heavy.resize(nseg + 1);
+    T.seg_chunk.resize(nseg + 1);
+    for (int k = 0; k <= nseg; ++k) {
+        T.seg_tile[k] = h[3 * k];
+        T.seg_heavy[k] = h[3 * k + 1];
+        T.seg_chunk[k] = h[3 * k + 2];
+    }
+    T.ntiles = T.seg_tile[nseg];
+    T.nheavy = T.seg_heavy[nseg];
+    T.nchunks = T.seg_chunk[nseg];
+    FJ_HIP(hipMemcpyAsync(T.d_seg_tile, T.seg_tile.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, st));
+    FJ_HIP(hipMemcpyAsync(T.d_seg_heavy, T.seg_heavy.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    return FJ_OK;
+}
+
 struct GraphLayout {
     double* opd; double* inv64; float* inv32;
     int32_t* t_row_ptr; int32_t* t_col; float* t_w; int32_t* t_cursor;
     int32_t* colour; uint64_t* key; int32_t* cur1; int32_t* cur2; int32_t* perm; int32_t* iperm;
     int32_t* hist; int64_t* class_off; int32_t* prow_ptr; int32_t* pcol; float* pw; double* popd; double* pinv64;
     int* flags; void* scan_tmp;
+    TileSet ta, tt, tp;
+    TileTemps tmp;
 };
 
 constexpr int kMaxJpRounds = 1 << 16;
@@ -419,6 +533,16 @@ GraphLayout carve_graph(Carver& cv, const fj_graph_desc* d, int32_t flags) {
         scan_n = std::max<int64_t>(scan_n, static_cast<int64_t>(kMaxColours) * nchunks);
     }
     L.scan_tmp = cv.take<char>(scan_tmp_bytes(scan_n));
+    carve_tileset(cv, L.ta, n, nnz);
+    if (d->directed) carve_tileset(cv, L.tt, n, nnz);
+    if (flags & FJ_GRAPH_COLOUR) carve_tileset(cv, L.tp, n, nnz);
+    L.tmp.mark = cv.take<int32_t>(n + 1);
+    L.tmp.tscan = cv.take<int32_t>(n + 1);
+    L.tmp.hscan = cv.take<int32_t>(n + 1);
+    L.tmp.cscan = cv.take<int32_t>(n + 1);
+    L.tmp.seg = cv.take<int64_t>(kMaxColours + 2);
+    L.tmp.segout = cv.take<int32_t>(3 * (kMaxColours + 2));
+    L.tmp.scan_tmp = L.scan_tmp;
     return L;
 }
 
@@ -511,6 +635,20 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     g->max_degree = hdeg[0];
     g->max_in_degree = d->directed ? hdeg[1] : hdeg[0];
 
+    if (n > 0) {
+        std::vector<int64_t> whole = {0, n};
+        g->tiles_a = L.ta;
+        fj_status rc = build_tiles(g->tiles_a, n, d->row_ptr, whole, L.tmp, st);
+        if (rc) return rc;
+        if (d->directed) {
+            g->tiles_t = L.tt;
+            rc = build_tiles(g->tiles_t, n, g->t_row_ptr, whole, L.tmp, st);
+            if (rc) return rc;
+        } else {
+            g->tiles_t = g->tiles_a;
+        }
+    }
+
     if (!(flags & FJ_GRAPH_COLOUR) || n == 0) return FJ_OK;
 
     // Jones-Plassmann colouring, rounds until no node is pending
@@ -570,6 +708,11 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     hipLaunchKernelGGL(k_perm_copy, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, L.perm, L.iperm, d->row_ptr, d->col,
                        d->w, L.opd, L.inv64, L.prow_ptr, L.pcol, L.pw, L.popd, L.pinv64);
     FJ_HIP(hipStreamSynchronize(st));
+    g->tiles_p = L.tp;
+    {
+        fj_status rc = build_tiles(g->tiles_p, n, L.prow_ptr, g->class_off, L.tmp, st);
+        if (rc) return rc;
+    }
     g->perm = L.perm;
     g->iperm = L.iperm;
     g->prow_ptr = L.prow_ptr;

@@ -42,6 +42,61 @@ struct Carver {
     size_t bytes() const { return (off + 255) & ~size_t(255); }
 };
 
+// Work partition of a CSR row range for wave-level kernels.
+//  - Light tiles: at most 64 consecutive rows and fewer than 2*kArcBudget arcs
+//    (a tile starts at every 64th row, wherever floor(row_ptr/kArcBudget)
+//    changes, at every segment start, and around every heavy row).
+//  - Heavy rows: more than kArcBudget arcs.  Each is a tile of its own and is
+//    split into chunks of kArcBudget arcs; partial sums per chunk are combined
+//    in chunk order by a second launch.
+// Segments (colour classes, or one segment for the whole graph) never share a
+// tile; per-segment offsets into every list are kept on the host.
+constexpr int kArcBudget = 256;
+// rows longer than this are reduced by a whole block in the persistent sweep
+constexpr int kBigRow = 2048;
+
+struct TileSet {
+    int64_t ntiles = 0, nheavy = 0, nchunks = 0;
+    int32_t* tile_start = nullptr;   // [ntiles + 1]
+    int32_t* tile_heavy = nullptr;   // [ntiles] heavy index of a heavy tile, else -1
+    int32_t* heavy_row = nullptr;    // [nheavy]
+    int32_t* heavy_chunk0 = nullptr; // [nheavy + 1]
+    int32_t* chunk_heavy = nullptr;  // [nchunks] heavy index owning the chunk
+    int32_t* chunk_beg = nullptr;    // [nchunks] first arc of the chunk
+    std::vector<int64_t> seg_tile, seg_heavy, seg_chunk;  // [nseg + 1] host offsets
+    int64_t* d_seg_tile = nullptr;   // device copies of seg_tile / seg_heavy
+    int64_t* d_seg_heavy = nullptr;
+};
+
+// Kernel-argument view of one segment of a TileSet (or of all of it).
+struct TileView {
+    const int32_t* tile_start;
+    const int32_t* tile_heavy;
+    const int32_t* heavy_row;
+    const int32_t* heavy_chunk0;
+    const int32_t* chunk_heavy;
+    const int32_t* chunk_beg;
+    int64_t t0, ntiles;  // tiles [t0, t0 + ntiles)
+    int64_t c0, nchunks; // heavy chunks [c0, c0 + nchunks)
+    int64_t h0, h1;      // heavy rows [h0, h1)
+};
+
+inline TileView tile_view(const TileSet& T, int seg) {
+    TileView v{T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg,
+               T.seg_tile[seg], T.seg_tile[seg + 1] - T.seg_tile[seg],
+               T.seg_chunk[seg], T.seg_chunk[seg + 1] - T.seg_chunk[seg],
+               T.seg_heavy[seg], T.seg_heavy[seg + 1]};
+    return v;
+}
+inline TileView tile_view_all(const TileSet& T) {
+    TileView v{T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg,
+               0, T.ntiles, 0, T.nchunks, 0, T.nheavy};
+    return v;
+}
+inline unsigned waves_to_blocks(int64_t waves) {
+    return static_cast<unsigned>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
 }  // namespace fj
 
 // Host object behind fj_graph*.
@@ -72,6 +127,10 @@ struct fj_graph {
     float* pw = nullptr;
     double* popd = nullptr;          // 1 + d, relabelled
     double* pinv64 = nullptr;
+    // wave work partitions
+    fj::TileSet tiles_a;   // CSR(A), original labels (certificate, measures)
+    fj::TileSet tiles_t;   // CSR(A^T), original labels (push); same as tiles_a when undirected
+    fj::TileSet tiles_p;   // relabelled CSR(A), one segment per colour class (SOR)
 };
 
 namespace fj {
@@ -84,7 +143,7 @@ size_t graph_ws_bytes(const fj_graph_desc* d, int32_t flags);
 // Scan helper (fj_graph.hip): exclusive scan of int32 in -> out (may alias), n entries,
 // returns total through *total_dev (device int64) when not null. tmp: scan_tmp_bytes(n).
 size_t scan_tmp_bytes(int64_t n);
-size_t certify_ws_bytes(int64_t n);
+size_t certify_ws_bytes(const fj_graph* g);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t st);
 
 }  // namespace fj

@@ -16,7 +16,9 @@ constexpr int kNodeItems = 8;
 constexpr int kNodeTile = kBlock * kNodeItems;
 
 inline unsigned nblocks_nodes(int64_t n) { return static_cast<unsigned>((n + kNodeTile - 1) / kNodeTile); }
-inline unsigned nblocks_tiles(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+inline unsigned nblocks_edges(const fj_graph* g) {
+    return waves_to_blocks(g->tiles_a.nchunks + g->tiles_a.ntiles);
+}
 
 // pass 1: sum z, sum z^2, sum (z - s)^2 per block
 __global__ __launch_bounds__(kBlock) void k_metrics_nodes(int64_t n, const double* __restrict__ s,
@@ -63,23 +65,41 @@ __global__ __launch_bounds__(kBlock) void k_metrics_centred(int64_t n, const dou
     if (threadIdx.x == 0) part[blockIdx.x] = a;
 }
 
-// edges: each lane accumulates its own arcs; wave tiles of 64 rows
-__global__ __launch_bounds__(kBlock) void k_metrics_edges(int64_t n, const int32_t* __restrict__ row_ptr,
+// edges: each lane accumulates its own arcs over a light tile or one chunk of
+// a heavy row; fixed-order block sums
+__global__ __launch_bounds__(kBlock) void k_metrics_edges(TileView tv, const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ col, const float* __restrict__ w,
                                                           const double* __restrict__ z, double* part) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_z[kWavesPerBlock][64];
     __shared__ double lds[kWavesPerBlock];
     const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64;
-    const int nrows = static_cast<int>(row0 < n ? (n - row0 < 64 ? n - row0 : 64) : 0);
-    if (lane < nrows) s_z[wid][lane] = z[row0 + lane];
+    const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     double acc = 0.0;
-    tile_for_each_arc(row_ptr, row0, nrows, s_pre[wid], [&](int k, int slot) {
-        double d = s_z[wid][slot] - z[col[k]];
-        double a = w ? static_cast<double>(w[k]) : 1.0;
-        acc += a * d * d;
-    });
+    if (wv < tv.nchunks) {
+        const int64_t c = tv.c0 + wv;
+        const int32_t row = tv.heavy_row[tv.chunk_heavy[c]];
+        const double zi = z[row];
+        const int beg = tv.chunk_beg[c];
+        const int end = min(beg + kArcBudget, row_ptr[row + 1]);
+        for (int k = beg + lane; k < end; k += 64) {
+            double d = zi - z[col[k]];
+            double a = w ? static_cast<double>(w[k]) : 1.0;
+            acc += a * d * d;
+        }
+    } else if (wv - tv.nchunks < tv.ntiles) {
+        const int64_t tix = tv.t0 + (wv - tv.nchunks);
+        if (tv.tile_heavy[tix] < 0) {
+            const int32_t r0 = tv.tile_start[tix];
+            const int nrows = tv.tile_start[tix + 1] - r0;
+            if (lane < nrows) s_z[wid][lane] = z[r0 + lane];
+            tile_for_each_arc(row_ptr, r0, nrows, s_pre[wid], [&](int k, int slot) {
+                double d = s_z[wid][slot] - z[col[k]];
+                double a = w ? static_cast<double>(w[k]) : 1.0;
+                acc += a * d * d;
+            });
+        }
+    }
     acc = block_sum<kBlock>(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
@@ -125,11 +145,12 @@ struct MetricsLayout {
     double* part1; double* part2; double* part_d; double* out;
 };
 
-MetricsLayout carve_metrics(Carver& cv, int64_t n) {
+MetricsLayout carve_metrics(Carver& cv, const fj_graph* g) {
+    const int64_t n = g->n;
     MetricsLayout L{};
     L.part1 = cv.take<double>(3 * (nblocks_nodes(n) + 1));
     L.part2 = cv.take<double>(nblocks_nodes(n) + 1);
-    L.part_d = cv.take<double>(nblocks_tiles(n) + 1);
+    L.part_d = cv.take<double>(nblocks_edges(g) + 1);
     L.out = cv.take<double>(8);
     return L;
 }
@@ -142,8 +163,8 @@ using namespace fj;
 extern "C" size_t fj_metrics_workspace_bytes(const fj_graph* g) {
     if (!g) return 0;
     Carver cv(nullptr);
-    carve_metrics(cv, g->n);
-    size_t cert = certify_ws_bytes(g->n);  // fj_certify shares this workspace
+    carve_metrics(cv, g);
+    size_t cert = certify_ws_bytes(g);  // fj_certify shares this workspace
     return cv.bytes() > cert ? cv.bytes() : cert;
 }
 
@@ -158,14 +179,15 @@ extern "C" fj_status fj_metrics(const fj_graph* g, const double* s, const double
         return FJ_ERR_WORKSPACE_TOO_SMALL;
     }
     Carver cv(ws);
-    MetricsLayout L = carve_metrics(cv, g->n);
+    MetricsLayout L = carve_metrics(cv, g);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = g->n;
     double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (n > 0) {
-        const unsigned nbn = nblocks_nodes(n), nbt = nblocks_tiles(n);
+        const unsigned nbn = nblocks_nodes(n), nbt = nblocks_edges(g);
         hipLaunchKernelGGL(k_metrics_nodes, dim3(nbn), dim3(kBlock), 0, st, n, s, z, L.part1);
-        hipLaunchKernelGGL(k_metrics_edges, dim3(nbt), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w, z, L.part_d);
+        hipLaunchKernelGGL(k_metrics_edges, dim3(nbt), dim3(kBlock), 0, st, tile_view_all(g->tiles_a), g->row_ptr,
+                           g->col, g->w, z, L.part_d);
         hipLaunchKernelGGL(k_metrics_mean, dim3(1), dim3(1024), 0, st, L.part1, static_cast<int64_t>(nbn), n, L.out);
         hipLaunchKernelGGL(k_metrics_centred, dim3(nbn), dim3(kBlock), 0, st, n, z, L.out + 4, L.part2);
         hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(1024), 0, st, L.part2, static_cast<int64_t>(nbn), L.part_d,

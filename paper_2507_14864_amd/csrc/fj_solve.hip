@@ -3,11 +3,13 @@
 // with Eqs. (sor1)-(sor3)), FP64 certificate (Lemma 7), refinement, unshift.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
 #include "fj_device.h"
 #include "fj_internal.h"
+#include "fj_grid.h"
 #include "fj_tile.h"
 
 namespace fj {
@@ -58,46 +60,97 @@ __global__ void k_init_warm(int64_t n, const double* __restrict__ s, const doubl
 // ------------------------------------------------------------ certificate
 // r = s' - (I+L) zhat' in FP64 over CSR(A): r_i = s'_i - (1+d_i) zhat'_i +
 // sum_j a_ij zhat'_j.  Per block: max |r_i| / h_i and the count of rows with
-// |r_i| > h_i (Alg. 3's stopping test).  refine != 0 also stores fl(r) as the
-// new tracked residual, which resets FP32 drift (Lemma 4 holds for any zhat').
+// |r_i| > h_i (Alg. 3's stopping test).  r_out != NULL also stores fl(r) as
+// the new tracked residual, which resets FP32 drift (Lemma 4 holds for any
+// zhat').  Light tiles finish their rows here; heavy rows leave one partial
+// sum per chunk for k_certify_heavy.
+struct RowOut {
+    double ratio;
+    int viol;
+};
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_certify(int64_t n, const int32_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                    const double* __restrict__ s, double c_res, double c_thr,
-                                                    double epsp, const double* __restrict__ zh,
-                                                    const double* __restrict__ opd, T* r_out, double* part_max,
-                                                    long long* part_viol) {
-    __shared__ int s_pre[kWavesPerBlock][65];
-    __shared__ double s_acc[kWavesPerBlock][64];
+__device__ __forceinline__ RowOut certify_row(int64_t i, double sum, const double* __restrict__ s, double c_res,
+                                              double c_thr, double epsp, const double* __restrict__ zh,
+                                              const double* __restrict__ opd, T* r_out) {
+    double ri = (s[i] + c_res) - opd[i] * zh[i] + sum;
+    double ratio = fabs(ri) / (epsp * (s[i] + c_thr));
+    RowOut o{ratio, !(ratio <= 1.0) ? 1 : 0};  // NaN counts as a violation
+    if (!isfinite(o.ratio)) o.ratio = INFINITY;
+    if (r_out) r_out[i] = static_cast<T>(ri);
+    return o;
+}
+
+__device__ __forceinline__ void block_max_count(double mx, int vc, double* part_max, long long* part_viol,
+                                                int slot) {
     __shared__ double s_mx[kWavesPerBlock];
     __shared__ long long s_vi[kWavesPerBlock];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64;
-    const int nrows = static_cast<int>(row0 < n ? (n - row0 < 64 ? n - row0 : 64) : 0);
-    double sum = tile_row_sums(row_ptr, row0, nrows, s_pre[wid], s_acc[wid], [&](int k) {
-        double a = w ? static_cast<double>(w[k]) : 1.0;
-        return a * zh[col[k]];
-    });
-    double ratio = 0.0;
-    int viol = 0;
-    if (lane < nrows) {
-        int64_t i = row0 + lane;
-        double ri = (s[i] + c_res) - opd[i] * zh[i] + sum;
-        ratio = fabs(ri) / (epsp * (s[i] + c_thr));
-        if (!(ratio <= 1.0)) viol = 1;  // NaN counts as a violation
-        if (!isfinite(ratio)) ratio = INFINITY;
-        if (r_out) r_out[i] = static_cast<T>(ri);
-    }
-    double mx = wave_max(ratio);
-    long long vc = __popcll(__ballot(viol));
-    if (lane == 0) { s_mx[wid] = mx; s_vi[wid] = vc; }
+    const int wid = threadIdx.x >> 6;
+    mx = wave_max(mx);
+    long long v = __popcll(__ballot(vc != 0));
+    if (lane_id() == 0) { s_mx[wid] = mx; s_vi[wid] = v; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0; long long v = 0;
-        for (int k = 0; k < kWavesPerBlock; ++k) { m = fmax(m, s_mx[k]); v += s_vi[k]; }
-        part_max[blockIdx.x] = m;
-        part_viol[blockIdx.x] = v;
+        double m = 0.0; long long c = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) { m = fmax(m, s_mx[k]); c += s_vi[k]; }
+        part_max[slot] = m;
+        part_viol[slot] = c;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_certify_tiles(TileView tv, const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const float* __restrict__ w, const double* __restrict__ s,
+                                                          double c_res, double c_thr, double epsp,
+                                                          const double* __restrict__ zh,
+                                                          const double* __restrict__ opd, T* r_out,
+                                                          double* partial, double* part_max, long long* part_viol) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    auto arc = [&](int k) {
+        double a = w ? static_cast<double>(w[k]) : 1.0;
+        return a * zh[col[k]];
+    };
+    RowOut ro{0.0, 0};
+    if (wv < tv.nchunks) {
+        int64_t cidx = tv.c0 + wv;
+        int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
+        int beg = tv.chunk_beg[cidx];
+        int end = min(beg + kArcBudget, row_ptr[row + 1]);
+        double sum = chunk_sum(beg, end, arc);
+        if (lane == 0) partial[cidx] = sum;
+    } else if (wv - tv.nchunks < tv.ntiles) {
+        int64_t tix = tv.t0 + (wv - tv.nchunks);
+        if (tv.tile_heavy[tix] < 0) {
+            int32_t r0 = tv.tile_start[tix];
+            int nrows = tv.tile_start[tix + 1] - r0;
+            double sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+            if (lane < nrows) ro = certify_row<T>(r0 + lane, sum, s, c_res, c_thr, epsp, zh, opd, r_out);
+        }
+    }
+    block_max_count(ro.ratio, ro.viol, part_max, part_viol, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_certify_heavy(TileView tv, const double* __restrict__ s, double c_res,
+                                                          double c_thr, double epsp, const double* __restrict__ zh,
+                                                          const double* __restrict__ opd, T* r_out,
+                                                          const double* __restrict__ partial, double* part_max,
+                                                          long long* part_viol, int slot0) {
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    RowOut ro{0.0, 0};
+    if (h < tv.h1) {
+        int32_t c0 = tv.heavy_chunk0[h], c1 = tv.heavy_chunk0[h + 1];
+        double sum = 0.0;
+        for (int32_t c = c0 + lane; c < c1; c += 64) sum += partial[c];
+        sum = wave_sum(sum);
+        if (lane == 0) ro = certify_row<T>(tv.heavy_row[h], sum, s, c_res, c_thr, epsp, zh, opd, r_out);
+    }
+    block_max_count(ro.ratio, ro.viol, part_max, part_viol, slot0 + blockIdx.x);
 }
 
 __global__ __launch_bounds__(1024) void k_certify_final(const double* part_max, const long long* part_viol, int64_t nb,
@@ -123,36 +176,63 @@ __global__ __launch_bounds__(1024) void k_certify_final(const double* part_max, 
 // Lemma 4 holds for any pushed amount, so concurrent pushes keep the invariant;
 // with omega = 1 the residual stays >= 0 from a cold start.
 //
-// Wave w owns nodes [64w, 64w+64).  Active nodes (|r_v| > h_v) take their
+// A wave owns one tile of CSR(A^T) rows.  Active nodes (|r_v| > h_v) take their
 // residual with an atomic exchange, add omega x / (1+d_v) to zhat'_v
 // (Eq. (sor1)), leave (1-omega) x at v (Eq. (sor2)), and scatter
 // a_uv omega x / (1+d_v) to every u in row v of CSR(A^T) (Eq. (sor3)) with
 // hardware float atomics.  The arcs of the active nodes are compacted with a
 // ballot + mbcnt prefix into LDS and streamed 64 at a time (merge-path split).
+// A heavy node only takes its residual here and publishes the scatter
+// coefficient; k_push_heavy scatters its arcs in chunks after this launch.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_push_round(int64_t n, const int32_t* __restrict__ t_row_ptr,
+__device__ __forceinline__ T take_residual(int64_t v, T* r, const T* __restrict__ inv,
+                                           const double* __restrict__ inv64, double* zh, double omega) {
+    T x = atomic_exch(&r[v], static_cast<T>(0));
+    if (omega != 1.0) atomic_add_noret(&r[v], static_cast<T>((1.0 - omega) * static_cast<double>(x)));
+    zh[v] += omega * static_cast<double>(x) * inv64[v];
+    return static_cast<T>(omega) * x * inv[v];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push_light(TileView tv, const int32_t* __restrict__ t_row_ptr,
                                                        const int32_t* __restrict__ t_col,
                                                        const float* __restrict__ t_w, T* r, const T* __restrict__ h,
                                                        const T* __restrict__ inv, const double* __restrict__ inv64,
-                                                       double* zh, double omega, const int* __restrict__ prev_active,
-                                                       int* this_active, unsigned long long* stats) {
+                                                       double* zh, double omega, T* heavy_coef,
+                                                       const int* __restrict__ prev_active, int* this_active,
+                                                       unsigned long long* stats) {
     __shared__ int s_beg[kWavesPerBlock][64];
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ T s_cf[kWavesPerBlock][64];
     if (__atomic_load_n(prev_active, __ATOMIC_RELAXED) == 0) return;  // previous round changed nothing
     const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t v = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64 + lane;
+    const int64_t tix = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (tix >= tv.ntiles) return;
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    const int32_t hv = tv.tile_heavy[tix];
+    if (hv >= 0) {  // one heavy node: take and publish; the arcs go to k_push_heavy
+        if (lane == 0) {
+            T cf = 0;
+            if (fabs(r[r0]) > h[r0]) {
+                cf = take_residual<T>(r0, r, inv, inv64, zh, omega);
+                flag_set(this_active);
+                stripe_add(stats, 0, 1ull);
+                stripe_add(stats, 1, static_cast<unsigned long long>(t_row_ptr[r0 + 1] - t_row_ptr[r0]));
+            }
+            heavy_coef[hv] = cf;
+        }
+        return;
+    }
+    const int64_t v = r0 + lane;
     bool act = false;
-    if (v < n) act = fabs(r[v]) > h[v];
+    if (lane < nrows) act = fabs(r[v]) > h[v];
     const uint64_t m = __ballot(act);
     if (m == 0) return;
     int beg = 0, deg = 0;
     T cf = 0;
     if (act) {
-        T x = atomic_exch(&r[v], static_cast<T>(0));
-        if (omega != 1.0) atomic_add_noret(&r[v], static_cast<T>((1.0 - omega) * static_cast<double>(x)));
-        zh[v] += omega * static_cast<double>(x) * inv64[v];
-        cf = static_cast<T>(omega) * x * inv[v];
+        cf = take_residual<T>(v, r, inv, inv64, zh, omega);
         beg = t_row_ptr[v];
         deg = t_row_ptr[v + 1] - beg;
     }
@@ -180,13 +260,38 @@ __global__ __launch_bounds__(kBlock) void k_push_round(int64_t n, const int32_t*
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push_heavy(TileView tv, const int32_t* __restrict__ t_row_ptr,
+                                                       const int32_t* __restrict__ t_col,
+                                                       const float* __restrict__ t_w, T* r,
+                                                       const T* __restrict__ heavy_coef,
+                                                       const int* __restrict__ prev_active) {
+    if (__atomic_load_n(prev_active, __ATOMIC_RELAXED) == 0) return;
+    const int wid = threadIdx.x >> 6;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (c >= tv.nchunks) return;
+    const int32_t hv = tv.chunk_heavy[c];
+    const T cf = heavy_coef[hv];
+    if (cf == static_cast<T>(0)) return;
+    const int32_t row = tv.heavy_row[hv];
+    const int beg = tv.chunk_beg[c];
+    const int end = min(beg + kArcBudget, t_row_ptr[row + 1]);
+    for (int k = beg + lane_id(); k < end; k += 64) {
+        int u = t_col[k];
+        T a = t_w ? static_cast<T>(t_w[k]) : static_cast<T>(1);
+        atomic_add_noret(&r[u], a * cf);
+    }
+}
+
 // ---------------------------------------------------------- colour-ordered SOR
-// Relabelled graph: colour class k occupies rows [class_off[k], class_off[k+1]).
-// Rows of one class are not adjacent in A + A^T, so updating them together is
-// exactly the sequential Gauss-Seidel update of each (Thm. 8), over-relaxed by
-// omega (Eq. (sor1)).  Pull form: r_i = s'_i - (1+d_i) zhat'_i + sum_j a_ij zhat'_j
+// Relabelled graph: colour class k occupies a contiguous row range.  Rows of
+// one class are not adjacent in A + A^T, so updating them together is exactly
+// the sequential Gauss-Seidel update of each (Thm. 8), over-relaxed by omega
+// (Eq. (sor1)).  Pull form: r_i = s'_i - (1+d_i) zhat'_i + sum_j a_ij zhat'_j
 // is recomputed from the current estimate (equal to the tracked residual by
-// Lemma 4), and row i is updated iff |r_i| > h_i = eps' s'_i (Alg. 3's test).
+// Lemma 4), and row i is updated iff |r_i| > h_i = eps' s'_i (Alg. 3's test;
+// a margin of 1e-6 h keeps a quiet sweep certified under the FP64 rounding of
+// the standalone certificate, which sums in a different order).
 __global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ s,
                            const double* __restrict__ z0, double c, double* sp, double* zh, int* bad) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -204,42 +309,184 @@ __global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const do
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sor_class(int64_t row_begin, int64_t row_end,
-                                                      const int32_t* __restrict__ prow_ptr,
+__device__ __forceinline__ bool sor_row(int64_t i, double sum, const double* __restrict__ sp,
+                                        const double* __restrict__ popd, const double* __restrict__ pinv, double* zh,
+                                        double omega, double epsp, bool* nonfinite) {
+    double z = zh[i];
+    double ri = sp[i] - popd[i] * z + sum;
+    *nonfinite = !isfinite(ri);
+    if (fabs(ri) > epsp * sp[i] * (1.0 - 1e-6)) {
+        zh[i] = z + omega * ri * pinv[i];
+        return true;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
                                                       const double* __restrict__ sp, const double* __restrict__ popd,
                                                       const double* __restrict__ pinv, double* zh, double omega,
-                                                      double epsp, int* updated, int* bad,
+                                                      double epsp, double* partial, int* updated, int* bad,
                                                       unsigned long long* stats) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
     const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row0 = row_begin + (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64;
-    const int nrows = static_cast<int>(row0 < row_end ? (row_end - row0 < 64 ? row_end - row0 : 64) : 0);
-    if (nrows <= 0) return;
-    double sum = tile_row_sums(prow_ptr, row0, nrows, s_pre[wid], s_acc[wid], [&](int k) {
+    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    auto arc = [&](int k) {
         double a = pw ? static_cast<double>(pw[k]) : 1.0;
         return a * zh[pcol[k]];
-    });
-    bool upd = false, nonfinite = false;
-    if (lane < nrows) {
-        int64_t i = row0 + lane;
-        double z = zh[i];
-        double ri = sp[i] - popd[i] * z + sum;
-        // a margin of 1e-6 h keeps a quiet sweep certified under the FP64 rounding
-        // of the standalone certificate (different summation order)
-        if (fabs(ri) > epsp * sp[i] * (1.0 - 1e-6)) {
-            zh[i] = z + omega * ri * pinv[i];
-            upd = true;
-        }
-        nonfinite = !isfinite(ri);
+    };
+    if (wv < tv.nchunks) {
+        int64_t cidx = tv.c0 + wv;
+        int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
+        int beg = tv.chunk_beg[cidx];
+        int end = min(beg + kArcBudget, prow_ptr[row + 1]);
+        double sum = chunk_sum(beg, end, arc);
+        if (lane == 0) partial[cidx] = sum;
+        return;
     }
+    wv -= tv.nchunks;
+    if (wv >= tv.ntiles) return;
+    const int64_t tix = tv.t0 + wv;
+    if (tv.tile_heavy[tix] >= 0) return;  // finished by k_sor_heavy
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+    bool upd = false, nonfinite = false;
+    if (lane < nrows) upd = sor_row(r0 + lane, sum, sp, popd, pinv, zh, omega, epsp, &nonfinite);
     uint64_t um = __ballot(upd);
     if (__ballot(nonfinite) && lane == 0) flag_set(bad);
     if (um && lane == 0) {
         flag_set(updated);
         stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, const double* __restrict__ sp,
+                                                      const double* __restrict__ popd,
+                                                      const double* __restrict__ pinv, double* zh, double omega,
+                                                      double epsp, const double* __restrict__ partial, int* updated,
+                                                      int* bad, unsigned long long* stats) {
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (hh >= tv.h1) return;
+    int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
+    double sum = 0.0;
+    for (int32_t c = c0 + lane; c < c1; c += 64) sum += partial[c];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+        bool nonfinite = false;
+        bool upd = sor_row(tv.heavy_row[hh], sum, sp, popd, pinv, zh, omega, epsp, &nonfinite);
+        if (nonfinite) flag_set(bad);
+        if (upd) {
+            flag_set(updated);
+            stripe_add(stats, 0, 1ull);
+        }
+    }
+}
+
+// Persistent form of the colour-ordered sweep: one cooperative launch runs up
+// to max_sweeps sweeps.  Colour classes are separated by grid barriers (the
+// in-kernel equivalent of the per-class launches above).  Rows longer than
+// kBigRow are reduced by a whole block, other heavy rows by one wave, light
+// tiles by one wave, so no partial sums cross a barrier.  The launch stops
+// after the first sweep that updated nothing (all blocks read the same
+// per-sweep flag after the sweep's last barrier).
+constexpr int kPBlock = 512;
+constexpr int kPWaves = kPBlock / 64;
+
+struct SorArgs {
+    const int32_t* tile_start;
+    const int32_t* tile_heavy;
+    const int32_t* heavy_row;
+    const int64_t* seg_tile;
+    const int64_t* seg_heavy;
+    int ncls;
+    const int32_t* prow_ptr;
+    const int32_t* pcol;
+    const float* pw;
+    const double* sp;
+    const double* popd;
+    const double* pinv;
+    double* zh;
+    double omega, epsp;
+    int max_sweeps;
+    int* flags;
+    int* bad;
+    unsigned long long* stats;
+    GridSync gs;
+};
+
+__global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
+    __shared__ int s_pre[kPWaves][65];
+    __shared__ double s_acc[kPWaves][64];
+    __shared__ double s_red[kPWaves];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t gw = static_cast<int64_t>(blockIdx.x) * kPWaves + wid;
+    const int64_t G = static_cast<int64_t>(gridDim.x) * kPWaves;
+    unsigned epoch = 0;
+    unsigned long long my_upd = 0;
+    auto arc = [&](int k) {
+        double w = a.pw ? static_cast<double>(a.pw[k]) : 1.0;
+        return w * a.zh[a.pcol[k]];
+    };
+    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+        int* upd = a.flags + sw;
+        for (int k = 0; k < a.ncls; ++k) {
+            const int64_t h0 = a.seg_heavy[k], h1 = a.seg_heavy[k + 1];
+            for (int64_t hh = h0 + blockIdx.x; hh < h1; hh += gridDim.x) {
+                const int32_t row = a.heavy_row[hh];
+                const int b = a.prow_ptr[row], e = a.prow_ptr[row + 1];
+                if (e - b <= kBigRow) continue;  // uniform across the block
+                double sum = block_arc_sum(b, e, s_red, arc);
+                if (threadIdx.x == 0) {
+                    bool nf = false;
+                    if (sor_row(row, sum, a.sp, a.popd, a.pinv, a.zh, a.omega, a.epsp, &nf)) {
+                        flag_set(upd);
+                        ++my_upd;
+                    }
+                    if (nf) flag_set(a.bad);
+                }
+            }
+            const int64_t t0 = a.seg_tile[k], t1 = a.seg_tile[k + 1];
+            for (int64_t tix = t0 + gw; tix < t1; tix += G) {
+                const int32_t r0 = a.tile_start[tix];
+                if (a.tile_heavy[tix] >= 0) {
+                    const int b = a.prow_ptr[r0], e = a.prow_ptr[r0 + 1];
+                    if (e - b > kBigRow) continue;  // done by a block above
+                    double sum = chunk_sum(b, e, arc);
+                    if (lane == 0) {
+                        bool nf = false;
+                        if (sor_row(r0, sum, a.sp, a.popd, a.pinv, a.zh, a.omega, a.epsp, &nf)) {
+                            flag_set(upd);
+                            ++my_upd;
+                        }
+                        if (nf) flag_set(a.bad);
+                    }
+                } else {
+                    const int nrows = a.tile_start[tix + 1] - r0;
+                    double sum = tile_row_sums(a.prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+                    bool u = false, nf = false;
+                    if (lane < nrows) u = sor_row(r0 + lane, sum, a.sp, a.popd, a.pinv, a.zh, a.omega, a.epsp, &nf);
+                    const uint64_t um = __ballot(u);
+                    const uint64_t nm = __ballot(nf);
+                    if (lane == 0) {
+                        if (um) {
+                            flag_set(upd);
+                            my_upd += __popcll(um);
+                        }
+                        if (nm) flag_set(a.bad);
+                    }
+                }
+            }
+            if (!grid_barrier(a.gs, epoch)) {
+                if (lane == 0 && my_upd) stripe_add(a.stats, 0, my_upd);
+                return;
+            }
+        }
+        if (__hip_atomic_load(upd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+    }
+    if (lane == 0 && my_upd) stripe_add(a.stats, 0, my_upd);
 }
 
 __global__ void k_sor_unshift(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ zh, double c,
@@ -260,11 +507,17 @@ __global__ void k_unshift(int64_t n, const double* __restrict__ zh, double c, do
 struct SolveLayout {
     void* r; void* h; double* zh; double* zh2; double* sp;
     int* flags; int* one; int* bad; unsigned long long* stats;
+    double* partial; void* heavy_coef; unsigned* barrier; int* abort;
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
 };
 
-SolveLayout carve_solve(Carver& cv, int64_t n, int precision) {
+int64_t cert_parts(const fj_graph* g) {
+    return waves_to_blocks(g->tiles_a.nchunks + g->tiles_a.ntiles) + waves_to_blocks(g->tiles_a.nheavy) + 2;
+}
+
+SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     SolveLayout L{};
+    const int64_t n = g->n;
     size_t tsz = precision == FJ_FP64 ? sizeof(double) : sizeof(float);
     L.r = cv.take<char>(tsz * n);
     L.h = cv.take<char>(tsz * n);
@@ -274,8 +527,13 @@ SolveLayout carve_solve(Carver& cv, int64_t n, int precision) {
     L.flags = cv.take<int>(kMaxRounds);
     L.one = cv.take<int>(1);
     L.bad = cv.take<int>(1);
+    L.barrier = cv.take<unsigned>(1);
+    L.abort = cv.take<int>(1);
     L.stats = cv.take<unsigned long long>(kStripes * kStripeStride);
-    int64_t nb = tile_blocks(n) + 1;
+    int64_t nch = std::max(g->tiles_a.nchunks, g->tiles_p.nchunks) + 1;
+    L.partial = cv.take<double>(nch);
+    L.heavy_coef = cv.take<char>(tsz * (g->tiles_t.nheavy + 1));
+    int64_t nb = cert_parts(g);
     L.part_max = cv.take<double>(nb);
     L.part_viol = cv.take<long long>(nb);
     L.cert_max = cv.take<double>(1);
@@ -283,7 +541,7 @@ SolveLayout carve_solve(Carver& cv, int64_t n, int precision) {
     return L;
 }
 
-// Optional per-launch timing of the iteration kernel with HIP events.
+// Optional per-launch timing of the iteration kernels with HIP events.
 struct LaunchTimer {
     bool on = false;
     hipStream_t st = nullptr;
@@ -339,12 +597,17 @@ template <typename T>
 fj_status certify(const fj_graph* g, const double* s, double c_res, double c_thr, double epsp, const double* zh,
                   T* r_out, const SolveLayout& L, hipStream_t st, double* max_ratio, long long* viol) {
     const int64_t n = g->n;
-    unsigned nb = tile_blocks(n);
     if (n > 0) {
-        hipLaunchKernelGGL(k_certify<T>, dim3(nb), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w, s, c_res, c_thr,
-                           epsp, zh, g->opd, r_out, L.part_max, L.part_viol);
+        TileView tv = tile_view_all(g->tiles_a);
+        unsigned nb1 = waves_to_blocks(tv.nchunks + tv.ntiles);
+        unsigned nb2 = waves_to_blocks(tv.h1 - tv.h0);
+        hipLaunchKernelGGL(k_certify_tiles<T>, dim3(nb1), dim3(kBlock), 0, st, tv, g->row_ptr, g->col, g->w, s, c_res,
+                           c_thr, epsp, zh, g->opd, r_out, L.partial, L.part_max, L.part_viol);
+        if (nb2 > 0)
+            hipLaunchKernelGGL(k_certify_heavy<T>, dim3(nb2), dim3(kBlock), 0, st, tv, s, c_res, c_thr, epsp, zh,
+                               g->opd, r_out, L.partial, L.part_max, L.part_viol, static_cast<int>(nb1));
         hipLaunchKernelGGL(k_certify_final, dim3(1), dim3(1024), 0, st, L.part_max, L.part_viol,
-                           static_cast<int64_t>(nb), L.cert_max, L.cert_viol);
+                           static_cast<int64_t>(nb1 + nb2), L.cert_max, L.cert_viol);
     } else {
         FJ_HIP(hipMemsetAsync(L.cert_max, 0, sizeof(double), st));
         FJ_HIP(hipMemsetAsync(L.cert_viol, 0, sizeof(long long), st));
@@ -361,15 +624,20 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
     const int64_t n = g->n;
     T* r = static_cast<T*>(L.r);
     T* h = static_cast<T*>(L.h);
+    T* coef = static_cast<T*>(L.heavy_coef);
     const T* inv = sizeof(T) == 4 ? reinterpret_cast<const T*>(g->inv32) : reinterpret_cast<const T*>(g->inv64);
     const int bs = 256;
-    if (o->z0) {
-        hipLaunchKernelGGL(k_init_warm<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->z0, o->c, epsp, h, L.zh, L.bad);
-        double mr; long long vi;
-        fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &mr, &vi);
-        if (rc) return rc;
-    } else {
-        hipLaunchKernelGGL(k_init_cold<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->c, epsp, r, h, L.zh, L.bad);
+    if (n > 0) {
+        if (o->z0) {
+            hipLaunchKernelGGL(k_init_warm<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->z0, o->c, epsp, h, L.zh,
+                               L.bad);
+            double mr; long long vi;
+            fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &mr, &vi);
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL(k_init_cold<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->c, epsp, r, h, L.zh,
+                               L.bad);
+        }
     }
     int hbad = 0;
     FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -380,7 +648,9 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
     }
     const int K = o->check_every > 0 ? o->check_every : 8;
     const int max_ref = o->max_refinements >= 0 ? o->max_refinements : 8;
-    const unsigned nb = tile_blocks(n);
+    const TileView tv = tile_view_all(g->tiles_t);
+    const unsigned nb_light = waves_to_blocks(tv.ntiles);
+    const unsigned nb_heavy = waves_to_blocks(tv.nchunks);
     int64_t rounds = 0, launches = 0;
     int refinements = 0;
     bool converged = false, capped = false;
@@ -402,13 +672,19 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
                 if (n > 0) {
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
-                    hipLaunchKernelGGL(k_push_round<T>, dim3(nb), dim3(kBlock), 0, st, n, g->t_row_ptr, g->t_col,
-                                       g->t_w, r, h, inv, g->inv64, L.zh, o->omega, prev, cur, L.stats);
+                    hipLaunchKernelGGL(k_push_light<T>, dim3(nb_light), dim3(kBlock), 0, st, tv, g->t_row_ptr,
+                                       g->t_col, g->t_w, r, h, inv, g->inv64, L.zh, o->omega, coef, prev, cur,
+                                       L.stats);
+                    ++launches;
+                    if (nb_heavy > 0) {
+                        hipLaunchKernelGGL(k_push_heavy<T>, dim3(nb_heavy), dim3(kBlock), 0, st, tv, g->t_row_ptr,
+                                           g->t_col, g->t_w, r, coef, prev);
+                        ++launches;
+                    }
                     rc0 = timer.after();
                     if (rc0) return rc0;
                 }
                 prev = cur;
-                ++launches;
             }
             FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + rounds, sizeof(int) * K, hipMemcpyDeviceToHost, st));
             fj_status rc = read_stats(L, st, &hs);
@@ -471,6 +747,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     const int K = o->check_every > 0 ? o->check_every : 8;
     const int max_ref = o->max_refinements >= 0 ? o->max_refinements : 8;
     const int nc = g->num_colours;
+    std::vector<TileView> views(nc);
+    for (int k = 0; k < nc; ++k) views[k] = tile_view(g->tiles_p, k);
     int64_t sweeps = 0, launches = 0;
     int refinements = 0;
     bool converged = false, capped = false, diverged = false;
@@ -479,24 +757,96 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     LaunchTimer timer;
     timer.on = o->profile != 0;
     timer.st = st;
+    // persistent cooperative launch when the device allows it
+    int coop_grid = 0;
+    if (n > 0 && o->persistent) {
+        int dev = 0, coop = 0, cus = 0, occ = 0;
+        FJ_HIP(hipGetDevice(&dev));
+        FJ_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        FJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        FJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sor_persistent, kPBlock, 0));
+        if (coop && cus > 0 && occ > 0) coop_grid = cus * occ;
+    }
+    SorArgs sa{};
+    sa.tile_start = g->tiles_p.tile_start;
+    sa.tile_heavy = g->tiles_p.tile_heavy;
+    sa.heavy_row = g->tiles_p.heavy_row;
+    sa.seg_tile = g->tiles_p.d_seg_tile;
+    sa.seg_heavy = g->tiles_p.d_seg_heavy;
+    sa.ncls = nc;
+    sa.prow_ptr = g->prow_ptr;
+    sa.pcol = g->pcol;
+    sa.pw = g->pw;
+    sa.sp = L.sp;
+    sa.popd = g->popd;
+    sa.pinv = g->pinv64;
+    sa.zh = L.zh;
+    sa.omega = o->omega;
+    sa.epsp = epsp;
+    sa.bad = L.bad;
+    sa.stats = L.stats;
+    sa.gs.counter = L.barrier;
+    sa.gs.abort = L.abort;
+    const int KP = std::max(K, 32);
+    std::vector<int> hfp(KP);
     while (true) {
         bool quiet = false;
+        while (!quiet && coop_grid > 0) {
+            if (sweeps + KP > kMaxRounds || (sweeps + KP) * (g->nnz + n) > cap) break;
+            FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * KP, st));
+            FJ_HIP(hipMemsetAsync(L.barrier, 0, sizeof(unsigned), st));
+            FJ_HIP(hipMemsetAsync(L.abort, 0, sizeof(int), st));
+            sa.max_sweeps = KP;
+            sa.flags = L.flags + sweeps;
+            void* args[] = {&sa};
+            fj_status rc0 = timer.before();
+            if (rc0) return rc0;
+            FJ_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sor_persistent), dim3(coop_grid),
+                                              dim3(kPBlock), args, 0, st));
+            rc0 = timer.after();
+            if (rc0) return rc0;
+            ++launches;
+            int habort = 0;
+            FJ_HIP(hipMemcpyAsync(hfp.data(), L.flags + sweeps, sizeof(int) * KP, hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipMemcpyAsync(&habort, L.abort, sizeof(int), hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipStreamSynchronize(st));
+            if (hbad) { diverged = true; break; }
+            int used = KP;
+            for (int b = 0; b < KP; ++b)
+                if (hfp[b] == 0) { used = b + 1; quiet = true; break; }
+            if (habort) {  // a barrier timed out: continue with per-class launches
+                coop_grid = 0;
+                quiet = false;
+                used = KP;
+                for (int b = 0; b < KP; ++b)
+                    if (hfp[b] == 0) { used = b; break; }
+            }
+            sweeps += used;
+        }
+        if (diverged) break;
         while (!quiet) {
             if (sweeps + K > kMaxRounds || (sweeps + K) * (g->nnz + n) > cap) { capped = true; break; }
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * K, st));
             for (int b = 0; b < K; ++b) {
                 int* cur = L.flags + sweeps + b;
                 for (int k = 0; k < nc; ++k) {
-                    int64_t rb = g->class_off[k], re = g->class_off[k + 1];
-                    if (re <= rb) continue;
+                    const TileView& tv = views[k];
+                    if (tv.ntiles == 0) continue;
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
-                    hipLaunchKernelGGL(k_sor_class, dim3(tile_blocks(re - rb)), dim3(kBlock), 0, st, rb, re,
-                                       g->prow_ptr, g->pcol, g->pw, L.sp, g->popd, g->pinv64, L.zh, o->omega, epsp,
-                                       cur, L.bad, L.stats);
+                    hipLaunchKernelGGL(k_sor_tiles, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0,
+                                       st, tv, g->prow_ptr, g->pcol, g->pw, L.sp, g->popd, g->pinv64, L.zh, o->omega,
+                                       epsp, L.partial, cur, L.bad, L.stats);
+                    ++launches;
+                    if (tv.h1 > tv.h0) {
+                        hipLaunchKernelGGL(k_sor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st,
+                                           tv, L.sp, g->popd, g->pinv64, L.zh, o->omega, epsp, L.partial, cur, L.bad,
+                                           L.stats);
+                        ++launches;
+                    }
                     rc0 = timer.after();
                     if (rc0) return rc0;
-                    ++launches;
                 }
             }
             FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
@@ -548,11 +898,12 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
 }
 
 struct CertLayout {
-    double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
+    double* partial; double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
 };
-CertLayout carve_cert(Carver& cv, int64_t n) {
+CertLayout carve_cert(Carver& cv, const fj_graph* g) {
     CertLayout L{};
-    int64_t nb = tile_blocks(n) + 1;
+    int64_t nb = cert_parts(g);
+    L.partial = cv.take<double>(g->tiles_a.nchunks + 1);
     L.part_max = cv.take<double>(nb);
     L.part_viol = cv.take<long long>(nb);
     L.cert_max = cv.take<double>(1);
@@ -562,9 +913,9 @@ CertLayout carve_cert(Carver& cv, int64_t n) {
 
 }  // namespace
 
-size_t certify_ws_bytes(int64_t n) {
+size_t certify_ws_bytes(const fj_graph* g) {
     Carver cv(nullptr);
-    carve_cert(cv, n);
+    carve_cert(cv, g);
     return cv.bytes();
 }
 
@@ -582,13 +933,14 @@ extern "C" fj_status fj_certify(const fj_graph* g, const double* s, const double
         set_error("fj_certify: need eps in (0,1), c >= 0, sigma > 0");
         return FJ_ERR_INVALID_ARGUMENT;
     }
-    if (ws_bytes < certify_ws_bytes(g->n)) {
+    if (ws_bytes < certify_ws_bytes(g)) {
         set_error("fj_certify: workspace too small");
         return FJ_ERR_WORKSPACE_TOO_SMALL;
     }
     Carver cv(ws);
-    CertLayout C = carve_cert(cv, g->n);
+    CertLayout C = carve_cert(cv, g);
     SolveLayout L{};
+    L.partial = C.partial;
     L.part_max = C.part_max;
     L.part_viol = C.part_viol;
     L.cert_max = C.cert_max;
@@ -604,7 +956,7 @@ extern "C" fj_status fj_certify(const fj_graph* g, const double* s, const double
 extern "C" size_t fj_solve_workspace_bytes(const fj_graph* g, const fj_solve_opts* opts) {
     if (!g || !opts) return 0;
     Carver cv(nullptr);
-    carve_solve(cv, g->n, opts->precision);
+    carve_solve(cv, g, opts->precision);
     return cv.bytes();
 }
 
@@ -639,7 +991,7 @@ extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve
         return FJ_ERR_INVALID_ARGUMENT;
     }
     Carver cv(ws);
-    SolveLayout L = carve_solve(cv, g->n, o->precision);
+    SolveLayout L = carve_solve(cv, g, o->precision);
     if (cv.bytes() > ws_bytes) {
         set_error("fj_solve: workspace too small: need " + std::to_string(cv.bytes()) + " bytes");
         return FJ_ERR_WORKSPACE_TOO_SMALL;

@@ -35,14 +35,7 @@ __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_
     if (lane < nrows) pre[lane] = rb - base;
     acc[lane] = 0.0;
     wave_sync_lds();
-    for (int e0 = 0; e0 < total; e0 += 64) {
-        const int e = e0 + lane;
-        int key = 64 + lane;
-        double v = 0.0;
-        if (e < total) {
-            key = tile_find(pre, nrows, e);
-            v = f(base + e);
-        }
+    auto reduce_chunk = [&](int key, double v) {
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             double y = __shfl_up(v, o, 64);
@@ -52,8 +45,63 @@ __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_
         int knext = __shfl_down(key, 1, 64);
         if ((lane == 63 || knext != key) && key < 64) acc[key] += v;
         wave_sync_lds();
+    };
+    // four 64-arc chunks per step: their loads are in flight together
+    for (int e0 = 0; e0 < total; e0 += 256) {
+        int key[4];
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = e0 + 64 * j + lane;
+            key[j] = 64 + lane;
+            v[j] = 0.0;
+            if (e < total) {
+                key[j] = tile_find(pre, nrows, e);
+                v[j] = f(base + e);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (e0 + 64 * j < total) reduce_chunk(key[j], v[j]);
     }
     return lane < nrows ? acc[lane] : 0.0;
+}
+
+// FP64 sum of f(k) over the arcs [beg, end) of one row chunk: lane-strided,
+// then a fixed butterfly, so identical run to run.  Result in every lane.
+template <typename F>
+__device__ __forceinline__ double chunk_sum(int beg, int end, F f) {
+    double acc = 0.0;
+    int k = beg + lane_id();
+    for (; k + 192 < end; k += 256) {  // four loads in flight per lane
+        double a0 = f(k), a1 = f(k + 64), a2 = f(k + 128), a3 = f(k + 192);
+        acc += a0; acc += a1; acc += a2; acc += a3;
+    }
+    for (; k < end; k += 64) acc += f(k);
+    return wave_sum(acc);
+}
+
+// FP64 sum of f(k) over arcs [beg, end) by a whole block, in a fixed order.
+// Every thread of the block must call it; the total is returned to all.
+template <typename F>
+__device__ __forceinline__ double block_arc_sum(int beg, int end, double* lds /*[blockDim/64]*/, F f) {
+    double acc = 0.0;
+    const int nt = blockDim.x;
+    int k = beg + static_cast<int>(threadIdx.x);
+    for (; k + 3 * nt < end; k += 4 * nt) {
+        double a0 = f(k), a1 = f(k + nt), a2 = f(k + 2 * nt), a3 = f(k + 3 * nt);
+        acc += a0; acc += a1; acc += a2; acc += a3;
+    }
+    for (; k < end; k += nt) acc += f(k);
+    acc = wave_sum(acc);
+    const int w = threadIdx.x >> 6, nw = nt >> 6;
+    __syncthreads();
+    if (lane_id() == 0) lds[w] = acc;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += lds[i];
+    __syncthreads();
+    return t;
 }
 
 // Same split without per-row sums: calls g(k, row_slot) for every CSR position

@@ -237,3 +237,23 @@ def test_work_cap_reports_not_converged():
             fj.solve(G, to_dev(s), eps=1e-6, schedule=sched, max_edge_visits=1000, check_every=1)
         assert e.value.stats["certified"] == 0
         assert np.all(np.isfinite(e.value.z.cpu().numpy()))
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_sor_persistent_and_per_class_launches_agree(directed):
+    """The persistent cooperative sweep and the one-launch-per-class sweep
+    visit the colour classes in the same order, so both reach the certificate
+    with the same number of sweeps and agree to rounding."""
+    fj = fjmod()
+    g = synth.chung_lu(60000, 600000, 2.2, 91 + directed, directed=directed, weighted=directed)
+    s = synth.opinions(g.n, "bimodal", 92)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    omega = 1.6 if not directed else 1.2
+    z1, st1 = fj.solve(G, sd, eps=1e-5, omega=omega, schedule="sor", persistent=True)
+    z2, st2 = fj.solve(G, sd, eps=1e-5, omega=omega, schedule="sor", persistent=False)
+    check_solution(g, s, z1, zt, 1e-5)
+    check_solution(g, s, z2, zt, 1e-5)
+    assert abs(st1["rounds"] - st2["rounds"]) <= 1
+    assert np.max(np.abs(z1.cpu().numpy() - z2.cpu().numpy())) <= 1e-9
