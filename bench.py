@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 WORKLOADS = {
     # name: (n, edge samples, gamma, directed, weighted, seed, opinion kind, eps, default omega)
     "cl10m": dict(n=10_000_000, m=100_000_000, gamma=2.3, directed=False, weighted=False, seed=3,
-                  s_kind="bimodal", eps=1e-4, omega=1.5,
+                  s_kind="bimodal", eps=1e-4, omega=1.6,
                   desc="undirected Chung-Lu n=10M, 100M edge samples (~200M stored arcs), gamma=2.3, "
                        "unit weights, s=0.5Beta(2,8)+0.5Beta(8,2)"),
     "cl1m_directed": dict(n=1_000_000, m=10_000_000, gamma=2.1, directed=True, weighted=True, seed=2,
@@ -63,8 +63,10 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted):
     RMW 8), +4 B with weights."""
     per_arc = 16 if weighted else 12
     if schedule == "sor":
+        # sweeps that gathered the 32-bit fixed-point copy move 4 B less per arc
         rows = stats["rounds"] * n
-        return 36 * rows + 8 * stats["pushes"] + per_arc * stats["edge_visits"]
+        mirror_arcs = stats.get("mirror_rounds", 0) * nnz
+        return 36 * rows + 12 * stats["pushes"] + per_arc * stats["edge_visits"] - 4 * mirror_arcs
     return 8 * stats["rounds"] * n + 44 * stats["pushes"] + per_arc * stats["edge_visits"]
 
 
@@ -109,6 +111,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--persistent", action="store_true",
                     help="SOR as one cooperative launch with grid barriers between colour classes")
     args = ap.parse_args()
@@ -170,10 +174,18 @@ def main():
         achieved = bytes_total / (stp["kernel_ms"] * 1e-3) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                        kernel="k_sor_class" if args.schedule == "sor" else "k_push_round",
+                        kernel="k_sor_tiles+k_sor_heavy" if args.schedule == "sor" else "k_push_light+k_push_heavy",
                         bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
                         launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))
         log(f"profiled step: {stp}")
+
+    if args.calib_copy:
+        # one elementwise kernel that reads 1 GiB and writes 1 GiB (4x the 256 MB Infinity Cache)
+        a = torch.empty(2**30 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        torch.cuda.synchronize()
+        b = a + 1.0
+        torch.cuda.synchronize()
+        log(f"calibration kernel: 1073741824 bytes read, 1073741824 bytes written ({float(b[0])})")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -144,6 +144,7 @@ typedef struct {
     double kernel_ms;     /* profile mode: summed event time of the iteration kernel launches */
     int64_t kernel_launches; /* profile mode: launches timed */
     int32_t num_colours;  /* colour classes swept (SOR), 0 for push */
+    int64_t mirror_rounds; /* SOR sweeps whose light rows gathered the 32-bit fixed-point copy */
 } fj_solve_stats;
 
 /* Bytes of solve workspace for this graph and options. */

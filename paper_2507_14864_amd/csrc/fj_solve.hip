@@ -292,56 +292,88 @@ __global__ __launch_bounds__(kBlock) void k_push_heavy(TileView tv, const int32_
 // Lemma 4), and row i is updated iff |r_i| > h_i = eps' s'_i (Alg. 3's test;
 // a margin of 1e-6 h keeps a quiet sweep certified under the FP64 rounding of
 // the standalone certificate, which sums in a different order).
+// 32-bit fixed-point copy of zhat' (scale 2^30, range (-2, 2)) used by the
+// light-row gathers while the sweeps are far from the certificate: half the
+// bytes of FP64 and an absolute resolution of 9.3e-10 (FP32 would give 6e-8
+// near 1).  The final sweeps and the certificate read FP64 only.
+constexpr double kFixScale = 1073741824.0;  // 2^30
+__device__ __forceinline__ int32_t fix_enc(double z) {
+    double q = rint(z * kFixScale);
+    q = fmin(fmax(q, -2147483647.0), 2147483647.0);
+    return static_cast<int32_t>(q);
+}
+__device__ __forceinline__ double fix_dec(int32_t q) { return static_cast<double>(q) * (1.0 / kFixScale); }
+
+struct SorState {
+    const double* sp;    // s' = s + c, relabelled
+    const double* popd;  // 1 + d
+    const double* pinv;  // 1 / (1 + d)
+    double* zh;          // zhat', FP64
+    int32_t* zq;         // fixed-point copy of zhat'
+    double omega;
+    double thr;          // update iff |r| > thr * eps' s'
+    double epsp;
+};
+
 __global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ s,
-                           const double* __restrict__ z0, double c, double* sp, double* zh, int* bad) {
+                           const double* __restrict__ z0, double c, double* sp, double* zh, int32_t* zq, int* bad) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t o = perm[i];
     double si = s[o];
     if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
     sp[i] = si + c;
+    double z = 0.0;
     if (z0) {
         double zi = z0[o];
         if (!isfinite(zi)) flag_set(bad);
-        zh[i] = zi + c;
-    } else {
-        zh[i] = 0.0;
+        z = zi + c;
     }
+    zh[i] = z;
+    zq[i] = fix_enc(z);
 }
 
-__device__ __forceinline__ bool sor_row(int64_t i, double sum, const double* __restrict__ sp,
-                                        const double* __restrict__ popd, const double* __restrict__ pinv, double* zh,
-                                        double omega, double epsp, bool* nonfinite) {
-    double z = zh[i];
-    double ri = sp[i] - popd[i] * z + sum;
+__device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S, bool* nonfinite) {
+    double z = S.zh[i];
+    double sp = __builtin_nontemporal_load(&S.sp[i]);
+    double ri = sp - __builtin_nontemporal_load(&S.popd[i]) * z + sum;
     *nonfinite = !isfinite(ri);
-    if (fabs(ri) > epsp * sp[i] * (1.0 - 1e-6)) {
-        zh[i] = z + omega * ri * pinv[i];
+    if (fabs(ri) > S.thr * S.epsp * sp) {
+        z += S.omega * ri * S.pinv[i];
+        S.zh[i] = z;
+        S.zq[i] = fix_enc(z);
         return true;
     }
     return false;
 }
 
+template <bool MIRROR>
 __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
-                                                      const double* __restrict__ sp, const double* __restrict__ popd,
-                                                      const double* __restrict__ pinv, double* zh, double omega,
-                                                      double epsp, double* partial, int* updated, int* bad,
+                                                      SorState S, double* partial, int* updated, int* bad,
                                                       unsigned long long* stats) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
     const int wid = threadIdx.x >> 6, lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    auto arc = [&](int k) {
-        double a = pw ? static_cast<double>(pw[k]) : 1.0;
-        return a * zh[pcol[k]];
+    const double* __restrict__ zh = S.zh;
+    const int32_t* __restrict__ zq = S.zq;
+    auto arc64 = [&](int k) {
+        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+        return a * zh[__builtin_nontemporal_load(&pcol[k])];
     };
-    if (wv < tv.nchunks) {
+    auto arc_light = [&](int k) {
+        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+        int j = __builtin_nontemporal_load(&pcol[k]);
+        if constexpr (MIRROR) return a * fix_dec(zq[j]);
+        else return a * zh[j];
+    };
+    if (wv < tv.nchunks) {  // heavy rows always gather FP64
         int64_t cidx = tv.c0 + wv;
         int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
         int beg = tv.chunk_beg[cidx];
         int end = min(beg + kArcBudget, prow_ptr[row + 1]);
-        double sum = chunk_sum(beg, end, arc);
+        double sum = chunk_sum(beg, end, arc64);
         if (lane == 0) partial[cidx] = sum;
         return;
     }
@@ -351,9 +383,9 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
     if (tv.tile_heavy[tix] >= 0) return;  // finished by k_sor_heavy
     const int32_t r0 = tv.tile_start[tix];
     const int nrows = tv.tile_start[tix + 1] - r0;
-    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc_light);
     bool upd = false, nonfinite = false;
-    if (lane < nrows) upd = sor_row(r0 + lane, sum, sp, popd, pinv, zh, omega, epsp, &nonfinite);
+    if (lane < nrows) upd = sor_row(r0 + lane, sum, S, &nonfinite);
     uint64_t um = __ballot(upd);
     if (__ballot(nonfinite) && lane == 0) flag_set(bad);
     if (um && lane == 0) {
@@ -362,11 +394,8 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, const double* __restrict__ sp,
-                                                      const double* __restrict__ popd,
-                                                      const double* __restrict__ pinv, double* zh, double omega,
-                                                      double epsp, const double* __restrict__ partial, int* updated,
-                                                      int* bad, unsigned long long* stats) {
+__global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, SorState S, const double* __restrict__ partial,
+                                                      int* updated, int* bad, unsigned long long* stats) {
     const int wid = threadIdx.x >> 6, lane = lane_id();
     int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
@@ -376,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, const double*
     sum = wave_sum(sum);
     if (lane == 0) {
         bool nonfinite = false;
-        bool upd = sor_row(tv.heavy_row[hh], sum, sp, popd, pinv, zh, omega, epsp, &nonfinite);
+        bool upd = sor_row(tv.heavy_row[hh], sum, S, &nonfinite);
         if (nonfinite) flag_set(bad);
         if (upd) {
             flag_set(updated);
@@ -405,11 +434,7 @@ struct SorArgs {
     const int32_t* prow_ptr;
     const int32_t* pcol;
     const float* pw;
-    const double* sp;
-    const double* popd;
-    const double* pinv;
-    double* zh;
-    double omega, epsp;
+    SorState S;
     int max_sweeps;
     int* flags;
     int* bad;
@@ -428,7 +453,7 @@ __global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
     unsigned long long my_upd = 0;
     auto arc = [&](int k) {
         double w = a.pw ? static_cast<double>(a.pw[k]) : 1.0;
-        return w * a.zh[a.pcol[k]];
+        return w * a.S.zh[a.pcol[k]];
     };
     for (int sw = 0; sw < a.max_sweeps; ++sw) {
         int* upd = a.flags + sw;
@@ -441,7 +466,7 @@ __global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
                 double sum = block_arc_sum(b, e, s_red, arc);
                 if (threadIdx.x == 0) {
                     bool nf = false;
-                    if (sor_row(row, sum, a.sp, a.popd, a.pinv, a.zh, a.omega, a.epsp, &nf)) {
+                    if (sor_row(row, sum, a.S, &nf)) {
                         flag_set(upd);
                         ++my_upd;
                     }
@@ -457,7 +482,7 @@ __global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
                     double sum = chunk_sum(b, e, arc);
                     if (lane == 0) {
                         bool nf = false;
-                        if (sor_row(r0, sum, a.sp, a.popd, a.pinv, a.zh, a.omega, a.epsp, &nf)) {
+                        if (sor_row(r0, sum, a.S, &nf)) {
                             flag_set(upd);
                             ++my_upd;
                         }
@@ -467,7 +492,7 @@ __global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
                     const int nrows = a.tile_start[tix + 1] - r0;
                     double sum = tile_row_sums(a.prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
                     bool u = false, nf = false;
-                    if (lane < nrows) u = sor_row(r0 + lane, sum, a.sp, a.popd, a.pinv, a.zh, a.omega, a.epsp, &nf);
+                    if (lane < nrows) u = sor_row(r0 + lane, sum, a.S, &nf);
                     const uint64_t um = __ballot(u);
                     const uint64_t nm = __ballot(nf);
                     if (lane == 0) {
@@ -505,7 +530,7 @@ __global__ void k_unshift(int64_t n, const double* __restrict__ zh, double c, do
 
 // --------------------------------------------------------------- workspace
 struct SolveLayout {
-    void* r; void* h; double* zh; double* zh2; double* sp;
+    void* r; void* h; double* zh; double* zh2; double* sp; int32_t* zq;
     int* flags; int* one; int* bad; unsigned long long* stats;
     double* partial; void* heavy_coef; unsigned* barrier; int* abort;
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
@@ -524,6 +549,7 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     L.zh = cv.take<double>(n);
     L.zh2 = cv.take<double>(n);
     L.sp = cv.take<double>(n);
+    L.zq = cv.take<int32_t>(n);
     L.flags = cv.take<int>(kMaxRounds);
     L.one = cv.take<int>(1);
     L.bad = cv.take<int>(1);
@@ -736,7 +762,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     const int bs = 256;
     if (n > 0)
         hipLaunchKernelGGL(k_sor_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, s, o->z0, o->c, L.sp, L.zh,
-                           L.bad);
+                           L.zq, L.bad);
     int hbad = 0;
     FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
@@ -749,7 +775,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     const int nc = g->num_colours;
     std::vector<TileView> views(nc);
     for (int k = 0; k < nc; ++k) views[k] = tile_view(g->tiles_p, k);
-    int64_t sweeps = 0, launches = 0;
+    int64_t sweeps = 0, launches = 0, mirror_sweeps = 0;
     int refinements = 0;
     bool converged = false, capped = false, diverged = false;
     double max_ratio = 0.0;
@@ -777,12 +803,16 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     sa.prow_ptr = g->prow_ptr;
     sa.pcol = g->pcol;
     sa.pw = g->pw;
-    sa.sp = L.sp;
-    sa.popd = g->popd;
-    sa.pinv = g->pinv64;
-    sa.zh = L.zh;
-    sa.omega = o->omega;
-    sa.epsp = epsp;
+    // FP64 sweeps: the margin of 1e-6 h keeps a quiet sweep certified under the
+    // FP64 rounding of the standalone certificate (different summation order).
+    SorState S64{L.sp, g->popd, g->pinv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp};
+    // Fixed-point sweeps: light rows gather the 32-bit copy, whose error per
+    // arc is <= 4.7e-10; a 5% margin on h makes it likely that the FP64
+    // certificate holds when these sweeps go quiet.  FP64 sweeps follow if not.
+    SorState SMIR = S64;
+    SMIR.thr = 0.95;
+    bool mirror = o->precision == FJ_FP32;
+    sa.S = S64;
     sa.bad = L.bad;
     sa.stats = L.stats;
     sa.gs.counter = L.barrier;
@@ -791,7 +821,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     std::vector<int> hfp(KP);
     while (true) {
         bool quiet = false;
-        while (!quiet && coop_grid > 0) {
+        while (!quiet && coop_grid > 0 && !mirror) {
             if (sweeps + KP > kMaxRounds || (sweeps + KP) * (g->nnz + n) > cap) break;
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * KP, st));
             FJ_HIP(hipMemsetAsync(L.barrier, 0, sizeof(unsigned), st));
@@ -835,14 +865,19 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                     if (tv.ntiles == 0) continue;
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
-                    hipLaunchKernelGGL(k_sor_tiles, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0,
-                                       st, tv, g->prow_ptr, g->pcol, g->pw, L.sp, g->popd, g->pinv64, L.zh, o->omega,
-                                       epsp, L.partial, cur, L.bad, L.stats);
+                    const SorState& S = mirror ? SMIR : S64;
+                    if (mirror)
+                        hipLaunchKernelGGL(k_sor_tiles<true>, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)),
+                                           dim3(kBlock), 0, st, tv, g->prow_ptr, g->pcol, g->pw, S, L.partial, cur,
+                                           L.bad, L.stats);
+                    else
+                        hipLaunchKernelGGL(k_sor_tiles<false>, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)),
+                                           dim3(kBlock), 0, st, tv, g->prow_ptr, g->pcol, g->pw, S, L.partial, cur,
+                                           L.bad, L.stats);
                     ++launches;
                     if (tv.h1 > tv.h0) {
                         hipLaunchKernelGGL(k_sor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st,
-                                           tv, L.sp, g->popd, g->pinv64, L.zh, o->omega, epsp, L.partial, cur, L.bad,
-                                           L.stats);
+                                           tv, S, L.partial, cur, L.bad, L.stats);
                         ++launches;
                     }
                     rc0 = timer.after();
@@ -857,6 +892,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
             for (int b = 0; b < K; ++b)
                 if (hf[b] == 0) { used = b + 1; quiet = true; break; }
             sweeps += used;
+            if (mirror) mirror_sweeps += used;
             if (n == 0) quiet = true;
         }
         if (capped || diverged) break;
@@ -866,6 +902,10 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
         fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L, st, &max_ratio, &viol);
         if (rc) return rc;
         if (viol == 0) { converged = true; break; }
+        if (mirror) {  // finish with FP64 gathers
+            mirror = false;
+            continue;
+        }
         if (refinements >= max_ref) break;
         ++refinements;
     }
@@ -881,6 +921,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     rc = timer.total_ms(&out->kernel_ms, &out->kernel_launches);
     if (rc) return rc;
     out->num_colours = nc;
+    out->mirror_rounds = mirror_sweeps;
     out->pushes = static_cast<int64_t>(hs.pushes);
     out->edge_visits = sweeps * g->nnz;
     out->rounds = sweeps;

@@ -61,7 +61,8 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("pushes", ctypes.c_int64), ("edge_visits", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("launches", ctypes.c_int64), ("refinements", ctypes.c_int32), ("certified", ctypes.c_int32),
                 ("max_ratio", ctypes.c_double), ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("kernel_launches", ctypes.c_int64), ("num_colours", ctypes.c_int32)]
+                ("kernel_launches", ctypes.c_int64), ("num_colours", ctypes.c_int32),
+                ("mirror_rounds", ctypes.c_int64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
