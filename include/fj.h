@@ -187,6 +187,62 @@ fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_met
 fj_status fj_certify(const fj_graph* g, const double* s, const double* z, double eps, double c,
                      double sigma, double* out_max_ratio, void* ws, size_t ws_bytes, void* stream);
 
+/* ----------------------------------------------------------- batched solve
+ * Many opinion vectors and many graphs solved by one enqueued sequence that
+ * never synchronizes the host (capture-safe), so a whole batch can run as one
+ * hipGraph launch.  Items with k = 1 are joined into one block-diagonal graph
+ * whose components stop sweeping once their own sweep is quiet; items with
+ * k > 1 keep their k vectors node-major ([n][k]) so every arc reads k
+ * estimates in one coalesced access.  The method per vector is the same
+ * colour-ordered ImprovedBLISOR as fj_solve (FP64 sweeps), with the same
+ * certificate (Lemma 7 with the shift of Alg. 2). */
+
+typedef struct fj_batch fj_batch;
+
+typedef struct {
+    fj_graph_desc graph; /* device CSR, same rules as fj_graph_create; must outlive the batch */
+    int32_t k;           /* opinion vectors on this graph, 1..64 */
+} fj_batch_item_desc;
+
+/* Bytes of batch workspace (graphs' ingest products, inputs, outputs, state). */
+size_t fj_batch_workspace_bytes(const fj_batch_item_desc* items, int32_t num_items);
+
+/* Validate and ingest every graph (as fj_graph_create with FJ_GRAPH_COLOUR).
+ * opts: eps, omega, c, sigma as for fj_solve (precision and schedule ignored:
+ * FP64 colour-ordered sweeps); max_refinements unused; check_every unused.
+ * The sweep budget starts at 256 and is reset by fj_batch_tune.  Synchronizes. */
+fj_status fj_batch_create(const fj_batch_item_desc* items, int32_t num_items, const fj_solve_opts* opts, void* ws,
+                          size_t ws_bytes, void* stream, fj_batch** out);
+fj_status fj_batch_destroy(fj_batch* b);
+
+/* Device pointers, inside the batch workspace, of item i's input s ([n][k]
+ * node-major, FP64) and output z (same layout).  The caller writes s there
+ * before fj_solve_batched; z is valid after it. [host] out. */
+fj_status fj_batch_io(const fj_batch* b, int32_t item, double** s, double** z);
+
+/* Autotuner (synchronizes): with the inputs currently in place, times the
+ * batched solve for each omega in omegas[0..n_omegas) (host-driven, with
+ * convergence feedback), keeps the fastest, sets the sweep budget to the
+ * sweeps it needed plus a margin, and records the launch sequence into a
+ * hipGraph that fj_solve_batched then replays.  [host] omegas. */
+fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_omegas, void* stream);
+
+typedef struct {
+    double omega;         /* chosen relaxation factor */
+    int32_t sweep_budget; /* sweeps recorded per solve */
+    int32_t graph_nodes;  /* kernel launches in the recorded hipGraph (0 if none) */
+    int32_t num_colours;  /* most colour classes over the items */
+    double tune_ms[16];   /* measured time per candidate omega */
+} fj_batch_info;
+fj_status fj_batch_get_info(const fj_batch* b, fj_batch_info* out);
+
+/* Solve every item.  Enqueues only (never synchronizes; uses no host memory):
+ * the recorded hipGraph if fj_batch_tune ran, else the kernels directly.
+ * stats_dev: device [num_items] or NULL; per item rounds = sweeps used,
+ * certified, max_ratio (over its k vectors); other fields 0.
+ * metrics_dev: device [sum of k] or NULL, item-major then vector. */
+fj_status fj_solve_batched(fj_batch* b, fj_solve_stats* stats_dev, fj_metrics_out* metrics_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,6 @@
 """Friedkin-Johnsen equilibrium z = (I+L)^{-1} s by residual push with
 over-relaxation (arXiv 2507.14864) on MI355X: a C-ABI HIP library (libfj.so,
 include/fj.h) and its Python binding."""
-from .fj import (FJError, FJNotConverged, Graph, certify, lib, metrics, solve)  # noqa: F401
+from .fj import (Batch, FJError, FJNotConverged, Graph, certify, lib, metrics, solve)  # noqa: F401
 
-__all__ = ["Graph", "solve", "metrics", "certify", "lib", "FJError", "FJNotConverged"]
+__all__ = ["Graph", "Batch", "solve", "metrics", "certify", "lib", "FJError", "FJNotConverged"]

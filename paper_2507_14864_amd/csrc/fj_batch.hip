@@ -1,0 +1,1076 @@
+// Batched solve: many graphs and many opinion vectors per graph in one
+// enqueued sequence with device-side convergence, recordable as a hipGraph.
+//
+// Every vector is solved by the same colour-ordered ImprovedBLISOR sweeps as
+// fj_solve (Alg. 2 around Alg. 3, Eqs. (sor1)-(sor3), Thm. 8), in FP64, and
+// judged by the same certificate (Lemma 7 with Alg. 2's shift).
+//  - Items with k = 1 are joined into one block-diagonal graph.  Its colour
+//    classes are the union of the components' classes, so one launch per
+//    class serves every component; a component whose last sweep updated
+//    nothing has final residuals (components do not interact) and is skipped.
+//  - Items with k > 1 keep their vectors node-major ([n][k]); a wave owns a
+//    row and lane l owns vector l, so every arc reads k estimates with one
+//    coalesced access.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fj_device.h"
+#include "fj_internal.h"
+#include "fj_sor.h"
+#include "fj_tile.h"
+
+namespace fj {
+namespace {
+
+inline unsigned g1d(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------ union build
+__global__ void k_item_rowptr_check(int64_t n, int64_t nnz, const int32_t* __restrict__ rp, int* err) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int32_t v = rp[i];
+    bool bad = v < 0 || v > nnz || (i == 0 && v != 0) || (i == n && v != nnz) || (i < n && rp[i + 1] < v);
+    if (bad) atomicOr(err, 1);
+}
+
+__global__ void k_union_copy(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const float* __restrict__ w, int64_t noff, int64_t aoff, int comp, int32_t* urp,
+                             int32_t* ucol, float* uw, int32_t* comp_of, int* err) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    urp[noff + i] = static_cast<int32_t>(aoff + rp[i]);
+    comp_of[noff + i] = comp;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        int32_t j = col[e];
+        if (j < 0 || j >= n) atomicOr(err, 2);  // must stay inside its own component
+        ucol[aoff + e] = static_cast<int32_t>(noff + j);
+        if (uw) uw[aoff + e] = w ? w[e] : 1.0f;
+    }
+}
+
+// symmetry of the undirected components (the union itself is declared directed)
+__global__ void k_union_symmetry(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                 const float* __restrict__ w, const int32_t* __restrict__ comp_of,
+                                 const int32_t* __restrict__ comp_dir, int* err) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n || comp_dir[comp_of[i]]) return;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        int j = col[k];
+        int64_t lo = rp[j], hi = rp[j + 1] - 1, found = -1;
+        while (lo <= hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int cc = col[mid];
+            if (cc == i) { found = mid; break; }
+            if (cc < i) lo = mid + 1; else hi = mid - 1;
+        }
+        if (found < 0 || (w && w[found] != w[k])) {
+            atomicOr(err, 4);
+            return;
+        }
+    }
+}
+
+__global__ void k_gather_i32(int64_t n, const int32_t* __restrict__ idx, const int32_t* __restrict__ src,
+                             int32_t* dst) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+// --------------------------------------------------------- flags per slot
+// slot = one component of the union or one multi-vector item
+__global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done, int* all_done, int* bad) {
+    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+        upd[s] = 0;
+        done[s] = 0;
+        sweeps_done[s] = 0;
+    }
+    if (threadIdx.x == 0) {
+        *all_done = 0;
+        *bad = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* upd, int* done, int* sweeps_done,
+                                                   int* all_done) {
+    __shared__ int s_open;
+    if (threadIdx.x == 0) s_open = 0;
+    __syncthreads();
+    if (*all_done) return;
+    int open = 0;
+    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+        if (!done[s]) {
+            if (!upd[s]) {
+                done[s] = 1;
+                sweeps_done[s] = sweep + 1;
+            } else {
+                open = 1;
+            }
+        }
+        upd[s] = 0;
+    }
+    if (open) s_open = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && !s_open) *all_done = 1;
+}
+
+// ------------------------------------------------- union sweep (k = 1)
+__global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
+                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
+                                                       SorState S, double* partial, const int32_t* __restrict__ pcomp,
+                                                       int* upd, const int* __restrict__ done,
+                                                       const int* __restrict__ all_done, int* bad) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    if (*all_done) return;
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    const double* __restrict__ zh = S.zh;
+    auto arc = [&](int k) {
+        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+        return a * zh[__builtin_nontemporal_load(&pcol[k])];
+    };
+    if (wv < tv.nchunks) {
+        int64_t cidx = tv.c0 + wv;
+        int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
+        if (done[pcomp[row]]) return;
+        int beg = tv.chunk_beg[cidx];
+        int end = min(beg + kArcBudget, prow_ptr[row + 1]);
+        double sum = chunk_sum(beg, end, arc);
+        if (lane == 0) partial[cidx] = sum;
+        return;
+    }
+    wv -= tv.nchunks;
+    if (wv >= tv.ntiles) return;
+    const int64_t tix = tv.t0 + wv;
+    if (tv.tile_heavy[tix] >= 0) return;
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    const int c0 = pcomp[r0], c1 = pcomp[r0 + nrows - 1];
+    if (c1 - c0 <= 1 && done[c0] && done[c1]) return;
+    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+    if (lane < nrows) {
+        const int c = pcomp[r0 + lane];
+        if (!done[c]) {
+            bool nf = false;
+            if (sor_row(r0 + lane, sum, S, &nf)) flag_set(&upd[c]);
+            if (nf) flag_set(bad);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_usor_heavy(TileView tv, SorState S, const double* __restrict__ partial,
+                                                       const int32_t* __restrict__ pcomp, int* upd,
+                                                       const int* __restrict__ done, const int* __restrict__ all_done,
+                                                       int* bad) {
+    if (*all_done) return;
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (hh >= tv.h1) return;
+    const int32_t row = tv.heavy_row[hh];
+    const int c = pcomp[row];
+    if (done[c]) return;
+    int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
+    double sum = 0.0;
+    for (int32_t q = c0 + lane; q < c1; q += 64) sum += partial[q];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+        bool nf = false;
+        if (sor_row(row, sum, S, &nf)) flag_set(&upd[c]);
+        if (nf) flag_set(bad);
+    }
+}
+
+// ------------------------------------------- multi-vector sweep (k > 1)
+struct MState {
+    const double* sp;    // [n][k] s' = s + c, relabelled rows
+    const double* popd;  // [n] 1 + d
+    const double* pinv;  // [n] 1 / (1 + d)
+    double* zh;          // [n][k]
+    double omega, thr, epsp;
+    int k;
+};
+
+// lane l < k: sum over arcs [beg, end) of a_e * zh[col_e][l]; four arcs in flight
+__device__ __forceinline__ double mrhs_arc_sum(int beg, int end, const int32_t* __restrict__ pcol,
+                                               const float* __restrict__ pw, const double* __restrict__ zh, int k,
+                                               int l) {
+    double acc = 0.0;
+    int e = beg;
+    for (; e + 3 < end; e += 4) {
+        int j0 = pcol[e], j1 = pcol[e + 1], j2 = pcol[e + 2], j3 = pcol[e + 3];
+        double a0 = pw ? pw[e] : 1.0, a1 = pw ? pw[e + 1] : 1.0, a2 = pw ? pw[e + 2] : 1.0, a3 = pw ? pw[e + 3] : 1.0;
+        double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+        if (l < k) {
+            v0 = zh[static_cast<int64_t>(j0) * k + l];
+            v1 = zh[static_cast<int64_t>(j1) * k + l];
+            v2 = zh[static_cast<int64_t>(j2) * k + l];
+            v3 = zh[static_cast<int64_t>(j3) * k + l];
+        }
+        acc += a0 * v0;
+        acc += a1 * v1;
+        acc += a2 * v2;
+        acc += a3 * v3;
+    }
+    for (; e < end; ++e) {
+        int j = pcol[e];
+        double a = pw ? pw[e] : 1.0;
+        if (l < k) acc += a * zh[static_cast<int64_t>(j) * k + l];
+    }
+    return acc;
+}
+
+__device__ __forceinline__ bool mrhs_row(int64_t i, int l, double sum, const MState& S, bool* nf) {
+    if (l >= S.k) return false;
+    const int64_t q = i * S.k + l;
+    double z = S.zh[q], sp = S.sp[q];
+    double r = sp - S.popd[i] * z + sum;
+    *nf = !isfinite(r);
+    if (fabs(r) > S.thr * S.epsp * sp) {
+        S.zh[q] = z + S.omega * r * S.pinv[i];
+        return true;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, int64_t re,
+                                                       const int32_t* __restrict__ prow_ptr,
+                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
+                                                       MState S, double* partial, int* upd,
+                                                       const int* __restrict__ done, const int* __restrict__ all_done,
+                                                       int* bad) {
+    if (*all_done || *done) return;
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (wv < tv.nchunks) {
+        const int64_t cidx = tv.c0 + wv;
+        const int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
+        const int beg = tv.chunk_beg[cidx];
+        const int end = min(beg + kArcBudget, prow_ptr[row + 1]);
+        double acc = mrhs_arc_sum(beg, end, pcol, pw, S.zh, S.k, lane);
+        if (lane < S.k) partial[cidx * S.k + lane] = acc;
+        return;
+    }
+    const int64_t i = rb + (wv - tv.nchunks);
+    if (i >= re) return;
+    const int b = prow_ptr[i], e = prow_ptr[i + 1];
+    if (e - b > kArcBudget) return;  // heavy: chunks + k_msor_heavy
+    double acc = mrhs_arc_sum(b, e, pcol, pw, S.zh, S.k, lane);
+    bool nf = false;
+    bool u = mrhs_row(i, lane, acc, S, &nf);
+    if (__ballot(u) && lane == 0) flag_set(upd);
+    if (__ballot(nf) && lane == 0) flag_set(bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_msor_heavy(TileView tv, MState S, const double* __restrict__ partial,
+                                                       int* upd, const int* __restrict__ done,
+                                                       const int* __restrict__ all_done, int* bad) {
+    if (*all_done || *done) return;
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (hh >= tv.h1) return;
+    const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
+    double sum = 0.0;
+    if (lane < S.k)
+        for (int32_t q = c0; q < c1; ++q) sum += partial[static_cast<int64_t>(q) * S.k + lane];
+    bool nf = false;
+    bool u = mrhs_row(tv.heavy_row[hh], lane, sum, S, &nf);
+    if (__ballot(u) && lane == 0) flag_set(upd);
+    if (__ballot(nf) && lane == 0) flag_set(bad);
+}
+
+__global__ void k_minit(int64_t n, int k, const int32_t* __restrict__ perm, const double* __restrict__ s, double c,
+                        double* sp, double* zh, int* bad) {
+    int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= n * k) return;
+    int64_t i = q / k;
+    int l = static_cast<int>(q - i * k);
+    double si = s[static_cast<int64_t>(perm[i]) * k + l];
+    if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
+    sp[q] = si + c;
+    zh[q] = 0.0;
+}
+
+__global__ void k_munshift(int64_t n, int k, const int32_t* __restrict__ perm, const double* __restrict__ zh,
+                           double c, double* z) {
+    int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= n * k) return;
+    int64_t i = q / k;
+    int l = static_cast<int>(q - i * k);
+    z[static_cast<int64_t>(perm[i]) * k + l] = zh[q] - c;
+}
+
+// --------------------------------------------- results: union (per row)
+// Per-row FP64 quantities over the union's CSR(A) in original labels, then
+// fixed-order reductions per component (one block each).
+//   mode 0: ratio_i = |s_i - ((I+L) z)_i| / (eps' (s_i + c))   (certificate)
+//   mode 1: d_i = sum_j a_ij (z_i - z_j)^2                      (disagreement)
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_urows_tiles(TileView tv, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                        const double* __restrict__ s, const double* __restrict__ z,
+                                                        const double* __restrict__ opd, double c, double epsp,
+                                                        double* partial, double* out) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (wv < tv.nchunks) {
+        const int64_t cidx = tv.c0 + wv;
+        const int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
+        const double zi = z[row];
+        const int beg = tv.chunk_beg[cidx];
+        const int end = min(beg + kArcBudget, row_ptr[row + 1]);
+        double sum = chunk_sum(beg, end, [&](int k) {
+            double a = w ? static_cast<double>(w[k]) : 1.0;
+            if constexpr (MODE == 0) return a * z[col[k]];
+            double d = zi - z[col[k]];
+            return a * d * d;
+        });
+        if (lane == 0) partial[cidx] = sum;
+        return;
+    }
+    wv -= tv.nchunks;
+    if (wv >= tv.ntiles) return;
+    const int64_t tix = tv.t0 + wv;
+    if (tv.tile_heavy[tix] >= 0) return;
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    __shared__ double s_z[kWavesPerBlock][64];
+    if (lane < nrows) s_z[wid][lane] = z[r0 + lane];
+    wave_sync_lds();
+    const int* pre = s_pre[wid];
+    double sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], [&](int k) {
+        double a = w ? static_cast<double>(w[k]) : 1.0;
+        if constexpr (MODE == 0) return a * z[col[k]];
+        // row of arc k inside the tile
+        int slot = tile_find(pre, nrows, k - row_ptr[r0]);
+        double d = s_z[wid][slot] - z[col[k]];
+        return a * d * d;
+    });
+    if (lane < nrows) {
+        const int64_t i = r0 + lane;
+        if constexpr (MODE == 0) {
+            double r = s[i] - opd[i] * z[i] + sum;
+            out[i] = fabs(r) / (epsp * (s[i] + c));
+        } else {
+            out[i] = sum;
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_urows_heavy(TileView tv, const double* __restrict__ s,
+                                                        const double* __restrict__ z, const double* __restrict__ opd,
+                                                        double c, double epsp, const double* __restrict__ partial,
+                                                        double* out) {
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (hh >= tv.h1) return;
+    const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
+    double sum = 0.0;
+    for (int32_t q = c0 + lane; q < c1; q += 64) sum += partial[q];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+        const int64_t i = tv.heavy_row[hh];
+        if constexpr (MODE == 0) {
+            double r = s[i] - opd[i] * z[i] + sum;
+            out[i] = fabs(r) / (epsp * (s[i] + c));
+        } else {
+            out[i] = sum;
+        }
+    }
+}
+
+// one block per component: [0] sum z, [1] sum z^2, [2] sum (z-s)^2, [3] sum d_i,
+// [4] max ratio; second pass [5] sum (z - mean)^2
+__global__ __launch_bounds__(256) void k_useg(const int64_t* __restrict__ node_off, const double* __restrict__ s,
+                                              const double* __restrict__ z, const double* __restrict__ drow,
+                                              const double* __restrict__ ratio, double* out, int pass) {
+    __shared__ double lds[4];
+    const int cidx = blockIdx.x;
+    const int64_t b = node_off[cidx], e = node_off[cidx + 1];
+    if (pass == 0) {
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, mx = 0;
+        for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+            double zi = z[i], d = zi - s[i];
+            a0 += zi;
+            a1 += zi * zi;
+            a2 += d * d;
+            a3 += drow[i];
+            double r = ratio[i];
+            mx = fmax(mx, isfinite(r) ? r : INFINITY);
+        }
+        a0 = block_sum<256>(a0, lds);
+        a1 = block_sum<256>(a1, lds);
+        a2 = block_sum<256>(a2, lds);
+        a3 = block_sum<256>(a3, lds);
+        mx = wave_max(mx);
+        __shared__ double smx[4];
+        if (lane_id() == 0) smx[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = fmax(fmax(smx[0], smx[1]), fmax(smx[2], smx[3]));
+            out[8 * cidx + 0] = a0;
+            out[8 * cidx + 1] = a1;
+            out[8 * cidx + 2] = a2;
+            out[8 * cidx + 3] = a3;
+            out[8 * cidx + 4] = m;
+        }
+    } else {
+        const double mean = (e > b) ? out[8 * cidx + 0] / static_cast<double>(e - b) : 0.0;
+        double a = 0;
+        for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+            double d = z[i] - mean;
+            a += d * d;
+        }
+        a = block_sum<256>(a, lds);
+        if (threadIdx.x == 0) out[8 * cidx + 5] = a;
+    }
+}
+
+// write per-item stats and measures of the union components
+__global__ void k_ufinish(int ncomp, const int32_t* __restrict__ comp_item, const int32_t* __restrict__ comp_dir,
+                          const int64_t* __restrict__ node_off, const int64_t* __restrict__ metric_slot,
+                          const double* __restrict__ seg, const int* __restrict__ sweeps_done, int slot0,
+                          int budget, fj_solve_stats* stats, fj_metrics_out* mets) {
+    int cidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= ncomp) return;
+    const int it = comp_item[cidx];
+    const double* o = seg + 8 * cidx;
+    const int64_t n = node_off[cidx + 1] - node_off[cidx];
+    fj_solve_stats st{};
+    int sw = sweeps_done[slot0 + cidx];
+    st.rounds = sw ? sw : budget;
+    st.max_ratio = o[4];
+    st.certified = (o[4] <= 1.0) ? 1 : 0;
+    stats[it] = st;
+    fj_metrics_out m;
+    m.P = o[5];
+    m.D = comp_dir[cidx] ? o[3] : 0.5 * o[3];
+    m.I = o[2];
+    m.C = o[1];
+    m.mean = n ? o[0] / static_cast<double>(n) : 0.0;
+    mets[metric_slot[it]] = m;
+}
+
+// -------------------------------------------- results: multi-vector item
+// wave per row (grid-stride), lane l = vector l; per-block partials per lane:
+// pass 0: [0] sum z, [1] sum z^2, [2] sum (z-s)^2, [3] sum_i sum_j a_ij (z_i-z_j)^2, [4] max ratio
+// pass 1: [5] sum (z - mean)^2
+constexpr int kMBlocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_mresults(int64_t n, int k, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                     const double* __restrict__ opd, const double* __restrict__ s,
+                                                     const double* __restrict__ z, double c, double epsp,
+                                                     const double* __restrict__ means, double* part, int pass) {
+    __shared__ double lds[kWavesPerBlock][64][6];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t W = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    const double mean = (pass == 1 && lane < k) ? means[lane] : 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; i < n; i += W) {
+        if (lane >= k) continue;
+        const double zi = z[i * k + lane];
+        if (pass == 1) {
+            double d = zi - mean;
+            a[5] += d * d;
+            continue;
+        }
+        const double si = s[i * k + lane];
+        double sz = 0.0, sd = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int64_t j = col[e];
+            const double aw = w ? static_cast<double>(w[e]) : 1.0;
+            const double zj = z[j * k + lane];
+            sz += aw * zj;
+            sd += aw * (zi - zj) * (zi - zj);
+        }
+        const double r = si - opd[i] * zi + sz;
+        double ratio = fabs(r) / (epsp * (si + c));
+        if (!isfinite(ratio)) ratio = INFINITY;
+        a[0] += zi;
+        a[1] += zi * zi;
+        a[2] += (zi - si) * (zi - si);
+        a[3] += sd;
+        a[4] = fmax(a[4], ratio);
+    }
+    for (int q = 0; q < 6; ++q) lds[wid][lane][q] = a[q];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double t[6] = {0, 0, 0, 0, 0, 0};
+        for (int v = 0; v < kWavesPerBlock; ++v) {
+            for (int q = 0; q < 6; ++q) {
+                if (q == 4) t[q] = fmax(t[q], lds[v][threadIdx.x][q]);
+                else t[q] += lds[v][threadIdx.x][q];
+            }
+        }
+        for (int q = 0; q < 6; ++q) part[(static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x) * 6 + q] = t[q];
+    }
+}
+
+// one thread per vector: fixed-order reduce of the block partials
+__global__ void k_mreduce(int k, int nb, const double* __restrict__ part, double* tot, double* means, int64_t n,
+                          int pass) {
+    const int l = threadIdx.x;
+    if (l >= k) return;
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 6; ++q) {
+            double v = part[(static_cast<int64_t>(b) * 64 + l) * 6 + q];
+            if (q == 4) t[q] = fmax(t[q], v); else t[q] += v;
+        }
+    if (pass == 0) {
+        for (int q = 0; q < 5; ++q) tot[8 * l + q] = t[q];
+        means[l] = n ? t[0] / static_cast<double>(n) : 0.0;
+    } else {
+        tot[8 * l + 5] = t[5];
+    }
+}
+
+__global__ void k_mfinish(int k, int item, int directed, int64_t n, int64_t mslot, const double* __restrict__ tot,
+                          const int* __restrict__ sweeps_done, int slot, int budget, fj_solve_stats* stats,
+                          fj_metrics_out* mets) {
+    const int l = threadIdx.x;
+    if (l >= k) return;
+    const double* o = tot + 8 * l;
+    fj_metrics_out m;
+    m.P = o[5];
+    m.D = directed ? o[3] : 0.5 * o[3];
+    m.I = o[2];
+    m.C = o[1];
+    m.mean = n ? o[0] / static_cast<double>(n) : 0.0;
+    mets[mslot + l] = m;
+    if (l == 0) {
+        double mx = 0.0;
+        for (int q = 0; q < k; ++q) mx = fmax(mx, tot[8 * q + 4]);
+        fj_solve_stats st{};
+        int sw = sweeps_done[slot];
+        st.rounds = sw ? sw : budget;
+        st.max_ratio = mx;
+        st.certified = mx <= 1.0 ? 1 : 0;
+        stats[item] = st;
+    }
+}
+
+}  // namespace
+}  // namespace fj
+
+using namespace fj;
+
+// ---------------------------------------------------------------- host side
+struct UnionGroup {
+    int ncomp = 0;
+    int64_t n = 0, nnz = 0;
+    bool weighted = false;
+    std::vector<int32_t> comp_item;
+    std::vector<int64_t> node_off, arc_off;
+    int32_t* row_ptr = nullptr; int32_t* col = nullptr; float* w = nullptr;
+    int64_t* d_node_off = nullptr;
+    int32_t* d_comp_item = nullptr; int32_t* comp_dir = nullptr; int32_t* comp_of = nullptr; int32_t* pcomp = nullptr;
+    fj_graph g;
+    void* gws = nullptr; size_t gws_bytes = 0;
+    double* s_in = nullptr; double* z_out = nullptr;
+    double* sp = nullptr; double* zh = nullptr; int32_t* zq = nullptr; double* partial = nullptr;
+    double* ratio = nullptr; double* drow = nullptr; double* seg = nullptr;
+};
+
+struct MrhsGroup {
+    int item = 0, k = 0;
+    fj_graph_desc desc{};
+    fj_graph g;
+    void* gws = nullptr; size_t gws_bytes = 0;
+    double* s_in = nullptr; double* z_out = nullptr;
+    double* sp = nullptr; double* zh = nullptr; double* partial = nullptr;
+    double* part = nullptr; double* tot = nullptr; double* means = nullptr;
+};
+
+struct fj_batch {
+    int num_items = 0;
+    std::vector<int> ks;
+    std::vector<int64_t> ns;
+    std::vector<int> item_group;  // -1 union, else index into M
+    double eps = 0, omega = 1, c = 0, sigma = 1, epsp = 0;
+    int budget = 256;
+    bool has_union = false;
+    UnionGroup U;
+    std::vector<MrhsGroup> M;
+    int nslots = 0;
+    int* upd = nullptr; int* done = nullptr; int* sweeps_done = nullptr; int* all_done = nullptr; int* bad = nullptr;
+    fj_solve_stats* stats = nullptr;
+    fj_metrics_out* mets = nullptr;
+    int64_t* metric_slot = nullptr;
+    std::vector<int64_t> h_metric_slot;
+    int64_t total_k = 0;
+    int num_colours = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_nodes = 0;
+    std::vector<double> tune_ms;
+    ~fj_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace fj {
+namespace {
+
+struct BatchLayoutSizes {
+    size_t bytes = 0;
+};
+
+// Carve (or size, when base is null) the whole batch workspace.
+size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, void* base) {
+    Carver cv(base);
+    int64_t un = 0, unnz = 0, ncomp = 0, total_k = 0;
+    bool uw = false, udir = false;
+    for (int i = 0; i < num; ++i) {
+        total_k += items[i].k;
+        if (items[i].k == 1) {
+            un += items[i].graph.n;
+            unnz += items[i].graph.nnz;
+            uw = uw || items[i].graph.w != nullptr;
+            udir = udir || items[i].graph.directed;
+            ++ncomp;
+        }
+    }
+    const int nm = static_cast<int>(num - ncomp);
+    const int nslots = static_cast<int>(ncomp) + nm;
+    int* upd = cv.take<int>(nslots + 1);
+    int* done = cv.take<int>(nslots + 1);
+    int* swd = cv.take<int>(nslots + 1);
+    int* alld = cv.take<int>(1);
+    int* bad = cv.take<int>(1);
+    fj_solve_stats* stats = cv.take<fj_solve_stats>(num);
+    fj_metrics_out* mets = cv.take<fj_metrics_out>(total_k);
+    int64_t* mslot = cv.take<int64_t>(num);
+    if (b) {
+        b->nslots = nslots;
+        b->upd = upd; b->done = done; b->sweeps_done = swd; b->all_done = alld; b->bad = bad;
+        b->stats = stats; b->mets = mets; b->metric_slot = mslot; b->total_k = total_k;
+    }
+    if (ncomp > 0) {
+        UnionGroup* U = b ? &b->U : nullptr;
+        auto* rp = cv.take<int32_t>(un + 1);
+        auto* col = cv.take<int32_t>(unnz);
+        auto* w = uw ? cv.take<float>(unnz) : nullptr;
+        auto* noff = cv.take<int64_t>(ncomp + 1);
+        auto* citem = cv.take<int32_t>(ncomp);
+        auto* cdir = cv.take<int32_t>(ncomp);
+        auto* cof = cv.take<int32_t>(un);
+        auto* pcomp = cv.take<int32_t>(un);
+        fj_graph_desc ud{un, unnz, rp, col, w, 1};
+        if (!base) { ud.row_ptr = reinterpret_cast<const int32_t*>(256); ud.col = ud.row_ptr; if (uw) ud.w = reinterpret_cast<const float*>(256); }
+        size_t gb = graph_ws_bytes(&ud, FJ_GRAPH_COLOUR);
+        void* gws = cv.take<char>(gb);
+        auto* s_in = cv.take<double>(un);
+        auto* z_out = cv.take<double>(un);
+        auto* sp = cv.take<double>(un);
+        auto* zh = cv.take<double>(un);
+        auto* zq = cv.take<int32_t>(un);
+        auto* partial = cv.take<double>(2 * (unnz / kArcBudget) + 4);
+        auto* ratio = cv.take<double>(un);
+        auto* drow = cv.take<double>(un);
+        auto* seg = cv.take<double>(8 * ncomp);
+        if (U) {
+            U->ncomp = static_cast<int>(ncomp); U->n = un; U->nnz = unnz; U->weighted = uw;
+            U->row_ptr = rp; U->col = col; U->w = w; U->d_node_off = noff; U->d_comp_item = citem;
+            U->comp_dir = cdir; U->comp_of = cof; U->pcomp = pcomp; U->gws = gws; U->gws_bytes = gb;
+            U->s_in = s_in; U->z_out = z_out; U->sp = sp; U->zh = zh; U->zq = zq; U->partial = partial;
+            U->ratio = ratio; U->drow = drow; U->seg = seg;
+        }
+    }
+    int mi = 0;
+    for (int i = 0; i < num; ++i) {
+        if (items[i].k == 1) continue;
+        const int64_t n = items[i].graph.n, nnz = items[i].graph.nnz;
+        const int k = items[i].k;
+        fj_graph_desc d = items[i].graph;
+        size_t gb = graph_ws_bytes(&d, FJ_GRAPH_COLOUR);
+        void* gws = cv.take<char>(gb);
+        auto* s_in = cv.take<double>(n * k);
+        auto* z_out = cv.take<double>(n * k);
+        auto* sp = cv.take<double>(n * k);
+        auto* zh = cv.take<double>(n * k);
+        auto* partial = cv.take<double>((2 * (nnz / kArcBudget) + 4) * k);
+        auto* part = cv.take<double>(static_cast<int64_t>(kMBlocks) * 64 * 6);
+        auto* tot = cv.take<double>(8 * 64);
+        auto* means = cv.take<double>(64);
+        if (b) {
+            MrhsGroup& G = b->M[mi];
+            G.item = i; G.k = k; G.desc = d; G.gws = gws; G.gws_bytes = gb; G.s_in = s_in; G.z_out = z_out;
+            G.sp = sp; G.zh = zh; G.partial = partial; G.part = part; G.tot = tot; G.means = means;
+        }
+        ++mi;
+    }
+    return cv.bytes();
+}
+
+// Enqueue one complete batched solve (capture-safe: kernels only).
+fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_out) {
+    int launches = 0;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_flags_reset, dim3(1), dim3(256), 0, st, b->nslots, b->upd, b->done, b->sweeps_done,
+                       b->all_done, b->bad);
+    ++launches;
+    UnionGroup& U = b->U;
+    const double epsp = b->epsp;
+    SorState SU{U.sp, U.g.popd, U.g.pinv64, U.zh, U.zq, b->omega, 1.0 - 1e-6, epsp};
+    if (b->has_union && U.n > 0) {
+        hipLaunchKernelGGL(k_sor_init, dim3(g1d(U.n, bs)), dim3(bs), 0, st, U.n, U.g.perm, U.s_in,
+                           static_cast<const double*>(nullptr), b->c, U.sp, U.zh, U.zq, b->bad);
+        ++launches;
+    }
+    for (auto& G : b->M) {
+        hipLaunchKernelGGL(k_minit, dim3(g1d(G.g.n * G.k, bs)), dim3(bs), 0, st, G.g.n, G.k, G.g.perm, G.s_in, b->c,
+                           G.sp, G.zh, b->bad);
+        ++launches;
+    }
+    int max_cls = b->has_union ? U.g.num_colours : 0;
+    for (auto& G : b->M) max_cls = std::max(max_cls, G.g.num_colours);
+    for (int sw = 0; sw < budget; ++sw) {
+        for (int k = 0; k < max_cls; ++k) {
+            if (b->has_union && k < U.g.num_colours) {
+                TileView tv = tile_view(U.g.tiles_p, k);
+                if (tv.ntiles + tv.nchunks > 0) {
+                    hipLaunchKernelGGL(k_usor_tiles, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0,
+                                       st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.pcomp, b->upd,
+                                       b->done, b->all_done, b->bad);
+                    ++launches;
+                }
+                if (tv.h1 > tv.h0) {
+                    hipLaunchKernelGGL(k_usor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv,
+                                       SU, U.partial, U.pcomp, b->upd, b->done, b->all_done, b->bad);
+                    ++launches;
+                }
+            }
+            for (size_t m = 0; m < b->M.size(); ++m) {
+                MrhsGroup& G = b->M[m];
+                if (k >= G.g.num_colours) continue;
+                const int slot = U.ncomp + static_cast<int>(m);
+                MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->omega, 1.0 - 1e-6, epsp, G.k};
+                TileView tv = tile_view(G.g.tiles_p, k);
+                const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
+                hipLaunchKernelGGL(k_msor_class, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, st,
+                                   tv, rb, re, G.g.prow_ptr, G.g.pcol, G.g.pw, S, G.partial, b->upd + slot,
+                                   b->done + slot, b->all_done, b->bad);
+                ++launches;
+                if (tv.h1 > tv.h0) {
+                    hipLaunchKernelGGL(k_msor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv, S,
+                                       G.partial, b->upd + slot, b->done + slot, b->all_done, b->bad);
+                    ++launches;
+                }
+            }
+        }
+        hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, st, b->nslots, sw, b->upd, b->done, b->sweeps_done,
+                           b->all_done);
+        ++launches;
+    }
+    // results
+    if (b->has_union && U.n > 0) {
+        hipLaunchKernelGGL(k_sor_unshift, dim3(g1d(U.n, bs)), dim3(bs), 0, st, U.n, U.g.perm, U.zh, b->c, U.z_out,
+                           static_cast<double*>(nullptr));
+        TileView ta = tile_view_all(U.g.tiles_a);
+        const unsigned nb1 = waves_to_blocks(ta.nchunks + ta.ntiles), nb2 = waves_to_blocks(ta.h1 - ta.h0);
+        hipLaunchKernelGGL(k_urows_tiles<0>, dim3(nb1), dim3(kBlock), 0, st, ta, U.row_ptr, U.col, U.w, U.s_in,
+                           U.z_out, U.g.opd, b->c, epsp, U.partial, U.ratio);
+        if (nb2) hipLaunchKernelGGL(k_urows_heavy<0>, dim3(nb2), dim3(kBlock), 0, st, ta, U.s_in, U.z_out, U.g.opd,
+                                    b->c, epsp, U.partial, U.ratio);
+        hipLaunchKernelGGL(k_urows_tiles<1>, dim3(nb1), dim3(kBlock), 0, st, ta, U.row_ptr, U.col, U.w, U.s_in,
+                           U.z_out, U.g.opd, b->c, epsp, U.partial, U.drow);
+        if (nb2) hipLaunchKernelGGL(k_urows_heavy<1>, dim3(nb2), dim3(kBlock), 0, st, ta, U.s_in, U.z_out, U.g.opd,
+                                    b->c, epsp, U.partial, U.drow);
+        hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
+                           U.seg, 0);
+        hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
+                           U.seg, 1);
+        hipLaunchKernelGGL(k_ufinish, dim3(g1d(U.ncomp, 256)), dim3(256), 0, st, U.ncomp, U.d_comp_item, U.comp_dir,
+                           U.d_node_off, b->metric_slot, U.seg, b->sweeps_done, 0, budget, b->stats, b->mets);
+        launches += 7 + (nb2 ? 2 : 0);
+    }
+    for (size_t m = 0; m < b->M.size(); ++m) {
+        MrhsGroup& G = b->M[m];
+        const int slot = U.ncomp + static_cast<int>(m);
+        hipLaunchKernelGGL(k_munshift, dim3(g1d(G.g.n * G.k, bs)), dim3(bs), 0, st, G.g.n, G.k, G.g.perm, G.zh, b->c,
+                           G.z_out);
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_mresults, dim3(kMBlocks), dim3(kBlock), 0, st, G.g.n, G.k, G.desc.row_ptr,
+                               G.desc.col, G.desc.w, G.g.opd, G.s_in, G.z_out, b->c, epsp, G.means, G.part, pass);
+            hipLaunchKernelGGL(k_mreduce, dim3(1), dim3(64), 0, st, G.k, kMBlocks, G.part, G.tot, G.means, G.g.n,
+                               pass);
+        }
+        hipLaunchKernelGGL(k_mfinish, dim3(1), dim3(64), 0, st, G.k, G.item, G.desc.directed, G.g.n,
+                           b->h_metric_slot[G.item], G.tot, b->sweeps_done, slot, budget, b->stats, b->mets);
+        launches += 6;
+    }
+    if (launches_out) *launches_out = launches;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "enqueue batched solve");
+    return FJ_OK;
+}
+
+bool valid_items(const fj_batch_item_desc* items, int32_t num) {
+    if (!items || num <= 0) return false;
+    for (int i = 0; i < num; ++i) {
+        const fj_graph_desc& d = items[i].graph;
+        if (items[i].k < 1 || items[i].k > 64) return false;
+        if (d.n <= 0 || d.nnz < 0 || !d.row_ptr || (d.nnz > 0 && !d.col)) return false;
+        if (d.n >= (int64_t(1) << 31) - 1 || d.nnz >= (int64_t(1) << 31) - 1) return false;
+    }
+    return true;
+}
+
+}  // namespace
+}  // namespace fj
+
+extern "C" size_t fj_batch_workspace_bytes(const fj_batch_item_desc* items, int32_t num_items) {
+    if (!valid_items(items, num_items)) return 0;
+    int64_t un = 0, unnz = 0;
+    for (int i = 0; i < num_items; ++i)
+        if (items[i].k == 1) { un += items[i].graph.n; unnz += items[i].graph.nnz; }
+    if (un >= (int64_t(1) << 31) - 1 || unnz >= (int64_t(1) << 31) - 1) return 0;
+    return carve_batch(nullptr, items, num_items, nullptr);
+}
+
+extern "C" fj_status fj_batch_create(const fj_batch_item_desc* items, int32_t num_items, const fj_solve_opts* o,
+                                     void* ws, size_t ws_bytes, void* stream, fj_batch** out) {
+    if (!out || !o || !ws) {
+        set_error("fj_batch_create: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (!valid_items(items, num_items)) {
+        set_error("fj_batch_create: need 1..64 vectors per item and valid graph descriptors");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (!(o->eps > 0.0 && o->eps < 1.0) || !(o->omega > 0.0 && o->omega < 2.0) || !(o->c >= 0.0) ||
+        !(o->sigma > 0.0)) {
+        set_error("fj_batch_create: need eps in (0,1), omega in (0,2), c >= 0, sigma > 0");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const size_t need = fj_batch_workspace_bytes(items, num_items);
+    if (need == 0 || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256) {
+        set_error("fj_batch_create: workspace too small or misaligned (need " + std::to_string(need) + " bytes)");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    fj_batch* b = new (std::nothrow) fj_batch();
+    if (!b) {
+        set_error("fj_batch_create: host allocation failed");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    b->num_items = num_items;
+    b->eps = o->eps; b->omega = o->omega; b->c = o->c; b->sigma = o->sigma;
+    b->epsp = o->sigma * o->eps / (o->c + o->sigma);
+    int nm = 0;
+    for (int i = 0; i < num_items; ++i) {
+        b->ks.push_back(items[i].k);
+        b->ns.push_back(items[i].graph.n);
+        if (items[i].k > 1) ++nm;
+    }
+    b->M.resize(nm);
+    carve_batch(b, items, num_items, ws);
+    auto fail = [&](fj_status rc) { delete b; return rc; };
+    // metric slots
+    b->h_metric_slot.resize(num_items);
+    int64_t acc = 0;
+    for (int i = 0; i < num_items; ++i) { b->h_metric_slot[i] = acc; acc += items[i].k; }
+    if (hipMemcpyAsync(b->metric_slot, b->h_metric_slot.data(), sizeof(int64_t) * num_items, hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return fail(hip_fail(hipGetLastError(), "metric slots"));
+    // union of the single-vector items
+    UnionGroup& U = b->U;
+    if (U.ncomp > 0) {
+        b->has_union = true;
+        U.node_off.assign(1, 0);
+        U.arc_off.assign(1, 0);
+        std::vector<int32_t> cdir;
+        int* err = b->bad;
+        if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) return fail(hip_fail(hipGetLastError(), "memset"));
+        int cidx = 0;
+        for (int i = 0; i < num_items; ++i) {
+            if (items[i].k != 1) continue;
+            const fj_graph_desc& d = items[i].graph;
+            U.comp_item.push_back(i);
+            cdir.push_back(d.directed ? 1 : 0);
+            hipLaunchKernelGGL(k_item_rowptr_check, dim3(g1d(d.n + 1, 256)), dim3(256), 0, st, d.n, d.nnz, d.row_ptr,
+                               err);
+            int herr = 0;
+            if (hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return fail(hip_fail(hipGetLastError(), "row_ptr check"));
+            if (herr) {
+                set_error("fj_batch_create: item " + std::to_string(i) + " has an invalid row_ptr");
+                return fail(FJ_ERR_INVALID_ARGUMENT);
+            }
+            hipLaunchKernelGGL(k_union_copy, dim3(g1d(d.n, 256)), dim3(256), 0, st, d.n, d.row_ptr, d.col, d.w,
+                               U.node_off.back(), U.arc_off.back(), cidx, U.row_ptr, U.col, U.w, U.comp_of, err);
+            U.node_off.push_back(U.node_off.back() + d.n);
+            U.arc_off.push_back(U.arc_off.back() + d.nnz);
+            ++cidx;
+        }
+        const int32_t total = static_cast<int32_t>(U.nnz);
+        FJ_HIP(hipMemcpyAsync(U.row_ptr + U.n, &total, sizeof(int32_t), hipMemcpyHostToDevice, st));
+        FJ_HIP(hipMemcpyAsync(U.d_node_off, U.node_off.data(), sizeof(int64_t) * (U.ncomp + 1), hipMemcpyHostToDevice, st));
+        FJ_HIP(hipMemcpyAsync(U.d_comp_item, U.comp_item.data(), sizeof(int32_t) * U.ncomp, hipMemcpyHostToDevice, st));
+        FJ_HIP(hipMemcpyAsync(U.comp_dir, cdir.data(), sizeof(int32_t) * U.ncomp, hipMemcpyHostToDevice, st));
+        int herr = 0;
+        FJ_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+        if (herr) {
+            set_error("fj_batch_create: a column index leaves its own graph");
+            return fail(FJ_ERR_INVALID_ARGUMENT);
+        }
+        fj_graph_desc ud{U.n, U.nnz, U.row_ptr, U.col, U.w, 1};
+        fj_status rc = graph_build(&U.g, &ud, FJ_GRAPH_COLOUR, U.gws, U.gws_bytes, st);
+        if (rc) return fail(rc);
+        hipLaunchKernelGGL(k_union_symmetry, dim3(g1d(U.n, 256)), dim3(256), 0, st, U.n, U.row_ptr, U.col, U.w,
+                           U.comp_of, U.comp_dir, err);
+        hipLaunchKernelGGL(k_gather_i32, dim3(g1d(U.n, 256)), dim3(256), 0, st, U.n, U.g.perm, U.comp_of, U.pcomp);
+        FJ_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+        if (herr) {
+            set_error("fj_batch_create: an undirected item is not symmetric");
+            return fail(FJ_ERR_INVALID_ARGUMENT);
+        }
+        b->num_colours = std::max(b->num_colours, U.g.num_colours);
+    }
+    for (auto& G : b->M) {
+        fj_status rc = graph_build(&G.g, &G.desc, FJ_GRAPH_COLOUR, G.gws, G.gws_bytes, st);
+        if (rc) return fail(rc);
+        b->num_colours = std::max(b->num_colours, G.g.num_colours);
+    }
+    b->budget = 256;
+    *out = b;
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_destroy(fj_batch* b) {
+    delete b;
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_io(const fj_batch* b, int32_t item, double** s, double** z) {
+    if (!b || !s || !z || item < 0 || item >= b->num_items) {
+        set_error("fj_batch_io: bad argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (b->ks[item] == 1) {
+        int cidx = -1;
+        for (int q = 0; q < b->U.ncomp; ++q)
+            if (b->U.comp_item[q] == item) { cidx = q; break; }
+        *s = b->U.s_in + b->U.node_off[cidx];
+        *z = b->U.z_out + b->U.node_off[cidx];
+    } else {
+        for (const auto& G : b->M)
+            if (G.item == item) { *s = G.s_in; *z = G.z_out; }
+    }
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_get_info(const fj_batch* b, fj_batch_info* out) {
+    if (!b || !out) {
+        set_error("fj_batch_get_info: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->omega = b->omega;
+    out->sweep_budget = b->budget;
+    out->graph_nodes = b->graph_nodes;
+    out->num_colours = b->num_colours;
+    for (size_t i = 0; i < b->tune_ms.size() && i < 16; ++i) out->tune_ms[i] = b->tune_ms[i];
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_omegas, void* stream) {
+    if (!b || !omegas || n_omegas < 1 || n_omegas > 16) {
+        set_error("fj_batch_tune: need 1..16 candidate omegas");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    for (int q = 0; q < n_omegas; ++q)
+        if (!(omegas[q] > 0.0 && omegas[q] < 2.0)) {
+            set_error("fj_batch_tune: omega must be in (0,2)");
+            return FJ_ERR_INVALID_ARGUMENT;
+        }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    b->graph_nodes = 0;
+    b->tune_ms.assign(n_omegas, 0.0);
+    double best_ms = 1e300, best_omega = b->omega;
+    int best_sweeps = b->budget;
+    const int probe_budget = 512;
+    std::vector<int> swd(b->nslots);
+    for (int q = 0; q < n_omegas; ++q) {
+        b->omega = omegas[q];
+        FJ_HIP(hipStreamSynchronize(st));
+        auto t0 = std::chrono::steady_clock::now();
+        fj_status rc = enqueue_solve(b, st, probe_budget, nullptr);
+        if (rc) return rc;
+        FJ_HIP(hipStreamSynchronize(st));
+        double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        FJ_HIP(hipMemcpy(swd.data(), b->sweeps_done, sizeof(int) * b->nslots, hipMemcpyDeviceToHost));
+        int needed = 0, open = 0, hbad = 0;
+        for (int v : swd) { needed = std::max(needed, v); open += (v == 0); }
+        FJ_HIP(hipMemcpy(&hbad, b->bad, sizeof(int), hipMemcpyDeviceToHost));
+        b->tune_ms[q] = ms;
+        if (!open && !hbad && ms < best_ms) {
+            best_ms = ms;
+            best_omega = omegas[q];
+            best_sweeps = needed;
+        }
+    }
+    if (best_ms == 1e300) {
+        set_error("fj_batch_tune: no candidate omega converged within 512 sweeps");
+        return FJ_ERR_NOT_CONVERGED;
+    }
+    b->omega = best_omega;
+    b->budget = best_sweeps + std::max(4, best_sweeps / 4);
+    // Record the launch sequence once on a private stream (the caller's may be
+    // the null stream, which cannot be captured); fj_solve_batched replays it
+    // on the caller's stream.
+    hipStream_t cap = nullptr;
+    FJ_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    int launches = 0;
+    fj_status rc = enqueue_solve(b, cap, b->budget, &launches);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    b->graph = g;
+    FJ_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_nodes = launches;
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_solve_batched(fj_batch* b, fj_solve_stats* stats_dev, fj_metrics_out* metrics_dev,
+                                      void* stream) {
+    if (!b) {
+        set_error("fj_solve_batched: null batch");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (b->exec) {
+        FJ_HIP(hipGraphLaunch(b->exec, st));
+    } else {
+        fj_status rc = enqueue_solve(b, st, b->budget, nullptr);
+        if (rc) return rc;
+    }
+    if (stats_dev)
+        FJ_HIP(hipMemcpyAsync(stats_dev, b->stats, sizeof(fj_solve_stats) * b->num_items, hipMemcpyDeviceToDevice, st));
+    if (metrics_dev)
+        FJ_HIP(hipMemcpyAsync(metrics_dev, b->mets, sizeof(fj_metrics_out) * b->total_k, hipMemcpyDeviceToDevice, st));
+    return FJ_OK;
+}

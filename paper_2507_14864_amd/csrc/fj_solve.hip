@@ -10,6 +10,7 @@
 #include "fj_device.h"
 #include "fj_internal.h"
 #include "fj_grid.h"
+#include "fj_sor.h"
 #include "fj_tile.h"
 
 namespace fj {
@@ -19,13 +20,6 @@ constexpr int kMaxRounds = 1 << 20;
 
 inline unsigned grid1d(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 inline unsigned tile_blocks(int64_t rows) { return static_cast<unsigned>((rows + kBlock - 1) / kBlock); }
-
-__device__ __forceinline__ void flag_set(int* f) {
-    if (__atomic_load_n(f, __ATOMIC_RELAXED) == 0) __atomic_store_n(f, 1, __ATOMIC_RELAXED);
-}
-__device__ __forceinline__ void stripe_add(unsigned long long* stats, int slot, unsigned long long v) {
-    atomicAdd(&stats[(blockIdx.x % kStripes) * kStripeStride + slot], v);
-}
 
 // ------------------------------------------------------------------- init
 // Alg. 2: s' = s + c, h = eps' s', zhat' = 0, r = s'.  The FP32 threshold is
@@ -292,128 +286,6 @@ __global__ __launch_bounds__(kBlock) void k_push_heavy(TileView tv, const int32_
 // Lemma 4), and row i is updated iff |r_i| > h_i = eps' s'_i (Alg. 3's test;
 // a margin of 1e-6 h keeps a quiet sweep certified under the FP64 rounding of
 // the standalone certificate, which sums in a different order).
-// 32-bit fixed-point copy of zhat' (scale 2^30, range (-2, 2)) used by the
-// light-row gathers while the sweeps are far from the certificate: half the
-// bytes of FP64 and an absolute resolution of 9.3e-10 (FP32 would give 6e-8
-// near 1).  The final sweeps and the certificate read FP64 only.
-constexpr double kFixScale = 1073741824.0;  // 2^30
-__device__ __forceinline__ int32_t fix_enc(double z) {
-    double q = rint(z * kFixScale);
-    q = fmin(fmax(q, -2147483647.0), 2147483647.0);
-    return static_cast<int32_t>(q);
-}
-__device__ __forceinline__ double fix_dec(int32_t q) { return static_cast<double>(q) * (1.0 / kFixScale); }
-
-struct SorState {
-    const double* sp;    // s' = s + c, relabelled
-    const double* popd;  // 1 + d
-    const double* pinv;  // 1 / (1 + d)
-    double* zh;          // zhat', FP64
-    int32_t* zq;         // fixed-point copy of zhat'
-    double omega;
-    double thr;          // update iff |r| > thr * eps' s'
-    double epsp;
-};
-
-__global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ s,
-                           const double* __restrict__ z0, double c, double* sp, double* zh, int32_t* zq, int* bad) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t o = perm[i];
-    double si = s[o];
-    if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
-    sp[i] = si + c;
-    double z = 0.0;
-    if (z0) {
-        double zi = z0[o];
-        if (!isfinite(zi)) flag_set(bad);
-        z = zi + c;
-    }
-    zh[i] = z;
-    zq[i] = fix_enc(z);
-}
-
-__device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S, bool* nonfinite) {
-    double z = S.zh[i];
-    double sp = __builtin_nontemporal_load(&S.sp[i]);
-    double ri = sp - __builtin_nontemporal_load(&S.popd[i]) * z + sum;
-    *nonfinite = !isfinite(ri);
-    if (fabs(ri) > S.thr * S.epsp * sp) {
-        z += S.omega * ri * S.pinv[i];
-        S.zh[i] = z;
-        S.zq[i] = fix_enc(z);
-        return true;
-    }
-    return false;
-}
-
-template <bool MIRROR>
-__global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
-                                                      const int32_t* __restrict__ pcol, const float* __restrict__ pw,
-                                                      SorState S, double* partial, int* updated, int* bad,
-                                                      unsigned long long* stats) {
-    __shared__ int s_pre[kWavesPerBlock][65];
-    __shared__ double s_acc[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    const double* __restrict__ zh = S.zh;
-    const int32_t* __restrict__ zq = S.zq;
-    auto arc64 = [&](int k) {
-        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
-        return a * zh[__builtin_nontemporal_load(&pcol[k])];
-    };
-    auto arc_light = [&](int k) {
-        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
-        int j = __builtin_nontemporal_load(&pcol[k]);
-        if constexpr (MIRROR) return a * fix_dec(zq[j]);
-        else return a * zh[j];
-    };
-    if (wv < tv.nchunks) {  // heavy rows always gather FP64
-        int64_t cidx = tv.c0 + wv;
-        int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
-        int beg = tv.chunk_beg[cidx];
-        int end = min(beg + kArcBudget, prow_ptr[row + 1]);
-        double sum = chunk_sum(beg, end, arc64);
-        if (lane == 0) partial[cidx] = sum;
-        return;
-    }
-    wv -= tv.nchunks;
-    if (wv >= tv.ntiles) return;
-    const int64_t tix = tv.t0 + wv;
-    if (tv.tile_heavy[tix] >= 0) return;  // finished by k_sor_heavy
-    const int32_t r0 = tv.tile_start[tix];
-    const int nrows = tv.tile_start[tix + 1] - r0;
-    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc_light);
-    bool upd = false, nonfinite = false;
-    if (lane < nrows) upd = sor_row(r0 + lane, sum, S, &nonfinite);
-    uint64_t um = __ballot(upd);
-    if (__ballot(nonfinite) && lane == 0) flag_set(bad);
-    if (um && lane == 0) {
-        flag_set(updated);
-        stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, SorState S, const double* __restrict__ partial,
-                                                      int* updated, int* bad, unsigned long long* stats) {
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    if (hh >= tv.h1) return;
-    int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
-    double sum = 0.0;
-    for (int32_t c = c0 + lane; c < c1; c += 64) sum += partial[c];
-    sum = wave_sum(sum);
-    if (lane == 0) {
-        bool nonfinite = false;
-        bool upd = sor_row(tv.heavy_row[hh], sum, S, &nonfinite);
-        if (nonfinite) flag_set(bad);
-        if (upd) {
-            flag_set(updated);
-            stripe_add(stats, 0, 1ull);
-        }
-    }
-}
-
 // Persistent form of the colour-ordered sweep: one cooperative launch runs up
 // to max_sweeps sweeps.  Colour classes are separated by grid barriers (the
 // in-kernel equivalent of the per-class launches above).  Rows longer than
@@ -514,14 +386,6 @@ __global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
     if (lane == 0 && my_upd) stripe_add(a.stats, 0, my_upd);
 }
 
-__global__ void k_sor_unshift(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ zh, double c,
-                              double* z, double* zh_orig) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t o = perm[i];
-    z[o] = zh[i] - c;
-    if (zh_orig) zh_orig[o] = zh[i];
-}
 
 __global__ void k_unshift(int64_t n, const double* __restrict__ zh, double c, double* z) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -275,3 +275,133 @@ def certify(graph: Graph, s: torch.Tensor, z: torch.Tensor, eps: float, c: float
                             float(eps), float(c), float(sigma), ctypes.byref(out),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out.value
+
+
+# ---------------------------------------------------------------- batched solve
+class BatchItemDesc(ctypes.Structure):
+    _fields_ = [("graph", GraphDesc), ("k", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("sweep_budget", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
+                ("num_colours", ctypes.c_int32), ("tune_ms", ctypes.c_double * 16)]
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        vp, i32, sz, P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER
+        L.fj_batch_workspace_bytes.argtypes = [P(BatchItemDesc), i32]
+        L.fj_batch_workspace_bytes.restype = sz
+        L.fj_batch_create.argtypes = [P(BatchItemDesc), i32, P(SolveOpts), vp, sz, vp, P(vp)]
+        L.fj_batch_create.restype = i32
+        L.fj_batch_destroy.argtypes = [vp]
+        L.fj_batch_destroy.restype = i32
+        L.fj_batch_io.argtypes = [vp, i32, P(ctypes.c_void_p), P(ctypes.c_void_p)]
+        L.fj_batch_io.restype = i32
+        L.fj_batch_tune.argtypes = [vp, P(ctypes.c_double), i32, vp]
+        L.fj_batch_tune.restype = i32
+        L.fj_batch_get_info.argtypes = [vp, P(BatchInfo)]
+        L.fj_batch_get_info.restype = i32
+        L.fj_solve_batched.argtypes = [vp, vp, vp, vp]
+        L.fj_solve_batched.restype = i32
+        L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Many graphs and opinion vectors solved by one enqueued sequence
+    (fj_solve_batched).  ``graphs`` is a list of (row_ptr, col, w, directed)
+    with CUDA tensors; ``ks`` the number of vectors per graph (1..64)."""
+
+    def __init__(self, graphs, ks, eps=1e-4, omega=1.5, c=1e-5, sigma=1e-5):
+        L = _batch_lib()
+        self._keep = []
+        self.ns, self.ks = [], [int(k) for k in ks]
+        descs = (BatchItemDesc * len(graphs))()
+        for i, (rp, col, w, directed) in enumerate(graphs):
+            n = rp.numel() - 1
+            self.ns.append(n)
+            self._keep += [rp, col, w]
+            descs[i].graph = GraphDesc(n, col.numel(), _dev_ptr(rp, torch.int32, n + 1, "row_ptr"),
+                                       _dev_ptr(col, torch.int32, col.numel(), "col"),
+                                       _dev_ptr(w, torch.float32, col.numel(), "w") if w is not None else None,
+                                       1 if directed else 0)
+            descs[i].k = self.ks[i]
+        self._descs = descs
+        self.device = graphs[0][0].device
+        nbytes = L.fj_batch_workspace_bytes(descs, len(graphs))
+        if nbytes == 0:
+            raise ValueError("invalid batch description")
+        self.ws = _workspace(nbytes, self.device)
+        opts = make_opts(eps=eps, omega=omega, c=c, sigma=sigma)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(L.fj_batch_create(descs, len(graphs), ctypes.byref(opts), ctypes.c_void_p(self.ws.data_ptr()),
+                                 self.ws.numel(), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.num_items = len(graphs)
+        self._stats = torch.empty(self.num_items * ctypes.sizeof(SolveStats), dtype=torch.uint8, device=self.device)
+        self._mets = torch.empty(sum(self.ks) * ctypes.sizeof(MetricsOut), dtype=torch.uint8, device=self.device)
+
+    def _view(self, ptr, i):
+        off = ptr - self.ws.data_ptr()
+        n, k = self.ns[i], self.ks[i]
+        t = self.ws[off:off + 8 * n * k].view(torch.float64)
+        return t.view(n, k) if k > 1 else t
+
+    def input(self, i) -> torch.Tensor:
+        """Writable view of item i's opinions ([n] or [n][k] node-major)."""
+        s, z = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_batch_lib().fj_batch_io(self._h, i, ctypes.byref(s), ctypes.byref(z)))
+        return self._view(s.value, i)
+
+    def output(self, i) -> torch.Tensor:
+        s, z = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_batch_lib().fj_batch_io(self._h, i, ctypes.byref(s), ctypes.byref(z)))
+        return self._view(z.value, i)
+
+    def tune(self, omegas=(1.0, 1.2, 1.4, 1.5, 1.6, 1.7)):
+        arr = (ctypes.c_double * len(omegas))(*omegas)
+        _check(_batch_lib().fj_batch_tune(self._h, arr, len(omegas), _stream()))
+        return self.info()
+
+    def info(self) -> dict:
+        out = BatchInfo()
+        _check(_batch_lib().fj_batch_get_info(self._h, ctypes.byref(out)))
+        d = {k: getattr(out, k) for k, _ in out._fields_ if k != "tune_ms"}
+        d["tune_ms"] = list(out.tune_ms)
+        return d
+
+    def solve_async(self):
+        """Enqueue one batched solve on the current stream (no host sync)."""
+        _check(_batch_lib().fj_solve_batched(self._h, ctypes.c_void_p(self._stats.data_ptr()),
+                                             ctypes.c_void_p(self._mets.data_ptr()), _stream()))
+
+    def results(self):
+        """(stats per item, measures per item and vector) after a solve."""
+        import numpy as np
+        torch.cuda.current_stream().synchronize()
+        st_raw = self._stats.cpu().numpy().tobytes()
+        me_raw = self._mets.cpu().numpy().tobytes()
+        stats = [SolveStats.from_buffer_copy(st_raw, i * ctypes.sizeof(SolveStats)).to_dict()
+                 for i in range(self.num_items)]
+        mets, off = [], 0
+        for i, k in enumerate(self.ks):
+            row = []
+            for q in range(k):
+                m = MetricsOut.from_buffer_copy(me_raw, (off + q) * ctypes.sizeof(MetricsOut))
+                row.append({f: getattr(m, f) for f, _ in m._fields_})
+            mets.append(row)
+            off += k
+        return stats, mets
+
+    def solve(self):
+        self.solve_async()
+        return self.results()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.fj_batch_destroy(h)
+            self._h = None

@@ -1,0 +1,144 @@
+"""Batched solve (fj_solve_batched) against the FP64 oracle, and its recorded
+hipGraph against eager enqueueing.
+
+The batch mixes directed/weighted and undirected single-vector graphs with a
+multi-vector item; every vector must meet the same certificate as fj_solve
+(Lemma 7 with Alg. 2's shift), and the measures must match the oracle's on
+the exact solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import graphs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+EPS = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dev(g):
+    rp = torch.from_numpy(g.row_ptr).to(DEV)
+    col = torch.from_numpy(g.col).to(DEV)
+    w = None if g.w is None else torch.from_numpy(g.w).to(DEV)
+    return (rp, col, w, g.directed)
+
+
+def _items():
+    single = [
+        synth.chung_lu(3000, 12000, 2.3, 501),
+        synth.chung_lu(5000, 40000, 2.1, 502, directed=True, weighted=True),
+        synth.barabasi_albert(1500, 4, 503),
+        graphs.random_graph(65, 0.1, 504),
+        synth.chung_lu(4000, 20000, 2.2, 505, weighted=True),
+    ]
+    multi = synth.chung_lu(20000, 100000, 2.3, 510)
+    return single, multi
+
+
+def _fill(B, single, multi, k):
+    ss = []
+    for i, g in enumerate(single):
+        s = synth.opinions(g.n, ["uniform", "bimodal", "beta", "exp", "pareto"][i], 600 + i)
+        B.input(i).copy_(torch.from_numpy(s))
+        ss.append(s)
+    sm = np.stack([synth.opinions(multi.n, "beta", 700 + q, a=2, b=2) for q in range(k)], axis=1)
+    B.input(len(single)).copy_(torch.from_numpy(np.ascontiguousarray(sm)))
+    return ss, sm
+
+
+def _check(g, s, z, zt):
+    epsp = 0.5 * EPS
+    assert np.all(np.abs(z - zt) <= epsp * (zt + 1e-5) * (1 + 1e-9) + 1e-15)
+    assert oracle.certificate(g, s, z, EPS) <= 1.0 + 1e-9
+
+
+def test_batched_matches_oracle():
+    import paper_2507_14864_amd as fj
+    single, multi = _items()
+    k = 5
+    B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+    ss, sm = _fill(B, single, multi, k)
+    stats, mets = B.solve()
+    for i, g in enumerate(single):
+        zt = oracle.exact(g, ss[i])
+        z = B.output(i).cpu().numpy()
+        _check(g, ss[i], z, zt)
+        assert stats[i]["certified"] == 1 and stats[i]["max_ratio"] <= 1.0
+        mo = oracle.metrics(g, ss[i], zt)
+        for key in "PDIC":
+            assert abs(mets[i][0][key] - mo[key]) <= 1e-5 * abs(mo[key]), (i, key)
+    zm = B.output(len(single)).cpu().numpy()
+    assert stats[-1]["certified"] == 1
+    for q in range(k):
+        zt = oracle.exact(multi, sm[:, q])
+        _check(multi, sm[:, q], zm[:, q], zt)
+        mo = oracle.metrics(multi, sm[:, q], zt)
+        for key in "PDIC":
+            assert abs(mets[-1][q][key] - mo[key]) <= 1e-5 * abs(mo[key]), (q, key)
+        # the measures reported for the returned z are those of z itself
+        mz = oracle.metrics(multi, sm[:, q], zm[:, q])
+        for key in "PDIC":
+            assert abs(mets[-1][q][key] - mz[key]) <= 1e-10 * abs(mz[key]), (q, key)
+
+
+def test_multi_vector_item_agrees_with_single_solves():
+    import paper_2507_14864_amd as fj
+    g = synth.chung_lu(15000, 80000, 2.3, 520, directed=True, weighted=True)
+    k = 64
+    S = np.stack([synth.opinions(g.n, "uniform", 800 + q) for q in range(k)], axis=1)
+    B = fj.Batch([_dev(g)], [k], eps=EPS, omega=1.1)
+    B.input(0).copy_(torch.from_numpy(np.ascontiguousarray(S)))
+    stats, _ = B.solve()
+    assert stats[0]["certified"] == 1
+    Z = B.output(0).cpu().numpy()
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    for q in (0, 17, 63):
+        z1, _ = fj.solve(G, torch.from_numpy(S[:, q].copy()).to(DEV), eps=EPS, omega=1.1, schedule="sor",
+                         precision="fp64")
+        assert np.max(np.abs(Z[:, q] - z1.cpu().numpy()) / (np.abs(z1.cpu().numpy()) + 1e-5)) <= 2 * EPS
+
+
+def test_recorded_graph_replays_match_eager():
+    import paper_2507_14864_amd as fj
+    single, multi = _items()
+    k = 3
+    B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+    _fill(B, single, multi, k)
+    info = B.tune([1.2, 1.5])
+    assert info["graph_nodes"] > 0 and info["omega"] in (1.2, 1.5)
+    # eager reference: a second batch with the tuned omega and no recorded graph
+    E = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS,
+                 omega=info["omega"])
+    _fill(E, single, multi, k)
+    stats_e, mets_e = E.solve()
+    z_e = [E.output(i).cpu().numpy().copy() for i in range(len(single) + 1)]
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=DEV)  # eager work between replays
+        junk.mul_(2.0).sum().item()
+        stats_g, mets_g = B.solve()
+        for i in range(len(single) + 1):
+            assert np.array_equal(B.output(i).cpu().numpy(), z_e[i]), (rep, i)
+        for i in range(len(single) + 1):
+            assert stats_g[i]["certified"] == 1
+            assert stats_g[i]["rounds"] == stats_e[i]["rounds"]
+            for q in range(len(mets_g[i])):
+                assert mets_g[i][q] == mets_e[i][q]
+
+
+def test_batch_rejects_bad_items():
+    import paper_2507_14864_amd as fj
+    g = synth.chung_lu(1000, 4000, 2.3, 530)
+    bad = synth.CSRGraph(3, np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32), None, False)  # asymmetric
+    with pytest.raises(fj.FJError):
+        fj.Batch([_dev(g), _dev(bad)], [1, 1])
+    with pytest.raises((fj.FJError, ValueError)):
+        fj.Batch([_dev(g)], [65])
