@@ -228,13 +228,21 @@ fj_status fj_batch_io(const fj_batch* b, int32_t item, double** s, double** z);
 fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_omegas, void* stream);
 
 typedef struct {
-    double omega;         /* chosen relaxation factor */
+    double omega;         /* relaxation factor of the last item group */
+    double omega_undirected; /* chosen for the undirected single-vector items (0 if none) */
+    double omega_directed;   /* chosen for the directed single-vector items (0 if none) */
+    double omega_multi;      /* chosen for the first multi-vector item (0 if none) */
     int32_t sweep_budget; /* sweeps recorded per solve */
     int32_t graph_nodes;  /* kernel launches in the recorded hipGraph (0 if none) */
     int32_t num_colours;  /* most colour classes over the items */
     double tune_ms[16];   /* measured time per candidate omega */
 } fj_batch_info;
 fj_status fj_batch_get_info(const fj_batch* b, fj_batch_info* out);
+
+/* Set the relaxation factor per item group by hand (each in (0,2); a value <= 0
+ * leaves that group unchanged) and drop any recorded hipGraph, so that
+ * fj_solve_batched enqueues the kernels directly with the current budget. */
+fj_status fj_batch_set_omegas(fj_batch* b, double omega_undirected, double omega_directed, double omega_multi);
 
 /* Solve every item.  Enqueues only (never synchronizes; uses no host memory):
  * the recorded hipGraph if fj_batch_tune ran, else the kernels directly.

@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* u
 __global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                        const int32_t* __restrict__ pcol, const float* __restrict__ pw,
                                                        SorState S, double* partial, const int32_t* __restrict__ pcomp,
-                                                       int* upd, const int* __restrict__ done,
+                                                       const double* __restrict__ comp_omega, int* upd,
+                                                       const int* __restrict__ done,
                                                        const int* __restrict__ all_done, int* bad) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
@@ -155,14 +156,17 @@ __global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_
         const int c = pcomp[r0 + lane];
         if (!done[c]) {
             bool nf = false;
-            if (sor_row(r0 + lane, sum, S, &nf)) flag_set(&upd[c]);
+            SorState Sc = S;
+            Sc.omega = comp_omega[c];
+            if (sor_row(r0 + lane, sum, Sc, &nf)) flag_set(&upd[c]);
             if (nf) flag_set(bad);
         }
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_usor_heavy(TileView tv, SorState S, const double* __restrict__ partial,
-                                                       const int32_t* __restrict__ pcomp, int* upd,
+                                                       const int32_t* __restrict__ pcomp,
+                                                       const double* __restrict__ comp_omega, int* upd,
                                                        const int* __restrict__ done, const int* __restrict__ all_done,
                                                        int* bad) {
     if (*all_done) return;
@@ -178,7 +182,9 @@ __global__ __launch_bounds__(kBlock) void k_usor_heavy(TileView tv, SorState S, 
     sum = wave_sum(sum);
     if (lane == 0) {
         bool nf = false;
-        if (sor_row(row, sum, S, &nf)) flag_set(&upd[c]);
+        SorState Sc = S;
+        Sc.omega = comp_omega[c];
+        if (sor_row(row, sum, Sc, &nf)) flag_set(&upd[c]);
         if (nf) flag_set(bad);
     }
 }
@@ -599,6 +605,8 @@ struct fj_batch {
     UnionGroup U;
     std::vector<MrhsGroup> M;
     int nslots = 0;
+    std::vector<double> slot_omega;   // relaxation factor per slot (union component or multi-vector item)
+    double* d_slot_omega = nullptr;
     int* upd = nullptr; int* done = nullptr; int* sweeps_done = nullptr; int* all_done = nullptr; int* bad = nullptr;
     fj_solve_stats* stats = nullptr;
     fj_metrics_out* mets = nullptr;
@@ -640,6 +648,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
     }
     const int nm = static_cast<int>(num - ncomp);
     const int nslots = static_cast<int>(ncomp) + nm;
+    double* somega = cv.take<double>(nslots + 1);
     int* upd = cv.take<int>(nslots + 1);
     int* done = cv.take<int>(nslots + 1);
     int* swd = cv.take<int>(nslots + 1);
@@ -650,6 +659,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
     int64_t* mslot = cv.take<int64_t>(num);
     if (b) {
         b->nslots = nslots;
+        b->d_slot_omega = somega;
         b->upd = upd; b->done = done; b->sweeps_done = swd; b->all_done = alld; b->bad = bad;
         b->stats = stats; b->mets = mets; b->metric_slot = mslot; b->total_k = total_k;
     }
@@ -738,13 +748,14 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
                 TileView tv = tile_view(U.g.tiles_p, k);
                 if (tv.ntiles + tv.nchunks > 0) {
                     hipLaunchKernelGGL(k_usor_tiles, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0,
-                                       st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.pcomp, b->upd,
-                                       b->done, b->all_done, b->bad);
+                                       st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.pcomp,
+                                       b->d_slot_omega, b->upd, b->done, b->all_done, b->bad);
                     ++launches;
                 }
                 if (tv.h1 > tv.h0) {
                     hipLaunchKernelGGL(k_usor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv,
-                                       SU, U.partial, U.pcomp, b->upd, b->done, b->all_done, b->bad);
+                                       SU, U.partial, U.pcomp, b->d_slot_omega, b->upd, b->done, b->all_done,
+                                       b->bad);
                     ++launches;
                 }
             }
@@ -752,7 +763,7 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
                 MrhsGroup& G = b->M[m];
                 if (k >= G.g.num_colours) continue;
                 const int slot = U.ncomp + static_cast<int>(m);
-                MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->omega, 1.0 - 1e-6, epsp, G.k};
+                MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->slot_omega[slot], 1.0 - 1e-6, epsp, G.k};
                 TileView tv = tile_view(G.g.tiles_p, k);
                 const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
                 hipLaunchKernelGGL(k_msor_class, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, st,
@@ -810,6 +821,13 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
     if (launches_out) *launches_out = launches;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "enqueue batched solve");
+    return FJ_OK;
+}
+
+fj_status upload_omegas(fj_batch* b, hipStream_t st) {
+    FJ_HIP(hipMemcpyAsync(b->d_slot_omega, b->slot_omega.data(), sizeof(double) * b->nslots, hipMemcpyHostToDevice,
+                          st));
+    FJ_HIP(hipStreamSynchronize(st));
     return FJ_OK;
 }
 
@@ -944,6 +962,11 @@ extern "C" fj_status fj_batch_create(const fj_batch_item_desc* items, int32_t nu
         b->num_colours = std::max(b->num_colours, G.g.num_colours);
     }
     b->budget = 256;
+    b->slot_omega.assign(b->nslots, b->omega);
+    {
+        fj_status rc = upload_omegas(b, st);
+        if (rc) return fail(rc);
+    }
     *out = b;
     return FJ_OK;
 }
@@ -978,6 +1001,13 @@ extern "C" fj_status fj_batch_get_info(const fj_batch* b, fj_batch_info* out) {
     }
     std::memset(out, 0, sizeof(*out));
     out->omega = b->omega;
+    std::vector<int32_t> cdir(b->U.ncomp);
+    if (b->U.ncomp) FJ_HIP(hipMemcpy(cdir.data(), b->U.comp_dir, sizeof(int32_t) * b->U.ncomp, hipMemcpyDeviceToHost));
+    for (int sl = 0; sl < b->U.ncomp; ++sl) {
+        if (cdir[sl]) out->omega_directed = b->slot_omega[sl];
+        else out->omega_undirected = b->slot_omega[sl];
+    }
+    if (!b->M.empty()) out->omega_multi = b->slot_omega[b->U.ncomp];
     out->sweep_budget = b->budget;
     out->graph_nodes = b->graph_nodes;
     out->num_colours = b->num_colours;
@@ -1000,35 +1030,61 @@ extern "C" fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     b->graph_nodes = 0;
     b->tune_ms.assign(n_omegas, 0.0);
-    double best_ms = 1e300, best_omega = b->omega;
-    int best_sweeps = b->budget;
     const int probe_budget = 512;
-    std::vector<int> swd(b->nslots);
+    // sweeps[q][slot]: sweeps slot needed with candidate q (0: did not converge)
+    std::vector<std::vector<int>> sweeps(n_omegas, std::vector<int>(b->nslots, 0));
     for (int q = 0; q < n_omegas; ++q) {
-        b->omega = omegas[q];
-        FJ_HIP(hipStreamSynchronize(st));
+        b->slot_omega.assign(b->nslots, omegas[q]);
+        fj_status rc = upload_omegas(b, st);
+        if (rc) return rc;
         auto t0 = std::chrono::steady_clock::now();
-        fj_status rc = enqueue_solve(b, st, probe_budget, nullptr);
+        rc = enqueue_solve(b, st, probe_budget, nullptr);
         if (rc) return rc;
         FJ_HIP(hipStreamSynchronize(st));
-        double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        FJ_HIP(hipMemcpy(swd.data(), b->sweeps_done, sizeof(int) * b->nslots, hipMemcpyDeviceToHost));
-        int needed = 0, open = 0, hbad = 0;
-        for (int v : swd) { needed = std::max(needed, v); open += (v == 0); }
-        FJ_HIP(hipMemcpy(&hbad, b->bad, sizeof(int), hipMemcpyDeviceToHost));
-        b->tune_ms[q] = ms;
-        if (!open && !hbad && ms < best_ms) {
-            best_ms = ms;
-            best_omega = omegas[q];
-            best_sweeps = needed;
-        }
+        b->tune_ms[q] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        FJ_HIP(hipMemcpy(sweeps[q].data(), b->sweeps_done, sizeof(int) * b->nslots, hipMemcpyDeviceToHost));
     }
-    if (best_ms == 1e300) {
-        set_error("fj_batch_tune: no candidate omega converged within 512 sweeps");
+    // One omega per group: the multi-vector items one each, the undirected and
+    // the directed union components one per kind (their launches are shared,
+    // so each kind is judged by its slowest component).
+    std::vector<int> group(b->nslots);
+    std::vector<int32_t> cdir(b->U.ncomp);
+    if (b->U.ncomp) FJ_HIP(hipMemcpy(cdir.data(), b->U.comp_dir, sizeof(int32_t) * b->U.ncomp, hipMemcpyDeviceToHost));
+    for (int sl = 0; sl < b->nslots; ++sl) group[sl] = sl < b->U.ncomp ? cdir[sl] : 2 + (sl - b->U.ncomp);
+    const int ngroups = 2 + static_cast<int>(b->M.size());
+    b->slot_omega.assign(b->nslots, b->omega);
+    int budget = 0;
+    bool all_ok = true;
+    for (int gidx = 0; gidx < ngroups; ++gidx) {
+        int best_q = -1, best_sw = 1 << 30;
+        bool any = false;
+        for (int q = 0; q < n_omegas; ++q) {
+            int worst = 0;
+            bool ok = true;
+            for (int sl = 0; sl < b->nslots; ++sl) {
+                if (group[sl] != gidx) continue;
+                any = true;
+                if (sweeps[q][sl] == 0) ok = false;
+                worst = std::max(worst, sweeps[q][sl]);
+            }
+            if (ok && worst < best_sw) { best_sw = worst; best_q = q; }
+        }
+        if (!any) continue;
+        if (best_q < 0) { all_ok = false; continue; }
+        for (int sl = 0; sl < b->nslots; ++sl)
+            if (group[sl] == gidx) b->slot_omega[sl] = omegas[best_q];
+        budget = std::max(budget, best_sw);
+    }
+    if (!all_ok) {
+        set_error("fj_batch_tune: some item did not converge within 512 sweeps for any candidate omega");
         return FJ_ERR_NOT_CONVERGED;
     }
-    b->omega = best_omega;
-    b->budget = best_sweeps + std::max(4, best_sweeps / 4);
+    b->omega = b->slot_omega.empty() ? b->omega : b->slot_omega.back();
+    b->budget = budget + std::max(4, budget / 4);
+    {
+        fj_status rc = upload_omegas(b, st);
+        if (rc) return rc;
+    }
     // Record the launch sequence once on a private stream (the caller's may be
     // the null stream, which cannot be captured); fj_solve_batched replays it
     // on the caller's stream.
@@ -1073,4 +1129,22 @@ extern "C" fj_status fj_solve_batched(fj_batch* b, fj_solve_stats* stats_dev, fj
     if (metrics_dev)
         FJ_HIP(hipMemcpyAsync(metrics_dev, b->mets, sizeof(fj_metrics_out) * b->total_k, hipMemcpyDeviceToDevice, st));
     return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_set_omegas(fj_batch* b, double omega_undirected, double omega_directed,
+                                         double omega_multi) {
+    if (!b || omega_undirected >= 2.0 || omega_directed >= 2.0 || omega_multi >= 2.0) {
+        set_error("fj_batch_set_omegas: need a batch and omegas below 2");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    std::vector<int32_t> cdir(b->U.ncomp);
+    if (b->U.ncomp) FJ_HIP(hipMemcpy(cdir.data(), b->U.comp_dir, sizeof(int32_t) * b->U.ncomp, hipMemcpyDeviceToHost));
+    for (int sl = 0; sl < b->nslots; ++sl) {
+        double w = sl < b->U.ncomp ? (cdir[sl] ? omega_directed : omega_undirected) : omega_multi;
+        if (w > 0.0) b->slot_omega[sl] = w;
+    }
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    b->graph_nodes = 0;
+    return upload_omegas(b, nullptr);
 }

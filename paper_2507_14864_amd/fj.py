@@ -283,7 +283,9 @@ class BatchItemDesc(ctypes.Structure):
 
 
 class BatchInfo(ctypes.Structure):
-    _fields_ = [("omega", ctypes.c_double), ("sweep_budget", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
+    _fields_ = [("omega", ctypes.c_double), ("omega_undirected", ctypes.c_double),
+                ("omega_directed", ctypes.c_double), ("omega_multi", ctypes.c_double),
+                ("sweep_budget", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
                 ("num_colours", ctypes.c_int32), ("tune_ms", ctypes.c_double * 16)]
 
 
@@ -303,6 +305,8 @@ def _batch_lib():
         L.fj_batch_tune.restype = i32
         L.fj_batch_get_info.argtypes = [vp, P(BatchInfo)]
         L.fj_batch_get_info.restype = i32
+        L.fj_batch_set_omegas.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.fj_batch_set_omegas.restype = i32
         L.fj_solve_batched.argtypes = [vp, vp, vp, vp]
         L.fj_solve_batched.restype = i32
         L._batch_ready = True
@@ -365,6 +369,11 @@ class Batch:
         arr = (ctypes.c_double * len(omegas))(*omegas)
         _check(_batch_lib().fj_batch_tune(self._h, arr, len(omegas), _stream()))
         return self.info()
+
+    def set_omegas(self, undirected=0.0, directed=0.0, multi=0.0):
+        """Per-group relaxation factors (<= 0 keeps a group's value); drops
+        the recorded graph."""
+        _check(_batch_lib().fj_batch_set_omegas(self._h, float(undirected), float(directed), float(multi)))
 
     def info(self) -> dict:
         out = BatchInfo()

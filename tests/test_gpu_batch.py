@@ -114,11 +114,14 @@ def test_recorded_graph_replays_match_eager():
     B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
     _fill(B, single, multi, k)
     info = B.tune([1.2, 1.5])
-    assert info["graph_nodes"] > 0 and info["omega"] in (1.2, 1.5)
-    # eager reference: a second batch with the tuned omega and no recorded graph
-    E = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS,
-                 omega=info["omega"])
+    assert info["graph_nodes"] > 0
+    for key in ("omega_undirected", "omega_directed", "omega_multi"):
+        assert info[key] in (1.2, 1.5)
+    # eager reference: a second batch with the tuned omegas set by hand and no
+    # recorded graph (kernels enqueued directly)
+    E = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
     _fill(E, single, multi, k)
+    E.set_omegas(info["omega_undirected"], info["omega_directed"], info["omega_multi"])
     stats_e, mets_e = E.solve()
     z_e = [E.output(i).cpu().numpy().copy() for i in range(len(single) + 1)]
     for rep in range(3):
