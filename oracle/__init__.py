@@ -187,6 +187,20 @@ def certificate(g, s, z, eps: float, sigma: float = 1e-5, c: float = 1e-5) -> fl
     return float(np.max(np.abs(r) / h)) if g.n else 0.0
 
 
+def fj_iterate(g, s, z, steps: int) -> np.ndarray:
+    """`steps` synchronous applications of the FJ update, Eq. (1):
+    z_i <- (s_i + sum_j a_ij z_j) / (1 + sum_j a_ij)."""
+    z = np.array(z, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    d = degrees(g)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    w = np.ones(g.nnz) if g.w is None else g.w.astype(np.float64)
+    for _ in range(steps):
+        acc = np.bincount(rows, weights=w * z[g.col], minlength=g.n)
+        z = (s + acc) / (1.0 + d)
+    return z
+
+
 def max_rel_error(z_est, z_true, floor: float = 1e-5) -> float:
     """max over v with z_true_v >= floor of |z_est_v - z_true_v| / z_true_v
     (the error measure of Sec. 6 restricted as in the ImprovedBLI lemma)."""

@@ -414,3 +414,92 @@ class Batch:
         if h is not None and _LIB is not None:
             _LIB.fj_batch_destroy(h)
             self._h = None
+
+
+# ------------------------------------------------------------ learned warm start
+def _net_lib():
+    L = lib()
+    if not getattr(L, "_net_ready", False):
+        vp, i32, sz, fl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_float
+        L.fj_wsnet_param_count.restype = i32
+        L.fj_wsnet_workspace_bytes.argtypes = [vp, i32]
+        L.fj_wsnet_workspace_bytes.restype = sz
+        L.fj_wsnet_forward.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.fj_wsnet_forward.restype = i32
+        L.fj_wsnet_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.fj_wsnet_grad.restype = i32
+        L.fj_wsnet_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, fl, vp, vp, sz, vp]
+        L.fj_wsnet_train_step.restype = i32
+        L.fj_jacobi_workspace_bytes.argtypes = [vp]
+        L.fj_jacobi_workspace_bytes.restype = sz
+        L.fj_jacobi_steps.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+        L.fj_jacobi_steps.restype = i32
+        L._net_ready = True
+    return L
+
+
+def wsnet_param_count() -> int:
+    return int(_net_lib().fj_wsnet_param_count())
+
+
+def _net_ws(graph: Graph, training: bool) -> torch.Tensor:
+    attr = "_net_ws_train" if training else "_net_ws_inf"
+    nbytes = _net_lib().fj_wsnet_workspace_bytes(graph.handle, 1 if training else 0)
+    ws = getattr(graph, attr, None)
+    if ws is None or ws.numel() < nbytes:
+        ws = _workspace(nbytes, graph.device)
+        setattr(graph, attr, ws)
+    return ws
+
+
+def wsnet_forward(graph: Graph, s: torch.Tensor, params: torch.Tensor, out: Optional[torch.Tensor] = None):
+    """Warm-start proposal z0 (FP64 [n]) from the network with FP32 params."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(params, torch.float32, wsnet_param_count(), "params")
+    z0 = out if out is not None else torch.empty(n, dtype=torch.float64, device=graph.device)
+    ws = _net_ws(graph, False)
+    _check(_net_lib().fj_wsnet_forward(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(params.data_ptr()),
+                                       ctypes.c_void_p(z0.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream()))
+    return z0
+
+
+def wsnet_grad(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, params: torch.Tensor):
+    """(loss, grad) of the mean squared error of z0 against z_target."""
+    n = graph.n
+    _dev_ptr(z_target, torch.float64, n, "z_target")
+    grad = torch.empty(wsnet_param_count(), dtype=torch.float32, device=graph.device)
+    loss = torch.empty(1, dtype=torch.float32, device=graph.device)
+    ws = _net_ws(graph, True)
+    _check(_net_lib().fj_wsnet_grad(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z_target.data_ptr()),
+                                    ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                    ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream()))
+    return loss, grad
+
+
+def wsnet_train_step(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, params: torch.Tensor,
+                     m: torch.Tensor, v: torch.Tensor, step: int, lr: float) -> torch.Tensor:
+    """One Adam step in place on params (m, v: moment buffers).  Returns the
+    loss (device scalar) of the forward pass before the step."""
+    loss = torch.empty(1, dtype=torch.float32, device=graph.device)
+    ws = _net_ws(graph, True)
+    _check(_net_lib().fj_wsnet_train_step(graph.handle, ctypes.c_void_p(s.data_ptr()),
+                                          ctypes.c_void_p(z_target.data_ptr()), ctypes.c_void_p(params.data_ptr()),
+                                          ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(step),
+                                          float(lr), ctypes.c_void_p(loss.data_ptr()),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return loss
+
+
+def jacobi_steps(graph: Graph, s: torch.Tensor, z: torch.Tensor, steps: int) -> torch.Tensor:
+    """In place: `steps` synchronous FJ updates (Eq. (1)) of z."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(z, torch.float64, n, "z")
+    nbytes = _net_lib().fj_jacobi_workspace_bytes(graph.handle)
+    ws = _workspace(nbytes, graph.device)
+    _check(_net_lib().fj_jacobi_steps(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                      int(steps), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return z

@@ -1,0 +1,92 @@
+"""Learned warm start on the GPU (an extension, not the paper's method).
+
+The network's kernels are checked against the FP64 reference in
+oracle/mpnn.py (BF16 tolerance); training must reduce the loss; and a start
+proposed by the network must reach the same residual certificate as the cold
+start (Lemma 4: any start is valid; Lemma 7: the certificate decides).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mpnn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _setup(n=6000, m=40000, seed=901):
+    import paper_2507_14864_amd as fj
+    g = synth.chung_lu(n, m, 2.1, seed, directed=True, weighted=True)
+    s = synth.opinions(g.n, "bimodal", seed + 1)
+    G = fj.Graph.from_host(g, DEV)
+    return fj, g, s, G
+
+
+def test_forward_matches_reference():
+    fj, g, s, G = _setup()
+    p = mpnn.init_params(3)
+    p[mpnn.N_PARAMS - 1] = 0.2
+    z_ref = mpnn.forward(g, s, p)["z0"]
+    z = fj.wsnet_forward(G, torch.from_numpy(s).to(DEV), torch.from_numpy(p.astype(np.float32)).to(DEV))
+    z = z.cpu().numpy()
+    span = s.max() - s.min()
+    assert np.max(np.abs(z - z_ref)) <= 2e-2 * span
+    assert np.corrcoef(z, z_ref)[0, 1] >= 0.999
+
+
+def test_gradient_matches_reference():
+    fj, g, s, G = _setup(n=4000, m=24000, seed=911)
+    p = mpnn.init_params(4)
+    zt = oracle.exact(g, s)
+    loss_ref, grad_ref = mpnn.loss_and_grad(g, s, p, zt)
+    loss, grad = fj.wsnet_grad(G, torch.from_numpy(s).to(DEV), torch.from_numpy(zt).to(DEV),
+                               torch.from_numpy(p.astype(np.float32)).to(DEV))
+    assert abs(float(loss.item()) - loss_ref) <= 2e-2 * loss_ref
+    grad = grad.cpu().numpy().astype(np.float64)
+    offs = {"W1": (0, 1024), "b1": (1024, 1088), "W2": (1088, 9280), "b2": (9280, 9344), "u": (9344, 9408),
+            "c0": (9408, 9409)}
+    for name, (a, b) in offs.items():
+        ref = grad_ref[a:b]
+        scale = max(np.max(np.abs(ref)), 1e-12)
+        assert np.max(np.abs(grad[a:b] - ref)) <= 5e-2 * scale, name
+        if b - a > 1:
+            assert np.corrcoef(grad[a:b], ref)[0, 1] >= 0.99, name
+
+
+def test_training_reduces_loss_and_start_is_certified():
+    fj, g, s, G = _setup(n=20000, m=160000, seed=921)
+    sd = torch.from_numpy(s).to(DEV)
+    zt, _ = fj.solve(G, sd, eps=1e-6, omega=1.0, schedule="push", precision="fp64")
+    params = torch.from_numpy(mpnn.init_params(5).astype(np.float32)).to(DEV)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    losses = []
+    for step in range(1, 201):
+        loss = fj.wsnet_train_step(G, sd, zt, params, m, v, step, 3e-3)
+        losses.append(float(loss.item()))
+    assert losses[-1] < 0.5 * losses[0]
+    z0 = fj.wsnet_forward(G, sd, params)
+    zc = z0.cpu().numpy()
+    assert zc.min() >= s.min() - 1e-12 and zc.max() <= s.max() + 1e-12
+    z, st = fj.solve(G, sd, eps=1e-4, omega=1.0, schedule="push", z0=z0)
+    assert st["certified"] == 1
+    zx = oracle.exact(g, s)
+    assert oracle.max_rel_error(z.cpu().numpy(), zx) <= 1e-4
+
+
+def test_jacobi_steps_match_equation_one():
+    fj, g, s, G = _setup(n=5000, m=30000, seed=931)
+    sd = torch.from_numpy(s).to(DEV)
+    z = sd.clone()
+    fj.jacobi_steps(G, sd, z, 5)
+    want = oracle.fj_iterate(g, s, s, 5)
+    assert np.max(np.abs(z.cpu().numpy() - want)) <= 1e-13

@@ -329,3 +329,16 @@ def test_certificate_bounds_relative_error():
     # a perturbed z fails it
     bad = zt * (1 + 3e-4)
     assert oracle.certificate(g, s, bad, 1e-4) > 1.0
+
+
+def test_fj_iterate_is_equation_one():
+    """One synchronous step of Eq. (1) by hand on a weighted directed path, and
+    many steps converge to the equilibrium of Lemma 1."""
+    g = graphs.chain(4, 0.5)
+    s = np.array([0.2, 0.4, 0.6, 0.8])
+    z = np.array([1.0, 0.0, 1.0, 0.0])
+    want = np.array([(0.2 + 0.5 * 0.0) / 1.5, (0.4 + 0.5 * 1.0) / 1.5, (0.6 + 0.5 * 0.0) / 1.5, 0.8])
+    assert np.allclose(oracle.fj_iterate(g, s, z, 1), want, atol=1e-15)
+    g2 = synth.chung_lu(2000, 9000, 2.3, 131, directed=True, weighted=True)
+    s2 = synth.opinions(g2.n, "uniform", 132)
+    assert np.max(np.abs(oracle.fj_iterate(g2, s2, s2, 400) - oracle.exact(g2, s2))) <= 1e-9
