@@ -99,6 +99,33 @@ def cpu_baseline(wl, budget_s):
                        f"({p['edge_visits']} edge visits); scaled x{scale:.1f} by arc count")
 
 
+def warm_start_eval(dev):
+    """Warm vs cold start on the held-out directed graph (5M nodes, 50M arc
+    samples, bimodal opinions) with the stored network weights: time to the
+    same certificate (eps 1e-4, omega 1.1), inference included, beside the
+    untrained controls z0 = s and z0 = k FJ steps (Eq. (1))."""
+    import torch
+    import paper_2507_14864_amd as fj
+    from paper_2507_14864_amd import warmstart
+    params = warmstart.load_params(dev)
+    if params is None:
+        return None
+    g, s = warmstart.heldout_problem()
+    G = fj.Graph.from_host(g, dev, colour=True)
+    sd = torch.from_numpy(s).to(dev)
+    res = warmstart.evaluate(G, sd, params, eps=1e-4, omega=1.1, jacobi=(2, 4))
+    out = {"workload": "directed Chung-Lu n=5M, 50M arc samples, exponent 2.1, weights U[0.5,1.5], bimodal s",
+           "omega": 1.1, "cold_s": round(res["cold"]["s"], 5), "net_s": round(res["net"]["s"], 5),
+           "net_inference_s": round(res["net"]["inference_s"], 5),
+           "sweeps": {k: v["sweeps"] for k, v in res.items() if isinstance(v, dict)},
+           "speedup_vs_cold": round(res["speedup_net_vs_cold"], 3),
+           "speedup_vs_best_untrained_control": round(res["speedup_net_vs_best_control"], 3),
+           "controls_s": {k: round(v["s"], 5) for k, v in res.items() if k.startswith("z0=")}}
+    del G
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_inputs():
     """64 vectors (22 U[0,1], 21 Beta(2,2), 21 bimodal; seeds 400-463) on an
     undirected Chung-Lu graph with 2M nodes and 20M edge samples (gamma 2.3,
@@ -188,6 +215,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the learned warm start evaluation on the held-out 5M-node directed graph")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--persistent", action="store_true",
@@ -266,6 +295,11 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration kernel: 1073741824 bytes read, 1073741824 bytes written ({float(b[0])})")
 
+    warm = None
+    if not args.no_warm_start and args.workload == "cl10m":
+        warm = warm_start_eval(dev)
+        log(f"warm start: {warm}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_budget)
@@ -292,6 +326,7 @@ def main():
                    "metrics": {k: m[k] for k in ("P", "D", "I", "C")}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "warm_start": warm,
     }
     print(json.dumps(out), flush=True)
 
