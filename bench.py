@@ -12,12 +12,14 @@ reported separately.
 Prints one JSON line (rank 0).  Diagnostics go to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+HERE = ROOT
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
@@ -55,19 +57,51 @@ def make_input(wl):
 def algorithmic_bytes(schedule, stats, n, nnz, weighted):
     """Bytes the iteration kernel must move, without cache reuse.
 
-    SOR class sweep (pull): per row scanned 36 B (row_ptr 4, s' 8, 1+d 8,
-    zhat' read 8, 1/(1+d) 8 folded in as read), per updated row 8 B (zhat'
-    write), per arc 12 B (col 4 + FP64 gather 8), +4 B with weights.
+    Colour-class sweep (pull form): per row scanned 28 B (row_ptr 4, s' 8,
+    1+d 8, own zhat' 8); per updated row 20 B (1/(1+d) 8, zhat' write 8,
+    fixed-point copy write 4); per arc 4 B column index plus the gathered
+    value, 8 B (FP64) or 4 B in the sweeps that gather the fixed-point copy
+    (heavy rows read 8 B there too: counted as 4, so the figure is low);
+    +4 B per arc with weights.
     Push round: per node scanned 8 B (r, h), per push 44 B (row_ptr 8, r
-    exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + r atomic
-    RMW 8), +4 B with weights."""
-    per_arc = 16 if weighted else 12
+    exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + residual
+    atomic RMW 8), +4 B with weights."""
     if schedule == "sor":
-        # sweeps that gathered the 32-bit fixed-point copy move 4 B less per arc
-        rows = stats["rounds"] * n
+        arcs = stats["edge_visits"]
         mirror_arcs = stats.get("mirror_rounds", 0) * nnz
-        return 36 * rows + 12 * stats["pushes"] + per_arc * stats["edge_visits"] - 4 * mirror_arcs
+        gather = 8 * (arcs - mirror_arcs) + 4 * mirror_arcs
+        return 28 * stats["rounds"] * n + 20 * stats["pushes"] + 4 * arcs + gather + (4 * arcs if weighted else 0)
+    per_arc = 16 if weighted else 12
     return 8 * stats["rounds"] * n + 44 * stats["pushes"] + per_arc * stats["edge_visits"]
+
+
+KERNEL_SOURCES = ("fj_sor.h", "fj_tile.h", "fj_device.h")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_sor_class_cl10m_pmc.txt")
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_2507_14864_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM-side bytes per launch of the sweep kernel from the committed
+    FETCH_SIZE/WRITE_SIZE counter summary, or None when the kernel sources
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            fields = dict(line.split(":", 1) for line in f if ":" in line)
+    except OSError:
+        return None
+    if fields.get("kernel_sources_sha256", "").strip() != kernel_sources_hash():
+        return None
+    try:
+        return int(float(fields["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, budget_s):
@@ -281,8 +315,9 @@ def main():
         avg_ms = stp["kernel_ms"] / launches
         achieved = bytes_total / (stp["kernel_ms"] * 1e-3) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                        kernel="k_sor_tiles+k_sor_heavy" if args.schedule == "sor" else "k_push_light+k_push_heavy",
+                        frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=measured_traffic() if args.schedule == "sor" and args.workload == "cl10m" else None,
+                        kernel="k_sor_class" if args.schedule == "sor" else "k_push_light+k_push_heavy",
                         bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
                         launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))
         log(f"profiled step: {stp}")

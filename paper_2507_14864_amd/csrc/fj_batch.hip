@@ -729,10 +729,11 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
     ++launches;
     UnionGroup& U = b->U;
     const double epsp = b->epsp;
-    SorState SU{U.sp, U.g.popd, U.g.pinv64, U.zh, U.zq, b->omega, 1.0 - 1e-6, epsp};
+    SorState SU{U.sp, U.g.popd, U.g.pinv64, U.zh, U.zq, b->omega, 1.0 - 1e-6, epsp, nullptr, nullptr};
     if (b->has_union && U.n > 0) {
         hipLaunchKernelGGL(k_sor_init, dim3(g1d(U.n, bs)), dim3(bs), 0, st, U.n, U.g.perm, U.s_in,
-                           static_cast<const double*>(nullptr), b->c, U.sp, U.zh, U.zq, b->bad);
+                           static_cast<const double*>(nullptr), b->c, U.sp, U.zh, U.zq, b->bad,
+                           static_cast<unsigned long long*>(nullptr));
         ++launches;
     }
     for (auto& G : b->M) {

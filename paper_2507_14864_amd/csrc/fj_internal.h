@@ -54,6 +54,11 @@ struct Carver {
 constexpr int kArcBudget = 256;
 // rows longer than this are reduced by a whole block in the persistent sweep
 constexpr int kBigRow = 2048;
+// heavy-row chunks combined inside one sweep launch: the low kPackedCountBits
+// of a row's 64-bit accumulator count arrivals, so a row may have at most
+// kMaxPackedChunks chunks for its colour class to be swept in one launch
+constexpr int kPackedCountBits = 12;
+constexpr int kMaxPackedChunks = (1 << kPackedCountBits) - 1;
 
 struct TileSet {
     int64_t ntiles = 0, nheavy = 0, nchunks = 0;
@@ -119,6 +124,7 @@ struct fj_graph {
     // colour-ordered copy (FJ_GRAPH_COLOUR)
     int32_t num_colours = 0, colour_rounds = 0;
     std::vector<int64_t> class_off;  // [num_colours + 1] host copy
+    std::vector<uint8_t> class_packed;  // [num_colours] 1: no heavy row has more than kMaxPackedChunks chunks
     int32_t* colour = nullptr;       // [n] original labels
     int32_t* perm = nullptr;         // new -> old
     int32_t* iperm = nullptr;        // old -> new

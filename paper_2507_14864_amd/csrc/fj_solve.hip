@@ -398,6 +398,7 @@ struct SolveLayout {
     int* flags; int* one; int* bad; unsigned long long* stats;
     double* partial; void* heavy_coef; unsigned* barrier; int* abort;
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
+    unsigned long long* hacc; unsigned long long* zmax_bits;
 };
 
 int64_t cert_parts(const fj_graph* g) {
@@ -423,6 +424,8 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     int64_t nch = std::max(g->tiles_a.nchunks, g->tiles_p.nchunks) + 1;
     L.partial = cv.take<double>(nch);
     L.heavy_coef = cv.take<char>(tsz * (g->tiles_t.nheavy + 1));
+    L.hacc = cv.take<unsigned long long>(g->tiles_p.nheavy + 1);
+    L.zmax_bits = cv.take<unsigned long long>(1);
     int64_t nb = cert_parts(g);
     L.part_max = cv.take<double>(nb);
     L.part_viol = cv.take<long long>(nb);
@@ -624,9 +627,11 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                     const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
     const int64_t n = g->n;
     const int bs = 256;
+    FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (g->tiles_p.nheavy + 1), st));
+    FJ_HIP(hipMemsetAsync(L.zmax_bits, 0, sizeof(unsigned long long), st));
     if (n > 0)
         hipLaunchKernelGGL(k_sor_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, s, o->z0, o->c, L.sp, L.zh,
-                           L.zq, L.bad);
+                           L.zq, L.bad, L.zmax_bits);
     int hbad = 0;
     FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
@@ -669,7 +674,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     sa.pw = g->pw;
     // FP64 sweeps: the margin of 1e-6 h keeps a quiet sweep certified under the
     // FP64 rounding of the standalone certificate (different summation order).
-    SorState S64{L.sp, g->popd, g->pinv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp};
+    SorState S64{L.sp, g->popd, g->pinv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp, L.hacc, L.zmax_bits};
     // Fixed-point sweeps: light rows gather the 32-bit copy, whose error per
     // arc is <= 4.7e-10; a 5% margin on h makes it likely that the FP64
     // certificate holds when these sweeps go quiet.  FP64 sweeps follow if not.
@@ -724,25 +729,36 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * K, st));
             for (int b = 0; b < K; ++b) {
                 int* cur = L.flags + sweeps + b;
+                const int* prev = b > 0 ? cur - 1 : nullptr;
                 for (int k = 0; k < nc; ++k) {
                     const TileView& tv = views[k];
                     if (tv.ntiles == 0) continue;
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
                     const SorState& S = mirror ? SMIR : S64;
-                    if (mirror)
-                        hipLaunchKernelGGL(k_sor_tiles<true>, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)),
-                                           dim3(kBlock), 0, st, tv, g->prow_ptr, g->pcol, g->pw, S, L.partial, cur,
-                                           L.bad, L.stats);
-                    else
-                        hipLaunchKernelGGL(k_sor_tiles<false>, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)),
-                                           dim3(kBlock), 0, st, tv, g->prow_ptr, g->pcol, g->pw, S, L.partial, cur,
-                                           L.bad, L.stats);
-                    ++launches;
-                    if (tv.h1 > tv.h0) {
-                        hipLaunchKernelGGL(k_sor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st,
-                                           tv, S, L.partial, cur, L.bad, L.stats);
+                    if (g->class_packed[k]) {
+                        const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
+                        if (mirror)
+                            hipLaunchKernelGGL(k_sor_class<true>, dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
+                                               g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                        else
+                            hipLaunchKernelGGL(k_sor_class<false>, dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
+                                               g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
                         ++launches;
+                    } else {
+                        const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
+                        if (mirror)
+                            hipLaunchKernelGGL(k_sor_tiles<true>, dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
+                                               g->pcol, g->pw, S, L.partial, prev, cur, L.bad, L.stats);
+                        else
+                            hipLaunchKernelGGL(k_sor_tiles<false>, dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
+                                               g->pcol, g->pw, S, L.partial, prev, cur, L.bad, L.stats);
+                        ++launches;
+                        if (tv.h1 > tv.h0) {
+                            hipLaunchKernelGGL(k_sor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0,
+                                               st, tv, S, L.partial, prev, cur, L.bad, L.stats);
+                            ++launches;
+                        }
                     }
                     rc0 = timer.after();
                     if (rc0) return rc0;

@@ -43,35 +43,49 @@ struct SorState {
     double omega;
     double thr;          // update iff |r| > thr * eps' s'
     double epsp;
+    unsigned long long* hacc;             // per heavy row: packed fixed-point sum and chunk count
+    const unsigned long long* zmax_bits;  // bits of max |zhat'| at the start (a nonnegative double)
 };
 
 __global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ s,
-                           const double* __restrict__ z0, double c, double* sp, double* zh, int32_t* zq, int* bad) {
+                           const double* __restrict__ z0, double c, double* sp, double* zh, int32_t* zq, int* bad,
+                           unsigned long long* zmax_bits) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t o = perm[i];
-    double si = s[o];
-    if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
-    sp[i] = si + c;
-    double z = 0.0;
-    if (z0) {
-        double zi = z0[o];
-        if (!isfinite(zi)) flag_set(bad);
-        z = zi + c;
+    double m = 0.0;
+    if (i < n) {
+        int32_t o = perm[i];
+        double si = s[o];
+        if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
+        sp[i] = si + c;
+        double z = 0.0;
+        if (z0) {
+            double zi = z0[o];
+            if (!isfinite(zi)) flag_set(bad);
+            z = zi + c;
+        }
+        zh[i] = z;
+        zq[i] = fix_enc(z);
+        m = fmax(si + c, fabs(z));
+        if (!isfinite(m)) m = 0.0;
     }
-    zh[i] = z;
-    zq[i] = fix_enc(z);
+    if (zmax_bits) {
+        m = wave_max(m);
+        // nonnegative doubles order like their bit patterns
+        if (lane_id() == 0 && m > 0.0) atomicMax(zmax_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+    }
 }
 
+// The row's own data is touched once per sweep: streaming (nontemporal) loads
+// and stores keep it from displacing the gathered values in L2.
 __device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S, bool* nonfinite) {
-    double z = S.zh[i];
+    double z = __builtin_nontemporal_load(&S.zh[i]);
     double sp = __builtin_nontemporal_load(&S.sp[i]);
     double ri = sp - __builtin_nontemporal_load(&S.popd[i]) * z + sum;
     *nonfinite = !isfinite(ri);
     if (fabs(ri) > S.thr * S.epsp * sp) {
-        z += S.omega * ri * S.pinv[i];
-        S.zh[i] = z;
-        S.zq[i] = fix_enc(z);
+        z += S.omega * ri * __builtin_nontemporal_load(&S.pinv[i]);
+        __builtin_nontemporal_store(z, &S.zh[i]);
+        __builtin_nontemporal_store(fix_enc(z), &S.zq[i]);
         return true;
     }
     return false;
@@ -80,10 +94,11 @@ __device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S
 template <bool MIRROR>
 __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
-                                                      SorState S, double* partial, int* updated, int* bad,
-                                                      unsigned long long* stats) {
+                                                      SorState S, double* partial, const int* prev, int* updated,
+                                                      int* bad, unsigned long long* stats) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
+    if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
     const int wid = threadIdx.x >> 6, lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     const double* __restrict__ zh = S.zh;
@@ -124,8 +139,97 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
     }
 }
 
+// Heavy rows inside one launch.  Every chunk wave converts its FP64 partial
+// sum to a fixed-point integer with a per-row power-of-two scale (chosen from
+// the row's weighted degree and a bound on |zhat'| so that the row total fits
+// in 50 bits) and adds (q << kPackedCountBits) + 1 to the row's 64-bit accumulator.
+// Integer addition is associative, so the total does not depend on the order
+// in which the chunks arrive; the wave whose addition completes the count owns
+// the total, updates the row and clears the accumulator for the next launch.
+// A partial outside the scaled range flags the sweep as diverged.
+__device__ __forceinline__ int heavy_scale_exp(double d, const unsigned long long* zmax_bits) {
+    double zb = 4.0 * __longlong_as_double(static_cast<long long>(*zmax_bits));
+    double bound = fmax(d * zb, 1e-300);
+    return 50 - static_cast<int>(ceil(log2(bound)));
+}
+
+// One colour class in a single launch: the first nchunks waves each sum one
+// heavy-row chunk (combined as above), the rest take one light tile each.
+// Used when no heavy row of the class has more than kMaxPackedChunks chunks.
+// A sweep that follows a quiet sweep (no row updated) would change nothing:
+// when *prev is 0 the launch returns at once.
+template <bool MIRROR>
+__global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t* __restrict__ prow_ptr,
+                                                      const int32_t* __restrict__ pcol, const float* __restrict__ pw,
+                                                      SorState S, const int* prev, int* updated, int* bad,
+                                                      unsigned long long* stats) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const double* __restrict__ zh = S.zh;
+    const int32_t* __restrict__ zq = S.zq;
+    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (wv < tv.nchunks) {  // heavy rows always gather FP64
+        auto arc64 = [&](int k) {
+            double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+            return a * zh[__builtin_nontemporal_load(&pcol[k])];
+        };
+        const int64_t cidx = tv.c0 + wv;
+        const int32_t h = tv.chunk_heavy[cidx];
+        const int32_t row = tv.heavy_row[h];
+        const int beg = tv.chunk_beg[cidx];
+        const int end = min(beg + kArcBudget, prow_ptr[row + 1]);
+        const double part = chunk_sum(beg, end, arc64);
+        if (lane == 0) {
+            const int nch = tv.heavy_chunk0[h + 1] - tv.heavy_chunk0[h];
+            const int e = heavy_scale_exp(S.popd[row] - 1.0, S.zmax_bits);
+            const double qd = rint(ldexp(part, e));
+            if (!(fabs(qd) <= 1125899906842624.0)) flag_set(bad);  // 2^50, or not finite
+            const long long q = static_cast<long long>(fmin(fmax(qd, -1125899906842624.0), 1125899906842624.0));
+            const unsigned long long add = (static_cast<unsigned long long>(q) << kPackedCountBits) + 1ull;
+            const unsigned long long old = atomicAdd(&S.hacc[h], add);
+            if (static_cast<int>(old & static_cast<unsigned long long>(kMaxPackedChunks)) + 1 == nch) {
+                const long long tot = static_cast<long long>(old + add) >> kPackedCountBits;
+                atomicExch(&S.hacc[h], 0ull);
+                bool nonfinite = false;
+                bool upd = sor_row(row, ldexp(static_cast<double>(tot), -e), S, &nonfinite);
+                if (nonfinite) flag_set(bad);
+                if (upd) {
+                    flag_set(updated);
+                    stripe_add(stats, 0, 1ull);
+                }
+            }
+        }
+        return;
+    }
+    wv -= tv.nchunks;
+    if (wv >= tv.ntiles) return;
+    const int64_t tix = tv.t0 + wv;
+    if (tv.tile_heavy[tix] >= 0) return;  // taken by the chunk waves
+    auto arc_light = [&](int k) {
+        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+        int j = __builtin_nontemporal_load(&pcol[k]);
+        if constexpr (MIRROR) return a * fix_dec(zq[j]);
+        else return a * zh[j];
+    };
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc_light);
+    bool upd = false, nonfinite = false;
+    if (lane < nrows) upd = sor_row(r0 + lane, sum, S, &nonfinite);
+    uint64_t um = __ballot(upd);
+    if (__ballot(nonfinite) && lane == 0) flag_set(bad);
+    if (um && lane == 0) {
+        flag_set(updated);
+        stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, SorState S, const double* __restrict__ partial,
-                                                      int* updated, int* bad, unsigned long long* stats) {
+                                                      const int* prev, int* updated, int* bad,
+                                                      unsigned long long* stats) {
+    if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
     const int wid = threadIdx.x >> 6, lane = lane_id();
     int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;

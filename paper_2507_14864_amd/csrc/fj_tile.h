@@ -81,18 +81,22 @@ __device__ __forceinline__ double chunk_sum(int beg, int end, F f) {
     return wave_sum(acc);
 }
 
-// FP64 sum of f(k) over arcs [beg, end) by a whole block, in a fixed order.
-// Every thread of the block must call it; the total is returned to all.
-template <typename F>
+// FP64 sum of f(k) over arcs [beg, end) by a whole block, in a fixed order:
+// each thread takes U arcs per step (all U loads in flight together, the
+// last step predicated), then a fixed butterfly per wave and the waves in
+// index order.  Every thread of the block must call it; the total is
+// returned to all.
+template <int U = 4, typename F>
 __device__ __forceinline__ double block_arc_sum(int beg, int end, double* lds /*[blockDim/64]*/, F f) {
     double acc = 0.0;
     const int nt = blockDim.x;
-    int k = beg + static_cast<int>(threadIdx.x);
-    for (; k + 3 * nt < end; k += 4 * nt) {
-        double a0 = f(k), a1 = f(k + nt), a2 = f(k + 2 * nt), a3 = f(k + 3 * nt);
-        acc += a0; acc += a1; acc += a2; acc += a3;
+    for (int k = beg + static_cast<int>(threadIdx.x); k < end; k += U * nt) {
+        double a[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) a[j] = k + j * nt < end ? f(k + j * nt) : 0.0;
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc += a[j];
     }
-    for (; k < end; k += nt) acc += f(k);
     acc = wave_sum(acc);
     const int w = threadIdx.x >> 6, nw = nt >> 6;
     __syncthreads();

@@ -257,3 +257,51 @@ def test_sor_persistent_and_per_class_launches_agree(directed):
     check_solution(g, s, z2, zt, 1e-5)
     assert abs(st1["rounds"] - st2["rounds"]) <= 1
     assert np.max(np.abs(z1.cpu().numpy() - z2.cpu().numpy())) <= 1e-9
+
+
+@pytest.mark.parametrize("directed,precision", [(False, "fp32"), (True, "fp32"), (False, "fp64")])
+def test_sor_repeat_is_bitwise_identical(directed, precision):
+    """Heavy rows are split into chunks whose partial sums are combined in
+    fixed point, so the order in which chunks finish cannot change a bit of
+    the result: two solves of the same problem return the same z and stats."""
+    fj = fjmod()
+    g = synth.chung_lu(200000, 4000000, 2.1, 95 + directed, directed=directed, weighted=directed)
+    assert np.diff(g.row_ptr).max() > 4 * 256  # rows of several chunks
+    s = synth.opinions(g.n, "bimodal", 96)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    omega = 1.6 if not directed else 1.2
+    z1, st1 = fj.solve(G, sd, eps=1e-6, omega=omega, schedule="sor", precision=precision)
+    z1 = z1.clone()
+    z2, st2 = fj.solve(G, sd, eps=1e-6, omega=omega, schedule="sor", precision=precision)
+    assert torch.equal(z1, z2)
+    for key in ("rounds", "pushes", "certified"):
+        assert st1[key] == st2[key], key
+    check_solution(g, s, z2, oracle.exact(g, s), 1e-6)
+
+
+def test_sor_star_beyond_packed_chunk_count():
+    """A hub with more arcs than the one-launch sweep combines (4095 chunks of
+    256) is swept by the two-launch path; its solution has a closed form:
+    leaves satisfy 2 z_i - z_0 = s_i and the hub (1 + m) z_0 - sum z_i = s_0."""
+    fj = fjmod()
+    m = 4095 * 256 + 1000
+    n = m + 1
+    rp = np.zeros(n + 1, np.int64)
+    rp[1] = m
+    rp[2:] = m + np.arange(1, m + 1)
+    col = np.empty(2 * m, np.int32)
+    col[:m] = np.arange(1, n)
+    col[m:] = 0
+    g = synth.CSRGraph(n, rp.astype(np.int32), col, None, False)
+    s = synth.opinions(n, "uniform", 97)
+    z0 = (s[0] + 0.5 * s[1:].sum()) / (1.0 + 0.5 * m)
+    zt = np.empty(n)
+    zt[0] = z0
+    zt[1:] = 0.5 * (s[1:] + z0)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    for precision in ("fp32", "fp64"):
+        z, st = fj.solve(G, to_dev(s), eps=1e-6, omega=1.3, schedule="sor", precision=precision)
+        assert st["certified"] == 1
+        zz = z.cpu().numpy()
+        assert np.max(np.abs(zz - zt) / (zt + 1e-5)) <= 1e-6
