@@ -630,8 +630,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (g->tiles_p.nheavy + 1), st));
     FJ_HIP(hipMemsetAsync(L.zmax_bits, 0, sizeof(unsigned long long), st));
     if (n > 0)
-        hipLaunchKernelGGL(k_sor_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, s, o->z0, o->c, L.sp, L.zh,
-                           L.zq, L.bad, L.zmax_bits);
+        hipLaunchKernelGGL(k_sor_init, dim3(std::min<unsigned>(grid1d(n, bs), 2048u)), dim3(bs), 0, st, n, g->perm, s,
+                           o->z0, o->c, L.sp, L.zh, L.zq, L.bad, L.zmax_bits);
     int hbad = 0;
     FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));

@@ -47,12 +47,15 @@ struct SorState {
     const unsigned long long* zmax_bits;  // bits of max |zhat'| at the start (a nonnegative double)
 };
 
-__global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ s,
-                           const double* __restrict__ z0, double c, double* sp, double* zh, int32_t* zq, int* bad,
-                           unsigned long long* zmax_bits) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+// Grid-stride over the nodes; one atomic per block for the magnitude bound.
+__global__ __launch_bounds__(256) void k_sor_init(int64_t n, const int32_t* __restrict__ perm,
+                                                  const double* __restrict__ s, const double* __restrict__ z0,
+                                                  double c, double* sp, double* zh, int32_t* zq, int* bad,
+                                                  unsigned long long* zmax_bits) {
+    __shared__ double s_max[4];
     double m = 0.0;
-    if (i < n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         int32_t o = perm[i];
         double si = s[o];
         if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
@@ -65,13 +68,17 @@ __global__ void k_sor_init(int64_t n, const int32_t* __restrict__ perm, const do
         }
         zh[i] = z;
         zq[i] = fix_enc(z);
-        m = fmax(si + c, fabs(z));
-        if (!isfinite(m)) m = 0.0;
+        double mi = fmax(si + c, fabs(z));
+        if (isfinite(mi)) m = fmax(m, mi);
     }
-    if (zmax_bits) {
-        m = wave_max(m);
+    if (!zmax_bits) return;  // uniform
+    m = wave_max(m);
+    if (lane_id() == 0) s_max[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (blockDim.x >> 6); ++w) m = fmax(m, s_max[w]);
         // nonnegative doubles order like their bit patterns
-        if (lane_id() == 0 && m > 0.0) atomicMax(zmax_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (m > 0.0) atomicMax(zmax_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
     }
 }
 
