@@ -74,20 +74,20 @@ void oracle_transpose(int64_t n, const int32_t* row_ptr, const int32_t* col, con
     free(cnt);
 }
 
-/* r = b - (I+L) z, row by row: r_i = b_i - (1+d_i) z_i + sum_j a_ij z_j.
- * By Lemma 4, z_exact - z = (I+L)^{-1} r, and since (I+L)^{-1} is nonnegative
- * and row-stochastic (Sec. 3.3), |z_exact - z| <= (I+L)^{-1}|r| <= ||r||_inf. */
+/* r = b - (I+L) z, row by row, with L = D - A written out per arc:
+ * r_i = (b_i - z_i) + sum_j a_ij (z_j - z_i), all terms in one compensated sum
+ * (the differences z_j - z_i avoid the cancellation of (1+d_i) z_i against
+ * sum_j a_ij z_j at hubs).  By Lemma 4, z_exact - z = (I+L)^{-1} r, and since
+ * (I+L)^{-1} is nonnegative and row-stochastic (Sec. 3.3),
+ * |z_exact - z| <= (I+L)^{-1}|r| <= ||r||_inf. */
 void oracle_residual(int64_t n, const int32_t* row_ptr, const int32_t* col, const float* w,
                      const double* b, const double* z, double* r) {
     #pragma omp parallel for schedule(dynamic, 1024)
     for (int64_t i = 0; i < n; ++i) {
-        double d = 0.0, acc = 0.0;
-        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-            double a = wgt(w, k);
-            d += a;
-            acc += a * z[col[k]];
-        }
-        r[i] = b[i] - (1.0 + d) * z[i] + acc;
+        ksum_t acc = {0.0, 0.0};
+        kadd(&acc, b[i] - z[i]);
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) kadd(&acc, wgt(w, k) * (z[col[k]] - z[i]));
+        r[i] = kval(&acc);
     }
 }
 
@@ -131,9 +131,20 @@ int oracle_cg(int64_t n, const int32_t* row_ptr, const int32_t* col, const float
     int it = 0, done = inf_norm(n, r) <= tol;
     for (int64_t i = 0; i < n; ++i) { y[i] = r[i] / (1.0 + d[i]); p[i] = y[i]; }
     double ry = dot(n, r, y);
+    int restarts = 0;
     while (!done && it < maxit) {
         apply_IL(n, row_ptr, col, w, d, p, q);
-        double alpha = ry / dot(n, p, q);
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0) || !isfinite(ry / pq)) {
+            /* breakdown at the rounding floor: restart from the true residual */
+            oracle_residual(n, row_ptr, col, w, s, z, r);
+            if (inf_norm(n, r) <= tol) { done = 1; break; }
+            if (++restarts > 50) break;
+            for (int64_t i = 0; i < n; ++i) { y[i] = r[i] / (1.0 + d[i]); p[i] = y[i]; }
+            ry = dot(n, r, y);
+            continue;
+        }
+        double alpha = ry / pq;
         for (int64_t i = 0; i < n; ++i) { z[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
         ++it;
         if (it % 8 == 0 || inf_norm(n, r) <= tol) { /* guard against recurrence drift */
@@ -163,9 +174,10 @@ int oracle_gs(int64_t n, const int32_t* row_ptr, const int32_t* col, const float
     int sw = 0, done = inf_norm(n, r) <= tol;
     while (!done && sw < maxsweeps) {
         for (int64_t i = 0; i < n; ++i) {
-            double acc = 0.0;
-            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) acc += wgt(w, k) * z[col[k]];
-            z[i] = (s[i] + acc) / (1.0 + d[i]);
+            ksum_t acc = {0.0, 0.0};  /* compensated, so hub rows reach the 1e-12 residual */
+            kadd(&acc, s[i]);
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) kadd(&acc, wgt(w, k) * z[col[k]]);
+            z[i] = kval(&acc) / (1.0 + d[i]);
         }
         ++sw;
         oracle_residual(n, row_ptr, col, w, s, z, r);
