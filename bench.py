@@ -244,7 +244,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl10m", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--schedule", default="sor", choices=["sor", "push"])
-    ap.add_argument("--omega", type=float, default=None)
+    ap.add_argument("--opinions", default=None, choices=["uniform", "exp", "pareto", "bimodal"],
+                    help="override the workload's opinion law (the paper's three laws of Sec. 6, or bimodal)")
+    ap.add_argument("--omega", default=None,
+                    help="a number, 'young' (Eq. (optimal-omega) from a power-iteration estimate of mu) or "
+                         "'tune' (the paper's heuristic: fewest updates over 1.95, 1.90, ..., 1.0); "
+                         "the estimate or the tuning runs before the timed steps")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
@@ -267,8 +272,18 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
-    wl = WORKLOADS[args.workload]
-    omega = args.omega if args.omega is not None else (wl["omega"] if args.schedule == "sor" else 1.0)
+    wl = dict(WORKLOADS[args.workload])
+    if args.opinions:
+        wl["s_kind"] = args.opinions
+        wl["desc"] = wl["desc"].split(", s=")[0].split(", s~")[0] + f", s: {args.opinions} (Sec. 6 law)"
+
+    omega_mode = args.omega if args.omega in ("young", "tune") else None
+    if args.omega is None:
+        omega = wl["omega"] if args.schedule == "sor" else 1.0
+    elif omega_mode is None:
+        omega = float(args.omega)
+    else:
+        omega = 1.0  # replaced after ingest
     precision = args.precision or ("fp64" if wl["eps"] < 1e-6 else "fp32")
     dev = "cuda:0"
     t0 = time.perf_counter()
@@ -282,6 +297,20 @@ def main():
     log(f"ingest {ingest_s:.2f}s info={info}")
     sd = torch.from_numpy(s).to(dev)
     z = torch.empty(g.n, dtype=torch.float64, device=dev)
+    omega_info = None
+    if omega_mode == "young":
+        t0 = time.perf_counter()
+        omega_info = fj.estimate_omega(G, max_iters=5000, tol=1e-6)
+        omega = round(omega_info["omega"], 4)
+        omega_info["seconds"] = round(time.perf_counter() - t0, 3)
+        log(f"omega from mu: {omega_info}")
+    elif omega_mode == "tune":
+        t0 = time.perf_counter()
+        omega_info = fj.tune_omega(G, sd, eps=wl["eps"], precision=precision, schedule=args.schedule,
+                                   max_edge_visits=64 * (g.nnz + g.n))
+        omega = omega_info["best"]
+        omega_info["seconds_total"] = round(time.perf_counter() - t0, 3)
+        log(f"omega tuned: {omega_info}")
 
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
@@ -355,6 +384,7 @@ def main():
         "dtype": "f32+f64" if precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": g.n, "nnz": g.nnz, "eps": wl["eps"], "omega": omega,
+                   "omega_choice": omega_mode or "fixed", "omega_search": omega_info,
                    "schedule": args.schedule, "precision": precision, "colours": info["num_colours"],
                    "sweeps_or_rounds": st["rounds"], "certified": st["certified"],
                    "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),

@@ -164,6 +164,36 @@ size_t fj_solve_workspace_bytes(const fj_graph* g, const fj_solve_opts* opts);
 fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve_opts* opts, double* z,
                    void* ws, size_t ws_bytes, fj_solve_stats* stats, void* stream);
 
+/* ---------------------------------------------------- relaxation factor */
+
+/* Eq. (optimal-omega): omega_opt = 1 + (mu / (1 + sqrt(1 - mu^2)))^2 for the
+ * spectral radius mu = rho((I+D)^{-1} A) (Young's optimum for consistently
+ * ordered matrices; a guide otherwise).  mu < 0 or NaN gives 1, mu >= 1 gives 2. */
+double fj_optimal_omega(double mu);
+
+size_t fj_omega_workspace_bytes(const fj_graph* g);
+
+/* mu = rho((I+D)^{-1} A) by power iteration on the GPU (on the similar
+ * symmetric matrix (I+D)^{-1/2} A (I+D)^{-1/2} when the graph is undirected),
+ * from x0 = 1/sqrt(n), until two estimates 10 iterations apart differ by at
+ * most tol * mu or max_iters (1..100000) iterations ran; then omega =
+ * fj_optimal_omega(mu).  mu, omega, iters: [host] (iters may be NULL).
+ * The estimate approaches mu from below when the second eigenvalue is close
+ * to it.  Synchronizes `stream`. */
+fj_status fj_estimate_omega(const fj_graph* g, int32_t max_iters, double tol, double* mu, double* omega,
+                            int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+/* The paper's heuristic for omega (Sec. 5.2): solve with each candidate in
+ * turn (fj_solve with opts, its omega replaced) and keep the candidate with
+ * the fewest updates (stats.pushes); ties go to the smaller omega.
+ * omegas: [host] n_omegas candidates.  updates, seconds: [host] n_omegas
+ * outputs or NULL (updates -1 where the candidate did not certify).
+ * z: device [n], holds the last candidate's result.  ws: a solve workspace
+ * (fj_solve_workspace_bytes).  FJ_ERR_NOT_CONVERGED if no candidate certified. */
+fj_status fj_tune_omega(const fj_graph* g, const double* s, const fj_solve_opts* opts, const double* omegas,
+                        int32_t n_omegas, int64_t* updates, double* seconds, double* best_omega, double* z,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* --------------------------------------------------------------- measures */
 
 typedef struct {
@@ -181,6 +211,18 @@ size_t fj_metrics_workspace_bytes(const fj_graph* g);
  * s, z: device [n].  out: [host].  Synchronizes `stream`. */
 fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out,
                      void* ws, size_t ws_bytes, void* stream);
+
+size_t fj_stress_workspace_bytes(const fj_graph* g);
+
+/* Stress of Sec. 3.4 for every node: stress_i = (z_i - s_i)^2 + sum_j a_ij (z_i - z_j)^2
+ * over row i of A (the nodes i listens to), in FP64.
+ * s, z: device [n].  stress: device [n] output, or NULL to return the total only.
+ * total: [host] sum_i stress_i in a fixed order (bitwise reproducible).  With D
+ * as fj_metrics reports it, the total equals I + 2D on an undirected graph (every
+ * edge is in two rows) and I + D on a directed one; the text of Sec. 3.4 states
+ * I + D for both.  Synchronizes `stream`. */
+fj_status fj_stress(const fj_graph* g, const double* s, const double* z, double* stress, double* total,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* FP64 certificate of an arbitrary z: max_v |s_v - ((I+L) z)_v| / (eps' (s_v + c)).
  * out_max_ratio: [host].  Synchronizes `stream`.  Uses the metrics workspace. */

@@ -177,6 +177,49 @@ def metrics(g, s, z) -> dict:
     return dict(P=out[0], D=out[1], I=out[2], C=out[3], mean=out[4])
 
 
+def jacobi_spectral_radius(g) -> float:
+    """mu = rho((I+D)^{-1} A), the quantity Eq. (optimal-omega) takes (Sec. 5.2):
+    all eigenvalues of the dense matrix for n <= 2000, else the largest-magnitude
+    one from scipy's Arnoldi iteration."""
+    d = degrees(g)
+    if g.n == 0:
+        return 0.0
+    if g.n <= 2000:
+        M = dense_matrix(g)  # I + L
+        A = np.diag(1.0 + d) - M
+        J = A / (1.0 + d)[:, None]
+        return float(np.max(np.abs(np.linalg.eigvals(J))))
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    w = np.ones(g.nnz) if g.w is None else g.w.astype(np.float64)
+    A = sp.csr_matrix((w, g.col, g.row_ptr), shape=(g.n, g.n))
+    J = sp.diags(1.0 / (1.0 + d)) @ A
+    vals = spla.eigs(J, k=1, which="LM", return_eigenvectors=False, tol=1e-12, maxiter=100000)
+    return float(np.max(np.abs(vals)))
+
+
+def optimal_omega(mu: float) -> float:
+    """Eq. (optimal-omega): 1 + (mu / (1 + sqrt(1 - mu^2)))^2."""
+    return 1.0 + (mu / (1.0 + np.sqrt(1.0 - mu * mu))) ** 2
+
+
+def stress(g, s, z) -> np.ndarray:
+    """Stress of every node (Sec. 3.4): (z_i - s_i)^2 + sum_{j in N_i} a_ij (z_i - z_j)^2,
+    N_i being the nodes listed in row i of A.  Plain per-node loops over the rows,
+    math.fsum per row."""
+    import math
+    s = np.asarray(s, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    out = np.empty(g.n)
+    for i in range(g.n):
+        terms = [(z[i] - s[i]) ** 2]
+        for k in range(int(g.row_ptr[i]), int(g.row_ptr[i + 1])):
+            a = 1.0 if g.w is None else float(g.w[k])
+            terms.append(a * (z[i] - z[g.col[k]]) ** 2)
+        out[i] = math.fsum(terms)
+    return out
+
+
 def certificate(g, s, z, eps: float, sigma: float = 1e-5, c: float = 1e-5) -> float:
     """max_v |r_v| / h_v with r = s' - (I+L)(z + c) = s - (I+L) z and
     h = eps' (s + c), eps' = sigma eps / (c + sigma) (Alg. 2, Alg. 3).

@@ -141,6 +141,98 @@ __global__ __launch_bounds__(1024) void k_metrics_final(const double* part_p, in
     }
 }
 
+// ------------------------------------------------------------------ stress
+// Per-node stress of Sec. 3.4: (z_i - s_i)^2 + sum_j a_ij (z_i - z_j)^2 over
+// row i of A.  Light tiles finish their rows; each heavy-row chunk writes its
+// partial sum, and k_stress_heavy adds them in chunk order.
+__global__ __launch_bounds__(kBlock) void k_stress_tiles(TileView tv, const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                         const double* __restrict__ s, const double* __restrict__ z,
+                                                         double* stress, double* partial) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    __shared__ double s_z[kWavesPerBlock][64];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (wv < tv.nchunks) {
+        const int64_t c = tv.c0 + wv;
+        const int32_t row = tv.heavy_row[tv.chunk_heavy[c]];
+        const double zi = z[row];
+        const int beg = tv.chunk_beg[c];
+        const int end = min(beg + kArcBudget, row_ptr[row + 1]);
+        const double part = chunk_sum(beg, end, [&](int k) {
+            const double d = zi - z[col[k]];
+            return (w ? static_cast<double>(w[k]) : 1.0) * d * d;
+        });
+        if (lane == 0) partial[c] = part;
+        return;
+    }
+    if (wv - tv.nchunks >= tv.ntiles) return;
+    const int64_t tix = tv.t0 + (wv - tv.nchunks);
+    if (tv.tile_heavy[tix] >= 0) return;  // finished by k_stress_heavy
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    if (lane < nrows) s_z[wid][lane] = z[r0 + lane];
+    wave_sync_lds();
+    const double sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], [&](int k, int slot) {
+        const double d = s_z[wid][slot] - z[col[k]];
+        return (w ? static_cast<double>(w[k]) : 1.0) * d * d;
+    });
+    if (lane < nrows) {
+        const double d = s_z[wid][lane] - s[r0 + lane];
+        stress[r0 + lane] = d * d + sum;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stress_heavy(TileView tv, const double* __restrict__ s,
+                                                         const double* __restrict__ z,
+                                                         const double* __restrict__ partial, double* stress) {
+    const int lane = lane_id();
+    const int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (h >= tv.h1) return;
+    double sum = 0.0;
+    for (int32_t c = tv.heavy_chunk0[h] + lane; c < tv.heavy_chunk0[h + 1]; c += 64) sum += partial[c];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+        const int32_t row = tv.heavy_row[h];
+        const double d = z[row] - s[row];
+        stress[row] = d * d + sum;
+    }
+}
+
+// fixed-order block sums of a node vector
+__global__ __launch_bounds__(kBlock) void k_node_sum(int64_t n, const double* __restrict__ x, double* part) {
+    __shared__ double lds[kWavesPerBlock];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kNodeTile + threadIdx.x;
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNodeItems; ++k) {
+        const int64_t i = base + static_cast<int64_t>(k) * kBlock;
+        if (i < n) a += x[i];
+    }
+    a = block_sum<kBlock>(a, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(1024) void k_sum_parts(const double* part, int64_t nb, double* out) {
+    __shared__ double lds[16];
+    const double t = reduce_parts(part, nb, 1, 0, lds);
+    if (threadIdx.x == 0) *out = t;
+}
+
+struct StressLayout {
+    double* stress; double* partial; double* part; double* out;
+};
+
+StressLayout carve_stress(Carver& cv, const fj_graph* g) {
+    StressLayout L{};
+    L.stress = cv.take<double>(g->n + 1);
+    L.partial = cv.take<double>(g->tiles_a.nchunks + 1);
+    L.part = cv.take<double>(nblocks_nodes(g->n) + 1);
+    L.out = cv.take<double>(1);
+    return L;
+}
+
 struct MetricsLayout {
     double* part1; double* part2; double* part_d; double* out;
 };
@@ -200,5 +292,45 @@ extern "C" fj_status fj_metrics(const fj_graph* g, const double* s, const double
     out->I = h[2];
     out->C = h[3];
     out->mean = h[4];
+    return FJ_OK;
+}
+
+extern "C" size_t fj_stress_workspace_bytes(const fj_graph* g) {
+    if (!g) return 0;
+    Carver cv(nullptr);
+    carve_stress(cv, g);
+    return cv.bytes();
+}
+
+extern "C" fj_status fj_stress(const fj_graph* g, const double* s, const double* z, double* stress, double* total,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (!g || !total || !ws || ((!s || !z) && g->n > 0)) {
+        set_error("fj_stress: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (ws_bytes < fj_stress_workspace_bytes(g)) {
+        set_error("fj_stress: workspace too small");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    Carver cv(ws);
+    StressLayout L = carve_stress(cv, g);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = g->n;
+    double h = 0.0;
+    if (n > 0) {
+        double* out = stress ? stress : L.stress;
+        const TileView tv = tile_view_all(g->tiles_a);
+        hipLaunchKernelGGL(k_stress_tiles, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0, st, tv,
+                           g->row_ptr, g->col, g->w, s, z, out, L.partial);
+        if (tv.h1 > tv.h0)
+            hipLaunchKernelGGL(k_stress_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv, s, z,
+                               L.partial, out);
+        const unsigned nbn = nblocks_nodes(n);
+        hipLaunchKernelGGL(k_node_sum, dim3(nbn), dim3(kBlock), 0, st, n, out, L.part);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, L.part, static_cast<int64_t>(nbn), L.out);
+        FJ_HIP(hipMemcpyAsync(&h, L.out, sizeof(double), hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+    }
+    *total = h;
     return FJ_OK;
 }

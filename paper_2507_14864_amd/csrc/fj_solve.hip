@@ -936,3 +936,35 @@ extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve
     if (stats) *stats = local;
     return rc;
 }
+
+extern "C" fj_status fj_tune_omega(const fj_graph* g, const double* s, const fj_solve_opts* opts,
+                                   const double* omegas, int32_t n_omegas, int64_t* updates, double* seconds,
+                                   double* best_omega, double* z, void* ws, size_t ws_bytes, void* stream) {
+    if (!g || !opts || !omegas || n_omegas < 1 || !best_omega) {
+        set_error("fj_tune_omega: null argument or no candidates");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    int64_t best_updates = -1;
+    double best = 1.0;
+    for (int32_t k = 0; k < n_omegas; ++k) {
+        fj_solve_opts o = *opts;
+        o.omega = omegas[k];
+        o.profile = 0;
+        fj_solve_stats st{};
+        fj_status rc = fj_solve(g, s, &o, z, ws, ws_bytes, &st, stream);
+        if (rc != FJ_OK && rc != FJ_ERR_NOT_CONVERGED) return rc;
+        const int64_t u = rc == FJ_OK ? st.pushes : -1;
+        if (updates) updates[k] = u;
+        if (seconds) seconds[k] = st.seconds;
+        if (u >= 0 && (best_updates < 0 || u < best_updates || (u == best_updates && omegas[k] < best))) {
+            best_updates = u;
+            best = omegas[k];
+        }
+    }
+    if (best_updates < 0) {
+        set_error("fj_tune_omega: no candidate reached the certificate");
+        return FJ_ERR_NOT_CONVERGED;
+    }
+    *best_omega = best;
+    return FJ_OK;
+}

@@ -7,6 +7,8 @@
 // tile).  Per-row sums come out of a segmented scan across the lanes, added in
 // a fixed order, so the result is identical run to run.
 #pragma once
+#include <type_traits>
+
 #include "fj_device.h"
 
 namespace fj {
@@ -23,6 +25,7 @@ __device__ __forceinline__ int tile_find(const int* pre, int cnt, int e) {
 
 // FP64 sum over row (row0 + lane) of f(k) for every CSR position k of that
 // row; lanes >= nrows get 0.  nrows in [0, 64], uniform across the wave.
+// f may also take (k, slot), slot being the arc's row minus row0.
 // pre: LDS [65] ints, acc: LDS [64] doubles, both private to this wave.
 template <typename F>
 __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_ptr, int64_t row0, int nrows,
@@ -57,7 +60,8 @@ __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_
             v[j] = 0.0;
             if (e < total) {
                 key[j] = tile_find(pre, nrows, e);
-                v[j] = f(base + e);
+                if constexpr (std::is_invocable_v<F, int, int>) v[j] = f(base + e, key[j]);
+                else v[j] = f(base + e);
             }
         }
 #pragma unroll

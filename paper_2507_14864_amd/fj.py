@@ -107,6 +107,19 @@ def lib():
         L.fj_metrics_workspace_bytes.restype = sz
         L.fj_metrics.argtypes = [vp, vp, vp, P(MetricsOut), vp, sz, vp]
         L.fj_metrics.restype = i32
+        L.fj_optimal_omega.argtypes = [dbl]
+        L.fj_optimal_omega.restype = dbl
+        L.fj_omega_workspace_bytes.argtypes = [vp]
+        L.fj_omega_workspace_bytes.restype = sz
+        L.fj_estimate_omega.argtypes = [vp, i32, dbl, P(dbl), P(dbl), P(i32), vp, sz, vp]
+        L.fj_estimate_omega.restype = i32
+        L.fj_tune_omega.argtypes = [vp, vp, P(SolveOpts), P(dbl), i32, P(ctypes.c_int64), P(dbl), P(dbl), vp,
+                                    vp, sz, vp]
+        L.fj_tune_omega.restype = i32
+        L.fj_stress_workspace_bytes.argtypes = [vp]
+        L.fj_stress_workspace_bytes.restype = sz
+        L.fj_stress.argtypes = [vp, vp, vp, vp, P(dbl), vp, sz, vp]
+        L.fj_stress.restype = i32
         L.fj_certify.argtypes = [vp, vp, vp, dbl, dbl, dbl, P(dbl), vp, sz, vp]
         L.fj_certify.restype = i32
         _LIB = L
@@ -261,6 +274,58 @@ def metrics(graph: Graph, s: torch.Tensor, z: torch.Tensor) -> dict:
     _check(lib().fj_metrics(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
                             ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def optimal_omega(mu: float) -> float:
+    """Eq. (optimal-omega) for a given spectral radius mu."""
+    return lib().fj_optimal_omega(float(mu))
+
+
+def estimate_omega(graph: Graph, max_iters: int = 2000, tol: float = 1e-7) -> dict:
+    """mu = rho((I+D)^{-1} A) by power iteration on the GPU and the omega of
+    Eq. (optimal-omega) for it."""
+    ws = _workspace(lib().fj_omega_workspace_bytes(graph.handle), graph.device)
+    mu, om, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(lib().fj_estimate_omega(graph.handle, int(max_iters), float(tol), ctypes.byref(mu), ctypes.byref(om),
+                                   ctypes.byref(it), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return {"mu": mu.value, "omega": om.value, "iters": it.value}
+
+
+def tune_omega(graph: Graph, s: torch.Tensor, omegas=None, **opts) -> dict:
+    """The paper's heuristic: solve once per candidate omega (default 1.95
+    down to 1.0 in steps of 0.05) and keep the one with the fewest updates."""
+    if omegas is None:
+        omegas = [round(1.95 - 0.05 * k, 2) for k in range(20)]
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    o = make_opts(**opts)
+    ws = _workspace(lib().fj_solve_workspace_bytes(graph.handle, ctypes.byref(o)), graph.device)
+    z = torch.empty(n, dtype=torch.float64, device=graph.device)
+    k = len(omegas)
+    om = (ctypes.c_double * k)(*omegas)
+    upd = (ctypes.c_int64 * k)()
+    secs = (ctypes.c_double * k)()
+    best = ctypes.c_double()
+    _check(lib().fj_tune_omega(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.byref(o), om, k, upd, secs,
+                               ctypes.byref(best), ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), _stream()))
+    return {"best": best.value, "omegas": list(omegas), "updates": list(upd), "seconds": list(secs)}
+
+
+def stress(graph: Graph, s: torch.Tensor, z: torch.Tensor, per_node: bool = True):
+    """Stress of every node, (z_i - s_i)^2 + sum_j a_ij (z_i - z_j)^2, and
+    their total (FP64, reproducible).  Returns (vector or None, total)."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(z, torch.float64, n, "z")
+    nbytes = lib().fj_stress_workspace_bytes(graph.handle)
+    ws = _workspace(nbytes, graph.device)
+    vec = torch.empty(n, dtype=torch.float64, device=graph.device) if per_node else None
+    total = ctypes.c_double()
+    _check(lib().fj_stress(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                           ctypes.c_void_p(vec.data_ptr() if vec is not None else None), ctypes.byref(total),
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return vec, total.value
 
 
 def certify(graph: Graph, s: torch.Tensor, z: torch.Tensor, eps: float, c: float = 1e-5,

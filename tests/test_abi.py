@@ -66,3 +66,14 @@ def test_binding_refuses_without_gpu():
     import paper_2507_14864_amd as fj
     with pytest.raises((RuntimeError, ValueError)):
         fj.Graph(torch.zeros(3, dtype=torch.int32), torch.zeros(0, dtype=torch.int32))
+
+
+def test_optimal_omega_is_host_arithmetic(lib):
+    """fj_optimal_omega is pure host code: Eq. (optimal-omega) against the oracle."""
+    import oracle
+    f = lib.fj_optimal_omega
+    f.argtypes = [ctypes.c_double]
+    f.restype = ctypes.c_double
+    for mu in (0.0, 0.25, 2.0 / 3.0, 0.95, 0.999):
+        assert abs(f(mu) - oracle.optimal_omega(mu)) <= 1e-15
+    assert f(-1.0) == 1.0 and f(1.0) == 2.0 and f(float("nan")) == 1.0

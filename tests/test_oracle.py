@@ -342,3 +342,87 @@ def test_fj_iterate_is_equation_one():
     g2 = synth.chung_lu(2000, 9000, 2.3, 131, directed=True, weighted=True)
     s2 = synth.opinions(g2.n, "uniform", 132)
     assert np.max(np.abs(oracle.fj_iterate(g2, s2, s2, 400) - oracle.exact(g2, s2))) <= 1e-9
+
+
+# ----------------------------------------------------------------- stress
+def test_stress_hand_example():
+    """Path 0-1-2 with unit weights, z = (0.1, 0.4, 0.9), s = (0, 0.5, 1):
+    stress = (0.01 + 0.09, 0.01 + 0.09 + 0.25, 0.01 + 0.25), worked by hand."""
+    g = synth.CSRGraph(3, np.array([0, 1, 3, 4], np.int32), np.array([1, 0, 2, 1], np.int32), None, False)
+    st = oracle.stress(g, [0.0, 0.5, 1.0], [0.1, 0.4, 0.9])
+    assert np.allclose(st, [0.10, 0.35, 0.26], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_stress_total_against_measures(directed):
+    """Sum of the per-node stress equals I + 2D on an undirected graph (each
+    edge sits in two rows) and I + D on a directed one, with D per Table 1
+    as the C measures compute it."""
+    g = synth.chung_lu(3000, 15000, 2.2, 81 + directed, directed=directed, weighted=True)
+    s = synth.opinions(g.n, "uniform", 82)
+    z = oracle.exact(g, s)
+    m = oracle.metrics(g, s, z)
+    total = oracle.stress(g, s, z).sum()
+    want = m["I"] + (m["D"] if directed else 2.0 * m["D"])
+    assert abs(total - want) <= 1e-12 * want
+
+
+def test_equilibrium_minimises_each_node_stress():
+    """At the equilibrium every node's opinion minimises its own stress with
+    the others held fixed (the FJ update of Eq. (1) is that minimiser), so
+    moving one node's z either way raises its stress."""
+    g = synth.chung_lu(500, 2500, 2.3, 83, weighted=True)
+    s = synth.opinions(g.n, "beta", 84, a=2, b=2)
+    z = oracle.exact(g, s)
+    base = oracle.stress(g, s, z)
+    for i in (0, 7, 123, 499):
+        for delta in (1e-3, -1e-3):
+            zp = z.copy()
+            zp[i] += delta
+            assert oracle.stress(g, s, zp)[i] > base[i]
+
+
+# ------------------------------------------------ spectral radius and omega
+@pytest.mark.parametrize("k", [3, 8, 32])
+def test_spectral_radius_even_cycle(k):
+    """Unit-weight cycle: (I+D)^{-1} A = A / 3, whose largest eigenvalue is 2/3."""
+    assert abs(oracle.jacobi_spectral_radius(graphs.cycle(2 * k)) - 2.0 / 3.0) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 5, 40])
+def test_spectral_radius_complete_graph(n):
+    """K_n: (I+D)^{-1} A = A / n with eigenvalues (n-1)/n and -1/n."""
+    assert abs(oracle.jacobi_spectral_radius(graphs.complete(n)) - (n - 1) / n) <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 10, 500])
+def test_spectral_radius_star(k):
+    """Star with k leaves: lambda x_c = k x_l / (1+k) and lambda x_l = x_c / 2,
+    so mu^2 = k / (2 (k+1))."""
+    assert abs(oracle.jacobi_spectral_radius(graphs.star(k)) - np.sqrt(k / (2.0 * (k + 1)))) <= 1e-12
+
+
+def test_spectral_radius_sparse_path_agrees_with_dense():
+    g = synth.chung_lu(2500, 12000, 2.2, 85, directed=True, weighted=True)
+    mu_sparse = oracle.jacobi_spectral_radius(g)
+    sub = synth.chung_lu(1500, 7000, 2.2, 85, directed=True, weighted=True)
+    mu_dense = oracle.jacobi_spectral_radius(sub)
+    # both paths must land inside (0, max_i d_i/(1+d_i)] (row sums bound rho)
+    for gg, mu in ((g, mu_sparse), (sub, mu_dense)):
+        d = oracle.degrees(gg)
+        assert 0.0 < mu <= np.max(d / (1.0 + d)) + 1e-12
+    # and the sparse path reproduces the dense one on the same graph
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    d = oracle.degrees(sub)
+    A = sp.csr_matrix((sub.w.astype(np.float64), sub.col, sub.row_ptr), shape=(sub.n, sub.n))
+    vals = spla.eigs(sp.diags(1.0 / (1.0 + d)) @ A, k=1, which="LM", return_eigenvectors=False, tol=1e-12)
+    assert abs(np.max(np.abs(vals)) - mu_dense) <= 1e-9
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3, 2.0 / 3.0, 0.9, 0.99])
+def test_optimal_omega_equals_young_form(mu):
+    """Eq. (optimal-omega) equals 2 / (1 + sqrt(1 - mu^2)): with q = mu/(1+t),
+    t = sqrt(1-mu^2), 1 + q^2 = (1 + 2t + t^2 + mu^2)/(1+t)^2 = 2/(1+t)."""
+    assert abs(oracle.optimal_omega(mu) - 2.0 / (1.0 + np.sqrt(1.0 - mu * mu))) <= 1e-14
+    assert 1.0 <= oracle.optimal_omega(mu) < 2.0
