@@ -258,6 +258,8 @@ def main():
                     help="skip the learned warm start evaluation on the held-out 5M-node directed graph")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--gather-bits", type=int, default=0, choices=[0, 32, 64],
+                    help="FP32 sweeps: gather the 32-bit fixed-point copy first (0, 32) or FP64 from the start (64)")
     ap.add_argument("--persistent", action="store_true",
                     help="SOR as one cooperative launch with grid barriers between colour classes")
     args = ap.parse_args()
@@ -314,7 +316,7 @@ def main():
 
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
-                          out=z, profile=profile, persistent=args.persistent)
+                          out=z, profile=profile, persistent=args.persistent, gather_bits=args.gather_bits)
         m = fj.metrics(G, sd, zz)
         return st, m
 

@@ -130,6 +130,8 @@ typedef struct {
                                 events on `stream` (adds small gaps between launches) */
     int32_t persistent;      /* nonzero: SOR runs as one cooperative launch with a grid
                                 barrier per colour class instead of one launch per class */
+    int32_t gather_bits;     /* FJ_FP32 sweeps: 0 or 32 = light rows gather the 32-bit fixed-point
+                                copy of zhat' until quiet, then FP64; 64 = FP64 from the start */
 } fj_solve_opts;
 
 typedef struct {

@@ -680,7 +680,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     // certificate holds when these sweeps go quiet.  FP64 sweeps follow if not.
     SorState SMIR = S64;
     SMIR.thr = 0.95;
-    bool mirror = o->precision == FJ_FP32;
+    bool mirror = o->precision == FJ_FP32 && o->gather_bits != 64;
     sa.S = S64;
     sa.bad = L.bad;
     sa.stats = L.stats;

@@ -367,3 +367,19 @@ def test_tune_omega_keeps_fewest_updates():
     for om, u in zip(cands[:2], r["updates"][:2]):
         _, st = fj.solve(G, sd, eps=1e-5, omega=om, schedule="sor")
         assert st["pushes"] == u
+
+
+@pytest.mark.parametrize("gather_bits", [32, 64])
+def test_gather_precision_reaches_the_same_certificate(gather_bits):
+    """FP32 sweeps may start from the 32-bit fixed-point copy of the estimate
+    or gather FP64 from the start; both end at the FP64 certificate."""
+    fj = fjmod()
+    n = 30011
+    g = synth.chung_lu(n, 10 * n, 2.2, 101, weighted=True)
+    s = synth.opinions(n, "bimodal", 102)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    z, st = fj.solve(G, to_dev(s), eps=1e-5, omega=1.5, schedule="sor", gather_bits=gather_bits)
+    assert st["certified"] == 1
+    check_solution(g, s, z, zt, 1e-5)
+    assert (st["mirror_rounds"] > 0) == (gather_bits == 32)
