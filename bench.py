@@ -260,6 +260,8 @@ def main():
                     help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--gather-bits", type=int, default=0, choices=[0, 32, 64],
                     help="FP32 sweeps: gather the 32-bit fixed-point copy first (0, 32) or FP64 from the start (64)")
+    ap.add_argument("--no-tail-merge", action="store_true",
+                    help="one launch per colour class, never a merged tail")
     ap.add_argument("--persistent", action="store_true",
                     help="SOR as one cooperative launch with grid barriers between colour classes")
     args = ap.parse_args()
@@ -316,7 +318,8 @@ def main():
 
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
-                          out=z, profile=profile, persistent=args.persistent, gather_bits=args.gather_bits)
+                          out=z, profile=profile, persistent=args.persistent, gather_bits=args.gather_bits,
+                          tail_merge=not args.no_tail_merge)
         m = fj.metrics(G, sd, zz)
         return st, m
 
@@ -388,7 +391,8 @@ def main():
         "config": {"workload": wl["desc"], "n": g.n, "nnz": g.nnz, "eps": wl["eps"], "omega": omega,
                    "omega_choice": omega_mode or "fixed", "omega_search": omega_info,
                    "schedule": args.schedule, "precision": precision, "colours": info["num_colours"],
-                   "sweeps_or_rounds": st["rounds"], "certified": st["certified"],
+                   "sweeps_or_rounds": st["rounds"], "merged_tail_classes": st.get("merged_classes", 0),
+                   "certified": st["certified"],
                    "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),
                    "metrics": {k: m[k] for k in ("P", "D", "I", "C")}},
         "roofline": roofline,

@@ -132,6 +132,12 @@ typedef struct {
                                 barrier per colour class instead of one launch per class */
     int32_t gather_bits;     /* FJ_FP32 sweeps: 0 or 32 = light rows gather the 32-bit fixed-point
                                 copy of zhat' until quiet, then FP64; 64 = FP64 from the start */
+    int32_t no_tail_merge;   /* nonzero: one launch per colour class always.  Otherwise, on an
+                                undirected graph, the trailing classes that each hold under 1% of
+                                the arcs are swept by one launch (a Jacobi step among their rows)
+                                when every such row's coupling to them, sum_j a_ij / (1 + d_i),
+                                is below 0.9 (2/omega - 1): the Householder-John condition for
+                                convergence of the resulting splitting */
 } fj_solve_opts;
 
 typedef struct {
@@ -147,6 +153,7 @@ typedef struct {
     int64_t kernel_launches; /* profile mode: launches timed */
     int32_t num_colours;  /* colour classes swept (SOR), 0 for push */
     int64_t mirror_rounds; /* SOR sweeps whose light rows gathered the 32-bit fixed-point copy */
+    int32_t merged_classes; /* colour classes swept together as a merged tail (0: none) */
 } fj_solve_stats;
 
 /* Bytes of solve workspace for this graph and options. */

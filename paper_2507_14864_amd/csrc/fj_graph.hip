@@ -329,6 +329,20 @@ __global__ void k_jp_level(int32_t count, const int32_t* __restrict__ row_ptr, c
     if (directed) jp_release(t_row_ptr, t_col, v, kv, key, wait, next, next_count);
 }
 
+// max over rows i >= r0 of sum_{arcs j >= r0} a_ij / (1 + d_i), one wave per row
+__global__ __launch_bounds__(256) void k_merge_coupling(int64_t r0, int64_t n, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                        const double* __restrict__ opd, unsigned long long* out) {
+    const int64_t i = r0 + static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= n) return;  // uniform across the wave
+    double s = 0.0;
+    for (int32_t k = row_ptr[i] + lane_id(); k < row_ptr[i + 1]; k += 64)
+        if (col[k] >= r0) s += w ? static_cast<double>(w[k]) : 1.0;
+    s = wave_sum(s);
+    if (lane_id() == 0 && s > 0.0)
+        atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(s / opd[i])));
+}
+
 __global__ void k_colour_count(int64_t n, const int32_t* __restrict__ colour, int* max_colour) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) atomicMax(max_colour, colour[i]);
@@ -454,7 +468,8 @@ __global__ void k_seg_mark(const int64_t* __restrict__ seg, int nseg, int64_t n,
 __global__ void k_tile_fill(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ mark,
                             const int32_t* __restrict__ tscan, const int32_t* __restrict__ hscan,
                             const int32_t* __restrict__ cscan, int32_t* tile_start, int32_t* tile_heavy,
-                            int32_t* heavy_row, int32_t* heavy_chunk0, int32_t* chunk_heavy, int32_t* chunk_beg) {
+                            int32_t* heavy_row, int32_t* heavy_chunk0, int32_t* chunk_heavy, int32_t* chunk_beg,
+                            int32_t* chunk_end) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i > n) return;
     if (i == n) {
@@ -475,6 +490,7 @@ __global__ void k_tile_fill(int64_t n, const int32_t* __restrict__ rp, const int
         for (int32_t j = 0; j < nch; ++j) {
             chunk_heavy[c0 + j] = h;
             chunk_beg[c0 + j] = rp[i] + j * kArcBudget;
+            chunk_end[c0 + j] = min(rp[i] + (j + 1) * kArcBudget, rp[i + 1]);
         }
     }
 }
@@ -503,6 +519,7 @@ void carve_tileset(Carver& cv, TileSet& T, int64_t n, int64_t nnz) {
     T.heavy_chunk0 = cv.take<int32_t>(hmax + 1);
     T.chunk_heavy = cv.take<int32_t>(2 * hmax + 2);
     T.chunk_beg = cv.take<int32_t>(2 * hmax + 2);
+    T.chunk_end = cv.take<int32_t>(2 * hmax + 2);
 }
 
 // segments: sorted row starts, segs.front() = 0, segs.back() = n
@@ -517,7 +534,8 @@ fj_status build_tiles(TileSet& T, int64_t n, const int32_t* rp, const std::vecto
     exclusive_scan_i32(tmp.hscan, tmp.hscan, n + 1, tmp.scan_tmp, st);
     exclusive_scan_i32(tmp.cscan, tmp.cscan, n + 1, tmp.scan_tmp, st);
     hipLaunchKernelGGL(k_tile_fill, dim3(grid1d(n + 1, bs)), dim3(bs), 0, st, n, rp, tmp.mark, tmp.tscan, tmp.hscan,
-                       tmp.cscan, T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg);
+                       tmp.cscan, T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg,
+                       T.chunk_end);
     hipLaunchKernelGGL(k_seg_offsets, dim3(grid1d(nseg + 1, bs)), dim3(bs), 0, st, tmp.seg, nseg, tmp.tscan, tmp.hscan,
                        tmp.cscan, tmp.segout);
     std::vector<int32_t> h(3 * (nseg + 1));
@@ -782,6 +800,38 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
         for (int k = 0; k < K; ++k)
             for (int64_t h = T.seg_heavy[k]; h < T.seg_heavy[k + 1]; ++h)
                 if (hc[h + 1] - hc[h] > kMaxPackedChunks) g->class_packed[k] = 0;
+    }
+    // Tail merge analysis: the trailing small classes and, for every start T,
+    // the largest coupling of a row to the rows of classes >= T
+    g->merge_min = K;
+    g->merge_coupling.assign(K + 1, 0.0);
+    if (!g->directed && K >= 3) {
+        std::vector<int32_t> bnd(K + 1);
+        for (int k = 0; k <= K; ++k)
+            FJ_HIP(hipMemcpyAsync(&bnd[k], L.prow_ptr + g->class_off[k], sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FJ_HIP(hipStreamSynchronize(st));
+        int T = K;
+        while (T > 1 && g->class_packed[T - 1] &&
+               static_cast<double>(bnd[T] - bnd[T - 1]) < kMergeArcFraction * static_cast<double>(nnz))
+            --T;
+        if (K - T >= 2) {
+            unsigned long long* mc = reinterpret_cast<unsigned long long*>(L.tmp.seg);
+            FJ_HIP(hipMemsetAsync(mc, 0, sizeof(unsigned long long) * (K + 1), st));
+            for (int t = T; t < K; ++t) {
+                const int64_t r0 = g->class_off[t];
+                hipLaunchKernelGGL(k_merge_coupling, dim3(grid1d((n - r0) * 64, bs)), dim3(bs), 0, st, r0, n,
+                                   L.prow_ptr, L.pcol, L.pw, L.popd, mc + t);
+            }
+            std::vector<unsigned long long> hm(K + 1);
+            FJ_HIP(hipMemcpyAsync(hm.data(), mc, sizeof(unsigned long long) * (K + 1), hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipStreamSynchronize(st));
+            for (int t = T; t < K; ++t) {
+                double v;
+                std::memcpy(&v, &hm[t], sizeof(double));
+                g->merge_coupling[t] = v;
+            }
+            g->merge_min = T;
+        }
     }
     g->perm = L.perm;
     g->iperm = L.iperm;

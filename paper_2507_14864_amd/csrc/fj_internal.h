@@ -59,6 +59,8 @@ constexpr int kBigRow = 2048;
 // kMaxPackedChunks chunks for its colour class to be swept in one launch
 constexpr int kPackedCountBits = 12;
 constexpr int kMaxPackedChunks = (1 << kPackedCountBits) - 1;
+// colour classes holding less than this fraction of the arcs may be swept together
+constexpr double kMergeArcFraction = 0.01;
 
 struct TileSet {
     int64_t ntiles = 0, nheavy = 0, nchunks = 0;
@@ -68,6 +70,7 @@ struct TileSet {
     int32_t* heavy_chunk0 = nullptr; // [nheavy + 1]
     int32_t* chunk_heavy = nullptr;  // [nchunks] heavy index owning the chunk
     int32_t* chunk_beg = nullptr;    // [nchunks] first arc of the chunk
+    int32_t* chunk_end = nullptr;    // [nchunks] one past the last arc of the chunk
     std::vector<int64_t> seg_tile, seg_heavy, seg_chunk;  // [nseg + 1] host offsets
     int64_t* d_seg_tile = nullptr;   // device copies of seg_tile / seg_heavy
     int64_t* d_seg_heavy = nullptr;
@@ -84,18 +87,19 @@ struct TileView {
     int64_t t0, ntiles;  // tiles [t0, t0 + ntiles)
     int64_t c0, nchunks; // heavy chunks [c0, c0 + nchunks)
     int64_t h0, h1;      // heavy rows [h0, h1)
+    const int32_t* chunk_end;
 };
 
 inline TileView tile_view(const TileSet& T, int seg) {
     TileView v{T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg,
                T.seg_tile[seg], T.seg_tile[seg + 1] - T.seg_tile[seg],
                T.seg_chunk[seg], T.seg_chunk[seg + 1] - T.seg_chunk[seg],
-               T.seg_heavy[seg], T.seg_heavy[seg + 1]};
+               T.seg_heavy[seg], T.seg_heavy[seg + 1], T.chunk_end};
     return v;
 }
 inline TileView tile_view_all(const TileSet& T) {
     TileView v{T.tile_start, T.tile_heavy, T.heavy_row, T.heavy_chunk0, T.chunk_heavy, T.chunk_beg,
-               0, T.ntiles, 0, T.nchunks, 0, T.nheavy};
+               0, T.ntiles, 0, T.nchunks, 0, T.nheavy, T.chunk_end};
     return v;
 }
 inline unsigned waves_to_blocks(int64_t waves) {
@@ -125,6 +129,11 @@ struct fj_graph {
     int32_t num_colours = 0, colour_rounds = 0;
     std::vector<int64_t> class_off;  // [num_colours + 1] host copy
     std::vector<uint8_t> class_packed;  // [num_colours] 1: no heavy row has more than kMaxPackedChunks chunks
+    // Tail merge (undirected graphs): classes [merge_min, num_colours) are each
+    // under kMergeArcFraction of the arcs; merge_coupling[T] (T >= merge_min) is
+    // max over rows i in classes >= T of sum_{j in classes >= T} a_ij / (1 + d_i).
+    int32_t merge_min = 0;
+    std::vector<double> merge_coupling;
     int32_t* colour = nullptr;       // [n] original labels
     int32_t* perm = nullptr;         // new -> old
     int32_t* iperm = nullptr;        // old -> new

@@ -398,7 +398,7 @@ struct SolveLayout {
     int* flags; int* one; int* bad; unsigned long long* stats;
     double* partial; void* heavy_coef; unsigned* barrier; int* abort;
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
-    unsigned long long* hacc; unsigned long long* zmax_bits;
+    unsigned long long* hacc; unsigned long long* zmax_bits; double* zsh; int32_t* zqsh;
 };
 
 int64_t cert_parts(const fj_graph* g) {
@@ -426,6 +426,9 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     L.heavy_coef = cv.take<char>(tsz * (g->tiles_t.nheavy + 1));
     L.hacc = cv.take<unsigned long long>(g->tiles_p.nheavy + 1);
     L.zmax_bits = cv.take<unsigned long long>(1);
+    const int64_t sh = g->merge_min < g->num_colours ? n - g->class_off[g->merge_min] : 0;
+    L.zsh = cv.take<double>(sh + 1);
+    L.zqsh = cv.take<int32_t>(sh + 1);
     int64_t nb = cert_parts(g);
     L.part_max = cv.take<double>(nb);
     L.part_viol = cv.take<long long>(nb);
@@ -674,7 +677,35 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     sa.pw = g->pw;
     // FP64 sweeps: the margin of 1e-6 h keeps a quiet sweep certified under the
     // FP64 rounding of the standalone certificate (different summation order).
-    SorState S64{L.sp, g->popd, g->pinv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp, L.hacc, L.zmax_bits};
+    SorState S64{L.sp, g->popd, g->pinv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp, L.hacc, L.zmax_bits,
+                 L.zsh, L.zqsh, 0};
+    // Merged tail: the trailing small classes [merge_T, nc) are swept by one
+    // launch in which their rows see each other's values from before it (a
+    // Jacobi step among them).  With A = (I+D) - W, the sweep is the splitting
+    // A = M - N with M = (I+D)/omega - E (E: couplings to earlier rows); by the
+    // Householder-John theorem it converges for symmetric positive definite A
+    // when M + M^T - A = (2/omega - 1)(I+D) + W_tail is positive definite,
+    // which holds when every merged row's coupling to the merged rows is below
+    // (2/omega - 1) of 1 + d_i (diagonal dominance).  A 10% margin is kept.
+    int merge_T = nc;
+    if (!o->no_tail_merge && !g->directed && g->merge_min < nc) {
+        const double lim = 0.9 * (2.0 / o->omega - 1.0);
+        for (int t = g->merge_min; t < nc - 1; ++t)
+            if (g->merge_coupling[t] < lim) { merge_T = t; break; }
+    }
+    TileView tail{};
+    if (merge_T < nc) {
+        const TileSet& T = g->tiles_p;
+        tail = tile_view_all(T);
+        tail.t0 = T.seg_tile[merge_T];
+        tail.ntiles = T.seg_tile[nc] - T.seg_tile[merge_T];
+        tail.c0 = T.seg_chunk[merge_T];
+        tail.nchunks = T.seg_chunk[nc] - T.seg_chunk[merge_T];
+        tail.h0 = T.seg_heavy[merge_T];
+        tail.h1 = T.seg_heavy[nc];
+        S64.sh_base = g->class_off[merge_T];
+    }
+    const int64_t tail_rows = merge_T < nc ? n - g->class_off[merge_T] : 0;
     // Fixed-point sweeps: light rows gather the 32-bit copy, whose error per
     // arc is <= 4.7e-10; a 5% margin on h makes it likely that the FP64
     // certificate holds when these sweeps go quiet.  FP64 sweeps follow if not.
@@ -730,7 +761,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
             for (int b = 0; b < K; ++b) {
                 int* cur = L.flags + sweeps + b;
                 const int* prev = b > 0 ? cur - 1 : nullptr;
-                for (int k = 0; k < nc; ++k) {
+                for (int k = 0; k < merge_T; ++k) {
                     const TileView& tv = views[k];
                     if (tv.ntiles == 0) continue;
                     fj_status rc0 = timer.before();
@@ -739,11 +770,11 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                     if (g->class_packed[k]) {
                         const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
                         if (mirror)
-                            hipLaunchKernelGGL(k_sor_class<true>, dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
-                                               g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                            hipLaunchKernelGGL((k_sor_class<true, false>), dim3(grid), dim3(kBlock), 0, st, tv,
+                                               g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
                         else
-                            hipLaunchKernelGGL(k_sor_class<false>, dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
-                                               g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                            hipLaunchKernelGGL((k_sor_class<false, false>), dim3(grid), dim3(kBlock), 0, st, tv,
+                                               g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
                         ++launches;
                     } else {
                         const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
@@ -760,6 +791,23 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                             ++launches;
                         }
                     }
+                    rc0 = timer.after();
+                    if (rc0) return rc0;
+                }
+                if (merge_T < nc) {  // the merged tail, then its commit
+                    fj_status rc0 = timer.before();
+                    if (rc0) return rc0;
+                    const SorState& S = mirror ? SMIR : S64;
+                    const unsigned grid = waves_to_blocks(tail.nchunks + tail.ntiles);
+                    if (mirror)
+                        hipLaunchKernelGGL((k_sor_class<true, true>), dim3(grid), dim3(kBlock), 0, st, tail,
+                                           g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                    else
+                        hipLaunchKernelGGL((k_sor_class<false, true>), dim3(grid), dim3(kBlock), 0, st, tail,
+                                           g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                    hipLaunchKernelGGL(k_sor_commit, dim3(grid1d(tail_rows, bs)), dim3(bs), 0, st,
+                                       g->class_off[merge_T], n, L.zsh, L.zqsh, L.zh, L.zq, prev);
+                    launches += 2;
                     rc0 = timer.after();
                     if (rc0) return rc0;
                 }
@@ -802,6 +850,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     if (rc) return rc;
     out->num_colours = nc;
     out->mirror_rounds = mirror_sweeps;
+    out->merged_classes = merge_T < nc ? nc - merge_T : 0;
     out->pushes = static_cast<int64_t>(hs.pushes);
     out->edge_visits = sweeps * g->nnz;
     out->rounds = sweeps;

@@ -45,6 +45,9 @@ struct SorState {
     double epsp;
     unsigned long long* hacc;             // per heavy row: packed fixed-point sum and chunk count
     const unsigned long long* zmax_bits;  // bits of max |zhat'| at the start (a nonnegative double)
+    double* zsh;                          // merged tail: new zhat' of rows >= sh_base (shadow)
+    int32_t* zqsh;                        // merged tail: new fixed-point copy (shadow)
+    int64_t sh_base;
 };
 
 // Grid-stride over the nodes; one atomic per block for the magnitude bound.
@@ -84,18 +87,35 @@ __global__ __launch_bounds__(256) void k_sor_init(int64_t n, const int32_t* __re
 
 // The row's own data is touched once per sweep: streaming (nontemporal) loads
 // and stores keep it from displacing the gathered values in L2.
-__device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S, bool* nonfinite) {
-    double z = __builtin_nontemporal_load(&S.zh[i]);
-    double sp = __builtin_nontemporal_load(&S.sp[i]);
-    double ri = sp - __builtin_nontemporal_load(&S.popd[i]) * z + sum;
+struct RowData {
+    double z, sp, opd, inv;
+};
+__device__ __forceinline__ RowData row_load(int64_t i, const SorState& S) {
+    return RowData{__builtin_nontemporal_load(&S.zh[i]), __builtin_nontemporal_load(&S.sp[i]),
+                   __builtin_nontemporal_load(&S.popd[i]), __builtin_nontemporal_load(&S.pinv[i])};
+}
+// Test and update with the row's data already loaded (the kernels issue these
+// loads before the arc loop, so they are not on the critical path).  In a
+// merged tail launch (SHADOW) every row writes its new or unchanged value to
+// the shadow arrays, so rows of the launch gather only values from before it.
+template <bool SHADOW = false>
+__device__ __forceinline__ bool sor_row_with(int64_t i, const RowData& d, double sum, const SorState& S,
+                                             bool* nonfinite) {
+    const double ri = d.sp - d.opd * d.z + sum;
     *nonfinite = !isfinite(ri);
-    if (fabs(ri) > S.thr * S.epsp * sp) {
-        z += S.omega * ri * __builtin_nontemporal_load(&S.pinv[i]);
+    const bool upd = fabs(ri) > S.thr * S.epsp * d.sp;
+    const double z = upd ? d.z + S.omega * ri * d.inv : d.z;
+    if constexpr (SHADOW) {
+        S.zsh[i - S.sh_base] = z;
+        S.zqsh[i - S.sh_base] = fix_enc(z);
+    } else if (upd) {
         __builtin_nontemporal_store(z, &S.zh[i]);
         __builtin_nontemporal_store(fix_enc(z), &S.zq[i]);
-        return true;
     }
-    return false;
+    return upd;
+}
+__device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S, bool* nonfinite) {
+    return sor_row_with(i, row_load(i, S), sum, S, nonfinite);
 }
 
 template <bool MIRROR>
@@ -163,9 +183,12 @@ __device__ __forceinline__ int heavy_scale_exp(double d, const unsigned long lon
 // One colour class in a single launch: the first nchunks waves each sum one
 // heavy-row chunk (combined as above), the rest take one light tile each.
 // Used when no heavy row of the class has more than kMaxPackedChunks chunks.
+// SHADOW: the launch covers several trailing classes at once (a merged tail);
+// rows write to the shadow arrays and k_sor_commit publishes them afterwards,
+// so within the launch every gather sees values from before it.
 // A sweep that follows a quiet sweep (no row updated) would change nothing:
 // when *prev is 0 the launch returns at once.
-template <bool MIRROR>
+template <bool MIRROR, bool SHADOW>
 __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
                                                       SorState S, const int* prev, int* updated, int* bad,
@@ -183,14 +206,17 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
             return a * zh[__builtin_nontemporal_load(&pcol[k])];
         };
         const int64_t cidx = tv.c0 + wv;
-        const int32_t h = tv.chunk_heavy[cidx];
-        const int32_t row = tv.heavy_row[h];
         const int beg = tv.chunk_beg[cidx];
-        const int end = min(beg + kArcBudget, prow_ptr[row + 1]);
+        const int end = tv.chunk_end[cidx];
+        const int32_t h = tv.chunk_heavy[cidx];
+        // row, chunk count and the row's data load while the arcs stream
+        const int32_t row = tv.heavy_row[h];
+        const int nch = tv.heavy_chunk0[h + 1] - tv.heavy_chunk0[h];
+        RowData rd{};
+        if (lane == 0) rd = row_load(row, S);
         const double part = chunk_sum(beg, end, arc64);
         if (lane == 0) {
-            const int nch = tv.heavy_chunk0[h + 1] - tv.heavy_chunk0[h];
-            const int e = heavy_scale_exp(S.popd[row] - 1.0, S.zmax_bits);
+            const int e = heavy_scale_exp(rd.opd - 1.0, S.zmax_bits);
             const double qd = rint(ldexp(part, e));
             if (!(fabs(qd) <= 1125899906842624.0)) flag_set(bad);  // 2^50, or not finite
             const long long q = static_cast<long long>(fmin(fmax(qd, -1125899906842624.0), 1125899906842624.0));
@@ -200,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
                 const long long tot = static_cast<long long>(old + add) >> kPackedCountBits;
                 atomicExch(&S.hacc[h], 0ull);
                 bool nonfinite = false;
-                bool upd = sor_row(row, ldexp(static_cast<double>(tot), -e), S, &nonfinite);
+                bool upd = sor_row_with<SHADOW>(row, rd, ldexp(static_cast<double>(tot), -e), S, &nonfinite);
                 if (nonfinite) flag_set(bad);
                 if (upd) {
                     flag_set(updated);
@@ -222,15 +248,27 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     };
     const int32_t r0 = tv.tile_start[tix];
     const int nrows = tv.tile_start[tix + 1] - r0;
+    RowData rd{};
+    if (lane < nrows) rd = row_load(r0 + lane, S);
     double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc_light);
     bool upd = false, nonfinite = false;
-    if (lane < nrows) upd = sor_row(r0 + lane, sum, S, &nonfinite);
+    if (lane < nrows) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite);
     uint64_t um = __ballot(upd);
     if (__ballot(nonfinite) && lane == 0) flag_set(bad);
     if (um && lane == 0) {
         flag_set(updated);
         stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
     }
+}
+
+// after a merged tail launch: the shadow values become the estimate
+__global__ void k_sor_commit(int64_t base, int64_t n, const double* __restrict__ zsh, const int32_t* __restrict__ zqsh,
+                             double* zh, int32_t* zq, const int* prev) {
+    if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
+    const int64_t i = base + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    zh[i] = zsh[i - base];
+    zq[i] = zqsh[i - base];
 }
 
 __global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, SorState S, const double* __restrict__ partial,

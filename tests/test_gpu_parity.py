@@ -383,3 +383,25 @@ def test_gather_precision_reaches_the_same_certificate(gather_bits):
     assert st["certified"] == 1
     check_solution(g, s, z, zt, 1e-5)
     assert (st["mirror_rounds"] > 0) == (gather_bits == 32)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.6])
+def test_merged_tail_reaches_the_same_certificate(omega):
+    """The trailing small colour classes swept as one launch (a Jacobi step
+    among their rows, allowed by the Householder-John bound) certify like the
+    one-launch-per-class sweep, and the merged sweep is reproducible."""
+    fj = fjmod()
+    g = synth.chung_lu(200000, 2000000, 2.3, 103)
+    s = synth.opinions(g.n, "bimodal", 104)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    z1, st1 = fj.solve(G, sd, eps=1e-5, omega=omega, schedule="sor")
+    z1 = z1.clone()
+    z2, st2 = fj.solve(G, sd, eps=1e-5, omega=omega, schedule="sor")
+    z3, st3 = fj.solve(G, sd, eps=1e-5, omega=omega, schedule="sor", tail_merge=False)
+    assert st1["merged_classes"] >= 2 and st3["merged_classes"] == 0
+    assert torch.equal(z1, z2)
+    for z, st in ((z1, st1), (z3, st3)):
+        assert st["certified"] == 1
+        check_solution(g, s, z, zt, 1e-5)
