@@ -25,9 +25,10 @@ __device__ __forceinline__ int tile_find(const int* pre, int cnt, int e) {
 
 // FP64 sum over row (row0 + lane) of f(k) for every CSR position k of that
 // row; lanes >= nrows get 0.  nrows in [0, 64], uniform across the wave.
-// f may also take (k, slot), slot being the arc's row minus row0.
+// f may also take (k, slot), slot being the arc's row minus row0.  NCH
+// 64-arc chunks are loaded together per step.
 // pre: LDS [65] ints, acc: LDS [64] doubles, both private to this wave.
-template <typename F>
+template <int NCH = 4, typename F>
 __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_ptr, int64_t row0, int nrows,
                                                 int* pre, double* acc, F f) {
     const int lane = lane_id();
@@ -49,12 +50,12 @@ __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_
         if ((lane == 63 || knext != key) && key < 64) acc[key] += v;
         wave_sync_lds();
     };
-    // four 64-arc chunks per step: their loads are in flight together
-    for (int e0 = 0; e0 < total; e0 += 256) {
-        int key[4];
-        double v[4];
+    // NCH 64-arc chunks per step: their loads are in flight together
+    for (int e0 = 0; e0 < total; e0 += 64 * NCH) {
+        int key[NCH];
+        double v[NCH];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NCH; ++j) {
             const int e = e0 + 64 * j + lane;
             key[j] = 64 + lane;
             v[j] = 0.0;
@@ -65,7 +66,7 @@ __device__ __forceinline__ double tile_row_sums(const int32_t* __restrict__ row_
             }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NCH; ++j)
             if (e0 + 64 * j < total) reduce_chunk(key[j], v[j]);
     }
     return lane < nrows ? acc[lane] : 0.0;
