@@ -54,7 +54,7 @@ def make_input(wl):
     return g, s
 
 
-def algorithmic_bytes(schedule, stats, n, nnz, weighted):
+def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
     """Bytes the iteration kernel must move, without cache reuse.
 
     Colour-class sweep (pull form): per row scanned 28 B (row_ptr 4, s' 8,
@@ -66,7 +66,7 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted):
     Push round: per node scanned 8 B (r, h), per push 44 B (row_ptr 8, r
     exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + residual
     atomic RMW 8), +4 B with weights."""
-    if schedule == "sor":
+    if schedule == "sor" or gather_rounds:
         arcs = stats["edge_visits"]
         mirror_arcs = stats.get("mirror_rounds", 0) * nnz
         gather = 8 * (arcs - mirror_arcs) + 4 * mirror_arcs
@@ -260,6 +260,8 @@ def main():
                     help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--gather-bits", type=int, default=0, choices=[0, 32, 64],
                     help="FP32 sweeps: gather the 32-bit fixed-point copy first (0, 32) or FP64 from the start (64)")
+    ap.add_argument("--push-scatter", action="store_true",
+                    help="push schedule: atomic scatter form of the rounds instead of the gather form")
     ap.add_argument("--no-tail-merge", action="store_true",
                     help="one launch per colour class, never a merged tail")
     ap.add_argument("--persistent", action="store_true",
@@ -319,7 +321,7 @@ def main():
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
                           out=z, profile=profile, persistent=args.persistent, gather_bits=args.gather_bits,
-                          tail_merge=not args.no_tail_merge)
+                          tail_merge=not args.no_tail_merge, push_scatter=args.push_scatter)
         m = fj.metrics(G, sd, zz)
         return st, m
 
@@ -344,14 +346,16 @@ def main():
         # same step with every launch of the iteration kernel bracketed by HIP
         # events on the library's stream
         stp, _ = step(profile=True)
-        bytes_total = algorithmic_bytes(args.schedule, stp, g.n, g.nnz, g.w is not None)
+        bytes_total = algorithmic_bytes(args.schedule, stp, g.n, g.nnz, g.w is not None,
+                                        gather_rounds=args.schedule == "push" and not args.push_scatter)
         launches = max(stp["kernel_launches"], 1)
         avg_ms = stp["kernel_ms"] / launches
         achieved = bytes_total / (stp["kernel_ms"] * 1e-3) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4),
                         traffic=measured_traffic() if args.schedule == "sor" and args.workload == "cl10m" else None,
-                        kernel="k_sor_class" if args.schedule == "sor" else "k_push_light+k_push_heavy",
+                        kernel=("k_sor_class" if args.schedule == "sor" or not args.push_scatter
+                                else "k_push_light+k_push_heavy"),
                         bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
                         launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))
         log(f"profiled step: {stp}")

@@ -132,6 +132,10 @@ typedef struct {
                                 barrier per colour class instead of one launch per class */
     int32_t gather_bits;     /* FJ_FP32 sweeps: 0 or 32 = light rows gather the 32-bit fixed-point
                                 copy of zhat' until quiet, then FP64; 64 = FP64 from the start */
+    int32_t push_scatter;    /* FJ_SCHED_PUSH: nonzero = every active node scatters omega r/(1+d)
+                                to its in-neighbours with atomics; 0 = the same rounds in gather
+                                form (each row recomputes its residual from the round's start
+                                estimate), used when no row of A exceeds 4095 x 256 arcs */
     int32_t no_tail_merge;   /* nonzero: one launch per colour class always.  Otherwise, on an
                                 undirected graph, the trailing classes that each hold under 1% of
                                 the arcs are swept by one launch (a Jacobi step among their rows)

@@ -710,6 +710,16 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
         g->tiles_a = L.ta;
         fj_status rc = build_tiles(g->tiles_a, n, d->row_ptr, whole, L.tmp, st);
         if (rc) return rc;
+        {  // can every heavy row of CSR(A) be combined in one launch?
+            const TileSet& T = g->tiles_a;
+            std::vector<int32_t> hc(T.nheavy + 1);
+            FJ_HIP(hipMemcpyAsync(hc.data(), T.heavy_chunk0, sizeof(int32_t) * (T.nheavy + 1), hipMemcpyDeviceToHost,
+                                  st));
+            FJ_HIP(hipStreamSynchronize(st));
+            g->a_packed = 1;
+            for (int64_t h = 0; h < T.nheavy; ++h)
+                if (hc[h + 1] - hc[h] > kMaxPackedChunks) g->a_packed = 0;
+        }
         if (d->directed) {
             g->tiles_t = L.tt;
             rc = build_tiles(g->tiles_t, n, g->t_row_ptr, whole, L.tmp, st);

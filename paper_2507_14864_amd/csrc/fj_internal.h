@@ -134,6 +134,8 @@ struct fj_graph {
     // max over rows i in classes >= T of sum_{j in classes >= T} a_ij / (1 + d_i).
     int32_t merge_min = 0;
     std::vector<double> merge_coupling;
+    // every heavy row of CSR(A) has at most kMaxPackedChunks chunks (gather-form rounds possible)
+    int a_packed = 0;
     int32_t* colour = nullptr;       // [n] original labels
     int32_t* perm = nullptr;         // new -> old
     int32_t* iperm = nullptr;        // old -> new

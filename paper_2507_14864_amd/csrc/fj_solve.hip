@@ -424,11 +424,10 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     int64_t nch = std::max(g->tiles_a.nchunks, g->tiles_p.nchunks) + 1;
     L.partial = cv.take<double>(nch);
     L.heavy_coef = cv.take<char>(tsz * (g->tiles_t.nheavy + 1));
-    L.hacc = cv.take<unsigned long long>(g->tiles_p.nheavy + 1);
+    L.hacc = cv.take<unsigned long long>(std::max(g->tiles_p.nheavy, g->tiles_a.nheavy) + 1);
     L.zmax_bits = cv.take<unsigned long long>(1);
-    const int64_t sh = g->merge_min < g->num_colours ? n - g->class_off[g->merge_min] : 0;
-    L.zsh = cv.take<double>(sh + 1);
-    L.zqsh = cv.take<int32_t>(sh + 1);
+    L.zsh = cv.take<double>(n + 1);  // merged tail, or every row in gather-form rounds
+    L.zqsh = cv.take<int32_t>(n + 1);
     int64_t nb = cert_parts(g);
     L.part_max = cv.take<double>(nb);
     L.part_viol = cv.take<long long>(nb);
@@ -621,6 +620,124 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
     if (!converged) {
         set_error(capped ? "work cap reached before the certificate held"
                          : "certificate failed after the refinement budget (or the iteration diverged)");
+        return FJ_ERR_NOT_CONVERGED;
+    }
+    return FJ_OK;
+}
+
+// Bulk rounds (Alg. 1 / Alg. 3 with the FIFO order relaxed to the round sets
+// of the proof of Thm. 5) in gather form: every round recomputes each row's
+// residual r_i = s'_i - (1+d_i) zhat'_i + sum_j a_ij zhat'_j from the estimate
+// of the round's start (equal to the tracked residual by Lemma 4) and moves
+// the rows above threshold by omega r_i / (1+d_i).  That is the same update
+// as every active node pushing at once, without the atomic scatter to its
+// in-neighbours: one launch of the class sweep over all of CSR(A) with shadow
+// writes (so all rows read the round's start), then a commit.
+fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve_opts* o, double epsp, double* z,
+                              const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
+    const int64_t n = g->n;
+    const int bs = 256;
+    FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (g->tiles_a.nheavy + 1), st));
+    FJ_HIP(hipMemsetAsync(L.zmax_bits, 0, sizeof(unsigned long long), st));
+    if (n > 0)
+        hipLaunchKernelGGL(k_sor_init, dim3(std::min<unsigned>(grid1d(n, bs), 2048u)), dim3(bs), 0, st, n,
+                           static_cast<const int32_t*>(nullptr), s, o->z0, o->c, L.sp, L.zh, L.zq, L.bad,
+                           L.zmax_bits);
+    int hbad = 0;
+    FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+        set_error("s must be finite and >= 0, and z0 finite");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const int K = o->check_every > 0 ? o->check_every : 8;
+    const int max_ref = o->max_refinements >= 0 ? o->max_refinements : 8;
+    const TileView tv = tile_view_all(g->tiles_a);
+    const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
+    SorState S64{L.sp, g->opd, g->inv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp, L.hacc, L.zmax_bits,
+                 L.zsh, L.zqsh, 0};
+    SorState SMIR = S64;
+    SMIR.thr = 0.95;
+    bool mirror = o->precision == FJ_FP32 && o->gather_bits != 64;
+    int64_t rounds = 0, launches = 0, mirror_rounds = 0;
+    int refinements = 0;
+    bool converged = false, capped = false, diverged = false;
+    double max_ratio = 0.0;
+    std::vector<int> hf(K);
+    LaunchTimer timer;
+    timer.on = o->profile != 0;
+    timer.st = st;
+    while (true) {
+        bool quiet = false;
+        while (!quiet) {
+            if (rounds + K > kMaxRounds || (rounds + K) * (g->nnz + n) > cap) { capped = true; break; }
+            FJ_HIP(hipMemsetAsync(L.flags + rounds, 0, sizeof(int) * K, st));
+            for (int b = 0; b < K; ++b) {
+                int* cur = L.flags + rounds + b;
+                const int* prev = b > 0 ? cur - 1 : nullptr;
+                if (n == 0) continue;
+                fj_status rc0 = timer.before();
+                if (rc0) return rc0;
+                if (mirror)
+                    hipLaunchKernelGGL((k_sor_class<true, true>), dim3(grid), dim3(kBlock), 0, st, tv, g->row_ptr,
+                                       g->col, g->w, SMIR, prev, cur, L.bad, L.stats);
+                else
+                    hipLaunchKernelGGL((k_sor_class<false, true>), dim3(grid), dim3(kBlock), 0, st, tv, g->row_ptr,
+                                       g->col, g->w, S64, prev, cur, L.bad, L.stats);
+                hipLaunchKernelGGL(k_sor_commit, dim3(grid1d(n, bs)), dim3(bs), 0, st, static_cast<int64_t>(0), n,
+                                   L.zsh, L.zqsh, L.zh, L.zq, prev);
+                launches += 2;
+                rc0 = timer.after();
+                if (rc0) return rc0;
+            }
+            FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + rounds, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipStreamSynchronize(st));
+            if (hbad) { diverged = true; break; }
+            int used = K;
+            for (int b = 0; b < K; ++b)
+                if (hf[b] == 0) { used = b + 1; quiet = true; break; }
+            rounds += used;
+            if (mirror) mirror_rounds += used;
+            if (n == 0) quiet = true;
+        }
+        if (capped || diverged) break;
+        long long viol = 0;
+        fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh, static_cast<double*>(nullptr), L, st,
+                                       &max_ratio, &viol);
+        if (rc) return rc;
+        if (viol == 0) { converged = true; break; }
+        if (mirror) {  // finish with FP64 gathers
+            mirror = false;
+            continue;
+        }
+        if (refinements >= max_ref) break;
+        ++refinements;
+    }
+    if (!converged && (capped || diverged)) {
+        long long viol = 0;
+        fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh, static_cast<double*>(nullptr), L, st,
+                                       &max_ratio, &viol);
+        if (rc) return rc;
+    }
+    if (n > 0) hipLaunchKernelGGL(k_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, L.zh, o->c, z);
+    HostStats hs;
+    fj_status rc = read_stats(L, st, &hs);
+    if (rc) return rc;
+    rc = timer.total_ms(&out->kernel_ms, &out->kernel_launches);
+    if (rc) return rc;
+    out->mirror_rounds = mirror_rounds;
+    out->pushes = static_cast<int64_t>(hs.pushes);
+    out->edge_visits = rounds * g->nnz;
+    out->rounds = rounds;
+    out->launches = launches;
+    out->refinements = refinements;
+    out->certified = converged ? 1 : 0;
+    out->max_ratio = max_ratio;
+    if (!converged) {
+        set_error(diverged ? "rounds diverged (non-finite residual)"
+                           : capped ? "work cap reached before the certificate held"
+                                    : "certificate failed after the refinement budget");
         return FJ_ERR_NOT_CONVERGED;
     }
     return FJ_OK;
@@ -977,6 +1094,8 @@ extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve
     fj_status rc;
     if (sched == FJ_SCHED_SOR)
         rc = solve_sor(g, s, o, epsp, z, L, &local, st, cap);
+    else if (!o->push_scatter && g->a_packed)
+        rc = solve_rounds_gather(g, s, o, epsp, z, L, &local, st, cap);
     else if (o->precision == FJ_FP64)
         rc = solve_push<double>(g, s, o, epsp, z, L, &local, st, cap);
     else

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_sor_init(int64_t n, const int32_t* __re
     double m = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        int32_t o = perm[i];
+        const int64_t o = perm ? perm[i] : i;
         double si = s[o];
         if (!(si >= 0.0) || !isfinite(si)) flag_set(bad);
         sp[i] = si + c;

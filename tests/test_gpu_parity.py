@@ -405,3 +405,23 @@ def test_merged_tail_reaches_the_same_certificate(omega):
     for z, st in ((z1, st1), (z3, st3)):
         assert st["certified"] == 1
         check_solution(g, s, z, zt, 1e-5)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_push_rounds_gather_and_scatter_forms(directed):
+    """The bulk push rounds in gather form (rows recompute their residual from
+    the round's start) and in atomic scatter form (a node pushes whatever its
+    residual holds when its wave reaches it, contributions of the same round
+    included) both reach the certificate."""
+    fj = fjmod()
+    g = synth.chung_lu(40000, 400000, 2.2, 105 + directed, directed=directed, weighted=directed)
+    s = synth.opinions(g.n, "uniform", 106)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV)
+    sd = to_dev(s)
+    zg, stg = fj.solve(G, sd, eps=1e-5, omega=1.0, schedule="push")
+    zg = zg.clone()
+    zs, sts = fj.solve(G, sd, eps=1e-5, omega=1.0, schedule="push", push_scatter=True)
+    for z, st in ((zg, stg), (zs, sts)):
+        assert st["certified"] == 1
+        check_solution(g, s, z, zt, 1e-5)
