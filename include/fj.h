@@ -77,7 +77,9 @@ size_t fj_graph_workspace_bytes(const fj_graph_desc* desc, int32_t flags);
  * of A^T (a push at v feeds every u with a_uv > 0, the column of A in the
  * proof of Lemma 4); with FJ_GRAPH_COLOUR a colouring of the symmetrised
  * pattern A + A^T and a relabelled copy of A whose colour classes are
- * contiguous (the order the SOR sweeps visit, Thm. 8 with Eq. (sor1)).
+ * contiguous (the order the SOR sweeps visit, Thm. 8 with Eq. (sor1)); on an
+ * undirected graph also, for the trailing small classes, the coupling bound
+ * that decides whether a solve may sweep them together (fj_solve_opts).
  * The caller's row_ptr/col/w must outlive the handle.  Synchronizes `stream`.
  * Errors: FJ_ERR_INVALID_ARGUMENT (bad desc or CSR), FJ_ERR_WORKSPACE_TOO_SMALL,
  * FJ_ERR_UNSUPPORTED (more colours than supported), FJ_ERR_HIP. */
@@ -93,7 +95,7 @@ typedef struct {
     int32_t max_degree;    /* longest row of A */
     int32_t max_in_degree; /* longest row of A^T */
     int32_t num_colours;   /* 0 when built without FJ_GRAPH_COLOUR */
-    int32_t colour_rounds; /* parallel colouring rounds used */
+    int32_t colour_rounds; /* priority levels of the parallel colouring (one launch each) */
 } fj_graph_info;
 
 /* [host] out. */
