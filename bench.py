@@ -313,7 +313,7 @@ def main():
     elif omega_mode == "tune":
         t0 = time.perf_counter()
         omega_info = fj.tune_omega(G, sd, eps=wl["eps"], precision=precision, schedule=args.schedule,
-                                   max_edge_visits=64 * (g.nnz + g.n))
+                                   max_edge_visits=256 * (g.nnz + g.n))
         omega = omega_info["best"]
         omega_info["seconds_total"] = round(time.perf_counter() - t0, 3)
         log(f"omega tuned: {omega_info}")

@@ -424,7 +424,7 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     int64_t nch = std::max(g->tiles_a.nchunks, g->tiles_p.nchunks) + 1;
     L.partial = cv.take<double>(nch);
     L.heavy_coef = cv.take<char>(tsz * (g->tiles_t.nheavy + 1));
-    L.hacc = cv.take<unsigned long long>(std::max(g->tiles_p.nheavy, g->tiles_a.nheavy) + 1);
+    L.hacc = cv.take<unsigned long long>(2 * std::max(g->tiles_p.nheavy, g->tiles_a.nheavy) + 2);
     L.zmax_bits = cv.take<unsigned long long>(1);
     L.zsh = cv.take<double>(n + 1);  // merged tail, or every row in gather-form rounds
     L.zqsh = cv.take<int32_t>(n + 1);
@@ -637,7 +637,7 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
                               const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
     const int64_t n = g->n;
     const int bs = 256;
-    FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (g->tiles_a.nheavy + 1), st));
+    FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (2 * g->tiles_a.nheavy + 2), st));
     FJ_HIP(hipMemsetAsync(L.zmax_bits, 0, sizeof(unsigned long long), st));
     if (n > 0)
         hipLaunchKernelGGL(k_sor_init, dim3(std::min<unsigned>(grid1d(n, bs), 2048u)), dim3(bs), 0, st, n,
@@ -747,7 +747,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                     const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
     const int64_t n = g->n;
     const int bs = 256;
-    FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (g->tiles_p.nheavy + 1), st));
+    FJ_HIP(hipMemsetAsync(L.hacc, 0, sizeof(unsigned long long) * (2 * g->tiles_p.nheavy + 2), st));
     FJ_HIP(hipMemsetAsync(L.zmax_bits, 0, sizeof(unsigned long long), st));
     if (n > 0)
         hipLaunchKernelGGL(k_sor_init, dim3(std::min<unsigned>(grid1d(n, bs), 2048u)), dim3(bs), 0, st, n, g->perm, s,

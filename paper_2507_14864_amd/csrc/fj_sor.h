@@ -90,6 +90,14 @@ __global__ __launch_bounds__(256) void k_sor_init(int64_t n, const int32_t* __re
 struct RowData {
     double z, sp, opd, inv;
 };
+// A light row that gathers the copy sees a sum off by at most 2^-31 d_i.
+// Where that exceeds the 5% margin the fixed-point sweeps keep below the
+// threshold (2^-31 d_i > 0.05 eps' s'_i: large degree, tiny opinion) the row
+// gathers FP64 instead, so the fixed-point sweeps can always go quiet.
+__device__ __forceinline__ bool fix_too_coarse(const RowData& d, double epsp) {
+    return (d.opd - 1.0) * (0.5 / kFixScale) > 0.05 * epsp * d.sp;
+}
+
 __device__ __forceinline__ RowData row_load(int64_t i, const SorState& S) {
     return RowData{__builtin_nontemporal_load(&S.zh[i]), __builtin_nontemporal_load(&S.sp[i]),
                    __builtin_nontemporal_load(&S.popd[i]), __builtin_nontemporal_load(&S.pinv[i])};
@@ -100,10 +108,10 @@ __device__ __forceinline__ RowData row_load(int64_t i, const SorState& S) {
 // the shadow arrays, so rows of the launch gather only values from before it.
 template <bool SHADOW = false>
 __device__ __forceinline__ bool sor_row_with(int64_t i, const RowData& d, double sum, const SorState& S,
-                                             bool* nonfinite) {
+                                             bool* nonfinite, double slack = 0.0) {
     const double ri = d.sp - d.opd * d.z + sum;
     *nonfinite = !isfinite(ri);
-    const bool upd = fabs(ri) > S.thr * S.epsp * d.sp;
+    const bool upd = fabs(ri) > S.thr * S.epsp * d.sp + slack;
     const double z = upd ? d.z + S.omega * ri * d.inv : d.z;
     if constexpr (SHADOW) {
         S.zsh[i - S.sh_base] = z;
@@ -118,6 +126,36 @@ __device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S
     return sor_row_with(i, row_load(i, S), sum, S, nonfinite);
 }
 
+// Row sums of a light tile.  FP64 sweeps gather zhat'; fixed-point sweeps
+// gather the 32-bit copy, except for rows the copy cannot resolve
+// (fix_too_coarse), which gather zhat' (flags in LDS, checked per arc only
+// when the tile holds such a row).  rd: the lane's row data (lane < nrows).
+template <bool MIRROR>
+__device__ __forceinline__ double light_tile_sums(const int32_t* __restrict__ prow_ptr, const int32_t* __restrict__ pcol,
+                                                  const float* __restrict__ pw, const SorState& S, int32_t r0,
+                                                  int nrows, const RowData& rd, int* pre, double* acc, int* flag) {
+    const double* __restrict__ zh = S.zh;
+    const int32_t* __restrict__ zq = S.zq;
+    const int lane = lane_id();
+    auto arc64 = [&](int k) {
+        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+        return a * zh[__builtin_nontemporal_load(&pcol[k])];
+    };
+    if constexpr (!MIRROR) {
+        return tile_row_sums(prow_ptr, r0, nrows, pre, acc, arc64);
+    } else {
+        auto arcq = [&](int k) {
+            double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+            return a * fix_dec(zq[__builtin_nontemporal_load(&pcol[k])]);
+        };
+        const bool coarse = lane < nrows && fix_too_coarse(rd, S.epsp);
+        if (!__ballot(coarse)) return tile_row_sums(prow_ptr, r0, nrows, pre, acc, arcq);
+        flag[lane] = coarse ? 1 : 0;  // published by the LDS sync inside tile_row_sums
+        return tile_row_sums(prow_ptr, r0, nrows, pre, acc,
+                             [&](int k, int slot) { return flag[slot] ? arc64(k) : arcq(k); });
+    }
+}
+
 template <bool MIRROR>
 __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
@@ -125,20 +163,14 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
                                                       int* bad, unsigned long long* stats) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
+    __shared__ int s_flag[kWavesPerBlock][64];
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
     const int wid = threadIdx.x >> 6, lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     const double* __restrict__ zh = S.zh;
-    const int32_t* __restrict__ zq = S.zq;
     auto arc64 = [&](int k) {
         double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
         return a * zh[__builtin_nontemporal_load(&pcol[k])];
-    };
-    auto arc_light = [&](int k) {
-        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
-        int j = __builtin_nontemporal_load(&pcol[k]);
-        if constexpr (MIRROR) return a * fix_dec(zq[j]);
-        else return a * zh[j];
     };
     if (wv < tv.nchunks) {  // heavy rows always gather FP64
         int64_t cidx = tv.c0 + wv;
@@ -155,9 +187,12 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
     if (tv.tile_heavy[tix] >= 0) return;  // finished by k_sor_heavy
     const int32_t r0 = tv.tile_start[tix];
     const int nrows = tv.tile_start[tix + 1] - r0;
-    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc_light);
+    RowData rd{};
+    if (lane < nrows) rd = row_load(r0 + lane, S);
+    const double sum = light_tile_sums<MIRROR>(prow_ptr, pcol, pw, S, r0, nrows, rd, s_pre[wid], s_acc[wid],
+                                               s_flag[wid]);
     bool upd = false, nonfinite = false;
-    if (lane < nrows) upd = sor_row(r0 + lane, sum, S, &nonfinite);
+    if (lane < nrows) upd = sor_row_with(r0 + lane, rd, sum, S, &nonfinite);
     uint64_t um = __ballot(upd);
     if (__ballot(nonfinite) && lane == 0) flag_set(bad);
     if (um && lane == 0) {
@@ -167,17 +202,42 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
 }
 
 // Heavy rows inside one launch.  Every chunk wave converts its FP64 partial
-// sum to a fixed-point integer with a per-row power-of-two scale (chosen from
-// the row's weighted degree and a bound on |zhat'| so that the row total fits
-// in 50 bits) and adds (q << kPackedCountBits) + 1 to the row's 64-bit accumulator.
-// Integer addition is associative, so the total does not depend on the order
-// in which the chunks arrive; the wave whose addition completes the count owns
-// the total, updates the row and clears the accumulator for the next launch.
-// A partial outside the scaled range flags the sweep as diverged.
-__device__ __forceinline__ int heavy_scale_exp(double d, const unsigned long long* zmax_bits) {
-    double zb = 4.0 * __longlong_as_double(static_cast<long long>(*zmax_bits));
-    double bound = fmax(d * zb, 1e-300);
-    return 50 - static_cast<int>(ceil(log2(bound)));
+// sum p to the integer P = round(p 2^F) with a per-row F chosen from the row's
+// weighted degree d and a bound zb on |zhat'| so that the row's partials
+// have sum |P| <= 2^94 (the absolute partials of a row sum to at most d zb),
+// which keeps the sum of the high words inside 63 bits.  P is split into
+// H = P >> 32 and L = P mod 2^32; H is added to one 64-bit word of the row,
+// then L plus an arrival count (bits 52..63) to the other.  Integer addition
+// is associative, so the total does not depend on the order in which chunks
+// arrive, and its resolution, 2^-94 d zb per chunk, stays far below the
+// margin of the FP64 sweeps (1e-6 of the smallest threshold eps' c).  The wave whose addition completes the count (each wave's H
+// addition has returned before it adds L) owns the total, updates the row and
+// clears both words for the next launch.  A partial outside the range flags
+// the solve as diverged.
+constexpr int kFixBits = 94;
+constexpr int kCountShift = 52;
+__device__ __forceinline__ int heavy_frac_bits(double d, const unsigned long long* zmax_bits) {
+    const double zb = 4.0 * __longlong_as_double(static_cast<long long>(*zmax_bits));
+    const double bound = fmax(d * zb, 1e-300);
+    return kFixBits - static_cast<int>(ceil(log2(bound)));
+}
+// P = round(p 2^F) (halves toward +infinity); false if |P| > 2^kFixBits or p not finite
+__device__ __forceinline__ bool to_fixed128(double p, int F, __int128* out) {
+    if (!isfinite(p)) return false;
+    if (p == 0.0) { *out = 0; return true; }
+    int x;
+    const double m = frexp(p, &x);  // p = m 2^x, 0.5 <= |m| < 1
+    const long long M = static_cast<long long>(ldexp(m, 53));
+    const int s = x - 53 + F;
+    if (x + F > kFixBits + 1) return false;  // |p| 2^F >= 2^(kFixBits+1)
+    __int128 P;
+    if (s >= 0) P = static_cast<__int128>(M) << s;
+    else if (s <= -64) P = 0;
+    else P = (static_cast<__int128>(M) + (static_cast<__int128>(1) << (-s - 1))) >> (-s);
+    const __int128 lim = static_cast<__int128>(1) << kFixBits;
+    if (P > lim || P < -lim) return false;
+    *out = P;
+    return true;
 }
 
 // One colour class in a single launch: the first nchunks waves each sum one
@@ -195,10 +255,10 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
                                                       unsigned long long* stats) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
+    __shared__ int s_flag[kWavesPerBlock][64];
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
     const int wid = threadIdx.x >> 6, lane = lane_id();
     const double* __restrict__ zh = S.zh;
-    const int32_t* __restrict__ zq = S.zq;
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (wv < tv.nchunks) {  // heavy rows always gather FP64
         auto arc64 = [&](int k) {
@@ -216,17 +276,24 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
         if (lane == 0) rd = row_load(row, S);
         const double part = chunk_sum(beg, end, arc64);
         if (lane == 0) {
-            const int e = heavy_scale_exp(rd.opd - 1.0, S.zmax_bits);
-            const double qd = rint(ldexp(part, e));
-            if (!(fabs(qd) <= 1125899906842624.0)) flag_set(bad);  // 2^50, or not finite
-            const long long q = static_cast<long long>(fmin(fmax(qd, -1125899906842624.0), 1125899906842624.0));
-            const unsigned long long add = (static_cast<unsigned long long>(q) << kPackedCountBits) + 1ull;
-            const unsigned long long old = atomicAdd(&S.hacc[h], add);
-            if (static_cast<int>(old & static_cast<unsigned long long>(kMaxPackedChunks)) + 1 == nch) {
-                const long long tot = static_cast<long long>(old + add) >> kPackedCountBits;
-                atomicExch(&S.hacc[h], 0ull);
+            const int F = heavy_frac_bits(rd.opd - 1.0, S.zmax_bits);
+            __int128 P = 0;
+            if (!to_fixed128(part, F, &P)) flag_set(bad);
+            const unsigned long long hi = static_cast<unsigned long long>(static_cast<long long>(P >> 32));
+            const unsigned long long lo = static_cast<unsigned long long>(P & static_cast<__int128>(0xffffffffull));
+            unsigned long long* acc = S.hacc + 2 * static_cast<int64_t>(h);
+            const unsigned long long hold = atomicAdd(&acc[1], hi);
+            asm volatile("" : : "v"(hold));  // the H addition has returned before L is added
+            const unsigned long long add = lo + (1ull << kCountShift);
+            const unsigned long long old = atomicAdd(&acc[0], add);
+            if (static_cast<int>(old >> kCountShift) + 1 == nch) {
+                const long long Ht = static_cast<long long>(atomicAdd(&acc[1], 0ull));
+                const unsigned long long Lt = (old + add) & ((1ull << kCountShift) - 1);
+                atomicExch(&acc[0], 0ull);
+                atomicExch(&acc[1], 0ull);
+                const double tot = ldexp(static_cast<double>(Ht), 32 - F) + ldexp(static_cast<double>(Lt), -F);
                 bool nonfinite = false;
-                bool upd = sor_row_with<SHADOW>(row, rd, ldexp(static_cast<double>(tot), -e), S, &nonfinite);
+                bool upd = sor_row_with<SHADOW>(row, rd, tot, S, &nonfinite);
                 if (nonfinite) flag_set(bad);
                 if (upd) {
                     flag_set(updated);
@@ -240,17 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     if (wv >= tv.ntiles) return;
     const int64_t tix = tv.t0 + wv;
     if (tv.tile_heavy[tix] >= 0) return;  // taken by the chunk waves
-    auto arc_light = [&](int k) {
-        double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
-        int j = __builtin_nontemporal_load(&pcol[k]);
-        if constexpr (MIRROR) return a * fix_dec(zq[j]);
-        else return a * zh[j];
-    };
     const int32_t r0 = tv.tile_start[tix];
     const int nrows = tv.tile_start[tix + 1] - r0;
     RowData rd{};
     if (lane < nrows) rd = row_load(r0 + lane, S);
-    double sum = tile_row_sums(prow_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc_light);
+    const double sum = light_tile_sums<MIRROR>(prow_ptr, pcol, pw, S, r0, nrows, rd, s_pre[wid], s_acc[wid],
+                                               s_flag[wid]);
     bool upd = false, nonfinite = false;
     if (lane < nrows) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite);
     uint64_t um = __ballot(upd);

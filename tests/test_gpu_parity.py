@@ -425,3 +425,19 @@ def test_push_rounds_gather_and_scatter_forms(directed):
     for z, st in ((zg, stg), (zs, sts)):
         assert st["certified"] == 1
         check_solution(g, s, z, zt, 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tiny_thresholds_at_hubs(precision):
+    """Normalised Pareto opinions put many s near 0, so h = eps' (s + c) is
+    about 5e-12 at eps = 1e-6 while hub rows sum thousands of arcs in chunks:
+    the heavy-row combine must resolve far below that."""
+    fj = fjmod()
+    g = synth.chung_lu(300000, 3000000, 2.1, 107)
+    assert np.diff(g.row_ptr).max() > 8 * 256
+    s = synth.opinions(g.n, "pareto", 108)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    z, st = fj.solve(G, to_dev(s), eps=1e-6, omega=1.5, schedule="sor", precision=precision)
+    assert st["certified"] == 1
+    check_solution(g, s, z, zt, 1e-6)
