@@ -203,19 +203,25 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
 
 // Heavy rows inside one launch.  Every chunk wave converts its FP64 partial
 // sum p to the integer P = round(p 2^F) with a per-row F chosen from the row's
-// weighted degree d and a bound zb on |zhat'| so that the row's partials
-// have sum |P| <= 2^94 (the absolute partials of a row sum to at most d zb),
-// which keeps the sum of the high words inside 63 bits.  P is split into
-// H = P >> 32 and L = P mod 2^32; H is added to one 64-bit word of the row,
-// then L plus an arrival count (bits 52..63) to the other.  Integer addition
-// is associative, so the total does not depend on the order in which chunks
-// arrive, and its resolution, 2^-94 d zb per chunk, stays far below the
-// margin of the FP64 sweeps (1e-6 of the smallest threshold eps' c).  The wave whose addition completes the count (each wave's H
-// addition has returned before it adds L) owns the total, updates the row and
-// clears both words for the next launch.  A partial outside the range flags
-// the solve as diverged.
-constexpr int kFixBits = 94;
-constexpr int kCountShift = 52;
+// weighted degree d and a bound zb on |zhat'| so that the row's partials have
+// sum |P| <= 2^82 (the absolute partials of a row sum to at most d zb).  P is
+// split into H = P >> 32 (signed) and L = P mod 2^32, and the wave adds
+// (H << 12) + 1 to one 64-bit word of the row and (L << 12) + 1 to the other:
+// each word carries its own arrival count in the low 12 bits, and the sums of
+// H and of L stay inside the 52 bits above it.  Integer addition is
+// associative, so the total does not depend on the order in which chunks
+// arrive.  Its resolution, 2^-82 d zb per chunk, lies some 2^29 below the FP64
+// rounding of the partial itself.  The two additions are issued back to back;
+// the wave that completes the count of the L word owns the total.  If its own
+// H addition did not complete the H word it polls that word: every missing H
+// addition belongs to a resident wave that has already performed its L
+// addition, so it is in flight or next to issue and the poll ends; a bounded
+// poll flags the solve as failed rather than wait without end.  The owner updates the row and clears both words for the next
+// launch.  A partial outside the range flags the solve as diverged; a row
+// total outside it (only if |zhat'| grew past twice zb) yields a wrong sum
+// that the final FP64 certificate rejects.
+constexpr int kFixBits = 82;
+constexpr int kHeavyPoll = 1 << 16;
 __device__ __forceinline__ int heavy_frac_bits(double d, const unsigned long long* zmax_bits) {
     const double zb = 4.0 * __longlong_as_double(static_cast<long long>(*zmax_bits));
     const double bound = fmax(d * zb, 1e-300);
@@ -279,19 +285,29 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
             const int F = heavy_frac_bits(rd.opd - 1.0, S.zmax_bits);
             __int128 P = 0;
             if (!to_fixed128(part, F, &P)) flag_set(bad);
-            const unsigned long long hi = static_cast<unsigned long long>(static_cast<long long>(P >> 32));
-            const unsigned long long lo = static_cast<unsigned long long>(P & static_cast<__int128>(0xffffffffull));
+            constexpr unsigned long long cmask = kMaxPackedChunks;
+            const unsigned long long addh =
+                (static_cast<unsigned long long>(static_cast<long long>(P >> 32)) << kPackedCountBits) + 1ull;
+            const unsigned long long addl =
+                (static_cast<unsigned long long>(P & static_cast<__int128>(0xffffffffull)) << kPackedCountBits) + 1ull;
             unsigned long long* acc = S.hacc + 2 * static_cast<int64_t>(h);
-            const unsigned long long hold = atomicAdd(&acc[1], hi);
-            asm volatile("" : : "v"(hold));  // the H addition has returned before L is added
-            const unsigned long long add = lo + (1ull << kCountShift);
-            const unsigned long long old = atomicAdd(&acc[0], add);
-            if (static_cast<int>(old >> kCountShift) + 1 == nch) {
-                const long long Ht = static_cast<long long>(atomicAdd(&acc[1], 0ull));
-                const unsigned long long Lt = (old + add) & ((1ull << kCountShift) - 1);
+            const unsigned long long oldh = atomicAdd(&acc[0], addh);
+            const unsigned long long oldl = atomicAdd(&acc[1], addl);
+            if (static_cast<int>(oldl & cmask) + 1 == nch) {
+                unsigned long long th = oldh + addh;
+                for (int poll = 0; static_cast<int>(th & cmask) != nch; ++poll) {
+                    if (poll == kHeavyPoll) {
+                        flag_set(bad);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    th = atomicAdd(&acc[0], 0ull);
+                }
+                const unsigned long long tl = oldl + addl;
                 atomicExch(&acc[0], 0ull);
                 atomicExch(&acc[1], 0ull);
-                const double tot = ldexp(static_cast<double>(Ht), 32 - F) + ldexp(static_cast<double>(Lt), -F);
+                const double tot = ldexp(static_cast<double>(static_cast<long long>(th) >> kPackedCountBits), 32 - F) +
+                                   ldexp(static_cast<double>(tl >> kPackedCountBits), -F);
                 bool nonfinite = false;
                 bool upd = sor_row_with<SHADOW>(row, rd, tot, S, &nonfinite);
                 if (nonfinite) flag_set(bad);
