@@ -340,6 +340,11 @@ def main():
     total = time.perf_counter() - t_all
     ms_per_step = 1000.0 * total / max(args.steps, 1)
     log(f"steps: {[round(t * 1000, 2) for t in times]} ms; last stats {st}; metrics {m}")
+    # a-posteriori bounds on the measures of the last solve (outside the timed steps)
+    mb, bounds, tau = fj.metrics_bounds(G, sd, z, c=1e-5)
+    if any(mb[k] != m[k] for k in m):
+        raise RuntimeError("measures from fj_metrics_bounds differ from fj_metrics")
+    log(f"metric bounds: tau {tau}; {bounds}")
 
     roofline = None
     if not args.no_profile:
@@ -398,7 +403,8 @@ def main():
                    "sweeps_or_rounds": st["rounds"], "merged_tail_classes": st.get("merged_classes", 0),
                    "certified": st["certified"],
                    "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),
-                   "metrics": {k: m[k] for k in ("P", "D", "I", "C")}},
+                   "metrics": {k: m[k] for k in ("P", "D", "I", "C")},
+                   "metric_bounds": {"tau": tau, **{k: bounds[k] for k in ("P", "D", "I", "C")}}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "warm_start": warm,

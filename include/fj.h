@@ -227,6 +227,28 @@ size_t fj_metrics_workspace_bytes(const fj_graph* g);
 fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* A-posteriori bounds on the error of the measures of z against those of the
+ * exact z* = (I+L)^{-1} s.  With the residual level
+ *   tau = max_v |s_v - ((I+L) z)_v| / (s_v + c)
+ * (the shift c >= 0 cancels in the residual because (I+L) 1 = 1), Lemma 7
+ * applied to the shifted system gives |z'- z*'| <= tau z*' entrywise
+ * (z' = z + c), hence |z_v - z*_v| <= b_v = tau (z_v + c) / (1 - tau) when
+ * tau < 1.  Each bound adds up, term by term, the largest change of the
+ * measure (Table 1 definitions) over moves |e_v| <= b_v:
+ *   C: sum 2|z_v| b_v + b_v^2        I: sum 2|z_v - s_v| b_v + b_v^2
+ *   P: sum 2|z_v - m| b_v + b_v^2    (the centred values sum to zero, so the
+ *      mean's move drops out of the first-order term)
+ *   D: sum over edges a_ij (2|z_i - z_j|(b_i + b_j) + (b_i + b_j)^2)
+ *   mean: mean b.
+ * Valid for any z, certified or not; a solve certified at (eps, c, sigma) has
+ * tau <= eps' = sigma eps / (c + sigma).  tau is infinite where some
+ * s_v + c = 0 (c = 0 with a zero opinion).  tau >= 1: every bound is +inf.
+ * s, z: device [n].  out: [host] the measures, bitwise equal to fj_metrics.
+ * bound: [host] the bounds in the same fields.  tau: [host] or NULL.
+ * Workspace: fj_metrics_workspace_bytes.  Synchronizes `stream`. */
+fj_status fj_metrics_bounds(const fj_graph* g, const double* s, const double* z, double c, fj_metrics_out* out,
+                            fj_metrics_out* bound, double* tau, void* ws, size_t ws_bytes, void* stream);
+
 size_t fj_stress_workspace_bytes(const fj_graph* g);
 
 /* Stress of Sec. 3.4 for every node: stress_i = (z_i - s_i)^2 + sum_j a_ij (z_i - z_j)^2

@@ -15,6 +15,8 @@ What it computes (arXiv 2507.14864):
   * ``push``             - ImprovedBLISOR (Alg. 2 around Alg. 3; Alg. 1 when
                            omega = 1), sequential FIFO, FP64;
   * ``metrics``          - P, D, I, C of Table 1, compensated FP64 sums;
+  * ``metrics_bounds``   - a-posteriori bounds on those measures' error from
+                           the residual level, by Lemma 7;
   * ``certificate``      - max_v |r_v| / h_v for a candidate z, the stopping
                            rule of Alg. 3 with the shift of Alg. 2 (Lemma 7);
   * ``mpnn``             - the warm-start network's forward/backward in FP64.
@@ -218,6 +220,52 @@ def stress(g, s, z) -> np.ndarray:
             terms.append(a * (z[i] - z[g.col[k]]) ** 2)
         out[i] = math.fsum(terms)
     return out
+
+
+def metrics_bounds(g, s, z, c: float = 1e-5):
+    """A-posteriori bounds on |M(z) - M(z_exact)| for the Table 1 measures.
+
+    Residual level tau = max_v |r_v| / (s_v + c) with r = s - (I+L) z; the
+    shift cancels in r because (I+L) 1 = 1.  Lemma 7 on the shifted system
+    gives |z' - z_exact'| <= tau z_exact' entrywise, so z_exact' <= z' / (1 - tau)
+    and |z_v - z_exact_v| <= b_v = tau (z_v + c) / (1 - tau) for tau < 1.  Each
+    measure's bound adds up, term by term, the largest change that moves
+    e_v with |e_v| <= b_v can cause: (x + e)^2 - x^2 = 2 x e + e^2, and
+    z_i - z_j moves by at most b_i + b_j.  For P the centred values sum to
+    zero, so the mean's move drops out of the first-order term and only
+    lowers the second-order one: |dP| <= sum 2|z_v - m| b_v + b_v^2.  The mean
+    moves by at most mean(b).  Returns (bounds dict with P, D, I, C, mean;
+    tau); infinite bounds when tau >= 1.  math.fsum for every sum."""
+    import math
+    s = np.asarray(s, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n = g.n
+    if n == 0:
+        return dict(P=0.0, D=0.0, I=0.0, C=0.0, mean=0.0), 0.0
+    r = residual(g, s, z)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.abs(r) / (s + c)
+    ratio[~np.isfinite(ratio)] = np.inf
+    tau = float(np.max(ratio))
+    if not tau < 1.0:
+        inf = float("inf")
+        return dict(P=inf, D=inf, I=inf, C=inf, mean=inf), tau
+    b = tau * (z + c) / (1.0 - tau)
+    m = math.fsum(z) / n
+    B = math.fsum(b) / n
+    C = math.fsum(2.0 * np.abs(z) * b + b * b)
+    I = math.fsum(2.0 * np.abs(z - s) * b + b * b)
+    P = math.fsum(2.0 * np.abs(z - m) * b + b * b)
+    terms = []
+    for i in range(n):
+        for k in range(int(g.row_ptr[i]), int(g.row_ptr[i + 1])):
+            j = int(g.col[k])
+            a = 1.0 if g.w is None else float(g.w[k])
+            terms.append(a * (2.0 * abs(z[i] - z[j]) * (b[i] + b[j]) + (b[i] + b[j]) ** 2))
+    D = math.fsum(terms)
+    if not g.directed:  # every undirected edge is stored as two arcs
+        D *= 0.5
+    return dict(P=P, D=D, I=I, C=C, mean=B), tau
 
 
 def certificate(g, s, z, eps: float, sigma: float = 1e-5, c: float = 1e-5) -> float:

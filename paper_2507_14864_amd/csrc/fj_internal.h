@@ -161,6 +161,9 @@ size_t graph_ws_bytes(const fj_graph_desc* d, int32_t flags);
 // returns total through *total_dev (device int64) when not null. tmp: scan_tmp_bytes(n).
 size_t scan_tmp_bytes(int64_t n);
 size_t certify_ws_bytes(const fj_graph* g);
+// max_v |s_v - ((I+L) z)_v| / (s_v + c) in FP64 (certificate kernels); synchronizes st
+fj_status residual_level(const fj_graph* g, const double* s, const double* z, double c, void* ws, size_t ws_bytes,
+                         hipStream_t st, double* tau);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t st);
 
 }  // namespace fj

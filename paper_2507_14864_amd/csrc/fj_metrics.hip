@@ -3,6 +3,18 @@
 // mean-centred vector of Sec. 3.4 (two passes, because the mean subtraction
 // cancels), D = sum over edges of a_ij (z_i - z_j)^2 (undirected: each edge
 // once, i.e. half of the sum over the stored arcs; directed: each arc once).
+//
+// The same passes accumulate what a-posteriori bounds on the measures need.
+// If every |z_v - z*_v| <= b_v with b_v = kappa u_v, u_v = z_v + c (Lemma 7
+// gives kappa = tau / (1 - tau) from the residual level tau, see
+// fj_metrics_bounds), then expanding (x + e)^2 - x^2 = 2 x e + e^2 gives
+//   |dC| <= kappa sum 2|z_v| u_v       + kappa^2 sum u_v^2
+//   |dI| <= kappa sum 2|z_v - s_v| u_v + kappa^2 sum u_v^2
+//   |dP| <= kappa sum 2|z_v - m| u_v   + kappa^2 sum u_v^2
+//   |dD| <= kappa sum a_ij 2|z_i - z_j|(u_i + u_j) + kappa^2 sum a_ij (u_i + u_j)^2
+// and the mean moves by at most kappa mean(u).  For P the centred values sum
+// to zero, so the mean's move drops out of the first-order term and can only
+// lower the second-order one.  The sums are formed once, before kappa is known.
 #include <cmath>
 
 #include "fj_device.h"
@@ -20,88 +32,107 @@ inline unsigned nblocks_edges(const fj_graph* g) {
     return waves_to_blocks(g->tiles_a.nchunks + g->tiles_a.ntiles);
 }
 
-// pass 1: sum z, sum z^2, sum (z - s)^2 per block
+// device result slots
+enum : int {
+    kOutP = 0, kOutD, kOutI, kOutC, kOutMean,
+    kOutUbar, kOutC1, kOutI1, kOutQ, kOutP1, kOutD1, kOutD2, kOutSlots
+};
+constexpr int kNodeStride = 7;
+
+// pass 1 per block: sum z, z^2, (z - s)^2, u, 2|z| u, 2|z - s| u, u^2
 __global__ __launch_bounds__(kBlock) void k_metrics_nodes(int64_t n, const double* __restrict__ s,
-                                                          const double* __restrict__ z, double* part) {
+                                                          const double* __restrict__ z, double c, double* part) {
     __shared__ double lds[kWavesPerBlock];
     int64_t base = static_cast<int64_t>(blockIdx.x) * kNodeTile + threadIdx.x;
-    double a = 0.0, b = 0.0, c = 0.0;
+    double acc[kNodeStride] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < kNodeItems; ++k) {
         int64_t i = base + static_cast<int64_t>(k) * kBlock;
         if (i < n) {
-            double zi = z[i], d = zi - s[i];
-            a += zi;
-            b += zi * zi;
-            c += d * d;
+            const double zi = z[i], d = zi - s[i], u = zi + c;
+            acc[0] += zi;
+            acc[1] += zi * zi;
+            acc[2] += d * d;
+            acc[3] += u;
+            acc[4] += 2.0 * fabs(zi) * u;
+            acc[5] += 2.0 * fabs(d) * u;
+            acc[6] += u * u;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kNodeStride; ++q) {
+        const double t = block_sum<kBlock>(acc[q], lds);
+        if (threadIdx.x == 0) part[kNodeStride * blockIdx.x + q] = t;
+    }
+}
+
+// pass 2 per block: sum (z - m)^2 and 2|z - m| u; m read from device
+__global__ __launch_bounds__(kBlock) void k_metrics_centred(int64_t n, const double* __restrict__ z, double c,
+                                                            const double* __restrict__ out, double* part) {
+    __shared__ double lds[kWavesPerBlock];
+    const double m = out[kOutMean];
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kNodeTile + threadIdx.x;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNodeItems; ++k) {
+        int64_t i = base + static_cast<int64_t>(k) * kBlock;
+        if (i < n) {
+            const double d = z[i] - m;
+            a += d * d;
+            b += 2.0 * fabs(d) * (z[i] + c);
         }
     }
     a = block_sum<kBlock>(a, lds);
     b = block_sum<kBlock>(b, lds);
-    c = block_sum<kBlock>(c, lds);
     if (threadIdx.x == 0) {
-        part[3 * blockIdx.x + 0] = a;
-        part[3 * blockIdx.x + 1] = b;
-        part[3 * blockIdx.x + 2] = c;
+        part[2 * blockIdx.x + 0] = a;
+        part[2 * blockIdx.x + 1] = b;
     }
-}
-
-// pass 2: sum (z - mean)^2, mean read from device
-__global__ __launch_bounds__(kBlock) void k_metrics_centred(int64_t n, const double* __restrict__ z,
-                                                            const double* __restrict__ mean, double* part) {
-    __shared__ double lds[kWavesPerBlock];
-    const double m = *mean;
-    int64_t base = static_cast<int64_t>(blockIdx.x) * kNodeTile + threadIdx.x;
-    double a = 0.0;
-#pragma unroll
-    for (int k = 0; k < kNodeItems; ++k) {
-        int64_t i = base + static_cast<int64_t>(k) * kBlock;
-        if (i < n) {
-            double d = z[i] - m;
-            a += d * d;
-        }
-    }
-    a = block_sum<kBlock>(a, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = a;
 }
 
 // edges: each lane accumulates its own arcs over a light tile or one chunk of
-// a heavy row; fixed-order block sums
+// a heavy row; fixed-order block sums of a d^2, a 2|d|(u_i + u_j), a (u_i + u_j)^2
 __global__ __launch_bounds__(kBlock) void k_metrics_edges(TileView tv, const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                          const double* __restrict__ z, double* part) {
+                                                          const double* __restrict__ z, double c, double* part) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_z[kWavesPerBlock][64];
     __shared__ double lds[kWavesPerBlock];
     const int wid = threadIdx.x >> 6, lane = lane_id();
     const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    double acc = 0.0;
+    double acc = 0.0, acc1 = 0.0, acc2 = 0.0;
+    auto arc = [&](double zi, int k) {
+        const double zj = z[col[k]];
+        const double d = zi - zj, us = (zi + c) + (zj + c);
+        const double a = w ? static_cast<double>(w[k]) : 1.0;
+        acc += a * d * d;
+        acc1 += a * 2.0 * fabs(d) * us;
+        acc2 += a * us * us;
+    };
     if (wv < tv.nchunks) {
-        const int64_t c = tv.c0 + wv;
-        const int32_t row = tv.heavy_row[tv.chunk_heavy[c]];
+        const int64_t cc = tv.c0 + wv;
+        const int32_t row = tv.heavy_row[tv.chunk_heavy[cc]];
         const double zi = z[row];
-        const int beg = tv.chunk_beg[c];
+        const int beg = tv.chunk_beg[cc];
         const int end = min(beg + kArcBudget, row_ptr[row + 1]);
-        for (int k = beg + lane; k < end; k += 64) {
-            double d = zi - z[col[k]];
-            double a = w ? static_cast<double>(w[k]) : 1.0;
-            acc += a * d * d;
-        }
+        for (int k = beg + lane; k < end; k += 64) arc(zi, k);
     } else if (wv - tv.nchunks < tv.ntiles) {
         const int64_t tix = tv.t0 + (wv - tv.nchunks);
         if (tv.tile_heavy[tix] < 0) {
             const int32_t r0 = tv.tile_start[tix];
             const int nrows = tv.tile_start[tix + 1] - r0;
             if (lane < nrows) s_z[wid][lane] = z[r0 + lane];
-            tile_for_each_arc(row_ptr, r0, nrows, s_pre[wid], [&](int k, int slot) {
-                double d = s_z[wid][slot] - z[col[k]];
-                double a = w ? static_cast<double>(w[k]) : 1.0;
-                acc += a * d * d;
-            });
+            tile_for_each_arc(row_ptr, r0, nrows, s_pre[wid], [&](int k, int slot) { arc(s_z[wid][slot], k); });
         }
     }
     acc = block_sum<kBlock>(acc, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+    acc1 = block_sum<kBlock>(acc1, lds);
+    acc2 = block_sum<kBlock>(acc2, lds);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = acc;
+        part[3 * blockIdx.x + 1] = acc1;
+        part[3 * blockIdx.x + 2] = acc2;
+    }
 }
 
 // single block: fixed-order sum of `cnt` partials with stride `stride` starting at `off`
@@ -120,24 +151,35 @@ __device__ double reduce_parts(const double* part, int64_t cnt, int stride, int 
 
 __global__ __launch_bounds__(1024) void k_metrics_mean(const double* part, int64_t nb, int64_t n, double* out) {
     __shared__ double lds[16];
-    double sz = reduce_parts(part, nb, 3, 0, lds);
-    double sc = reduce_parts(part, nb, 3, 1, lds);
-    double si = reduce_parts(part, nb, 3, 2, lds);
+    double t[kNodeStride];
+    for (int q = 0; q < kNodeStride; ++q) t[q] = reduce_parts(part, nb, kNodeStride, q, lds);
     if (threadIdx.x == 0) {
-        out[4] = n ? sz / static_cast<double>(n) : 0.0;  // mean
-        out[3] = sc;                                      // C
-        out[2] = si;                                      // I
+        const double inv = n ? 1.0 / static_cast<double>(n) : 0.0;
+        out[kOutMean] = n ? t[0] / static_cast<double>(n) : 0.0;
+        out[kOutC] = t[1];
+        out[kOutI] = t[2];
+        out[kOutUbar] = t[3] * inv;
+        out[kOutC1] = t[4];
+        out[kOutI1] = t[5];
+        out[kOutQ] = t[6];
     }
 }
 
 __global__ __launch_bounds__(1024) void k_metrics_final(const double* part_p, int64_t nbp, const double* part_d,
                                                         int64_t nbd, int directed, double* out) {
     __shared__ double lds[16];
-    double p = reduce_parts(part_p, nbp, 1, 0, lds);
-    double d = reduce_parts(part_d, nbd, 1, 0, lds);
+    const double p = reduce_parts(part_p, nbp, 2, 0, lds);
+    const double p1 = reduce_parts(part_p, nbp, 2, 1, lds);
+    const double d = reduce_parts(part_d, nbd, 3, 0, lds);
+    const double d1 = reduce_parts(part_d, nbd, 3, 1, lds);
+    const double d2 = reduce_parts(part_d, nbd, 3, 2, lds);
     if (threadIdx.x == 0) {
-        out[0] = p;
-        out[1] = directed ? d : 0.5 * d;
+        const double f = directed ? 1.0 : 0.5;
+        out[kOutP] = p;
+        out[kOutP1] = p1;
+        out[kOutD] = f * d;
+        out[kOutD1] = f * d1;
+        out[kOutD2] = f * d2;
     }
 }
 
@@ -240,11 +282,30 @@ struct MetricsLayout {
 MetricsLayout carve_metrics(Carver& cv, const fj_graph* g) {
     const int64_t n = g->n;
     MetricsLayout L{};
-    L.part1 = cv.take<double>(3 * (nblocks_nodes(n) + 1));
-    L.part2 = cv.take<double>(nblocks_nodes(n) + 1);
-    L.part_d = cv.take<double>(nblocks_edges(g) + 1);
-    L.out = cv.take<double>(8);
+    L.part1 = cv.take<double>(kNodeStride * (nblocks_nodes(n) + 1));
+    L.part2 = cv.take<double>(2 * (nblocks_nodes(n) + 1));
+    L.part_d = cv.take<double>(3 * (nblocks_edges(g) + 1));
+    L.out = cv.take<double>(kOutSlots);
     return L;
+}
+
+// The measures and the bound sums, into h[kOutSlots] on the host.
+fj_status metrics_passes(const fj_graph* g, const double* s, const double* z, double c, const MetricsLayout& L,
+                         hipStream_t st, double* h) {
+    for (int q = 0; q < kOutSlots; ++q) h[q] = 0.0;
+    const int64_t n = g->n;
+    if (n == 0) return FJ_OK;
+    const unsigned nbn = nblocks_nodes(n), nbt = nblocks_edges(g);
+    hipLaunchKernelGGL(k_metrics_nodes, dim3(nbn), dim3(kBlock), 0, st, n, s, z, c, L.part1);
+    hipLaunchKernelGGL(k_metrics_edges, dim3(nbt), dim3(kBlock), 0, st, tile_view_all(g->tiles_a), g->row_ptr,
+                       g->col, g->w, z, c, L.part_d);
+    hipLaunchKernelGGL(k_metrics_mean, dim3(1), dim3(1024), 0, st, L.part1, static_cast<int64_t>(nbn), n, L.out);
+    hipLaunchKernelGGL(k_metrics_centred, dim3(nbn), dim3(kBlock), 0, st, n, z, c, L.out, L.part2);
+    hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(1024), 0, st, L.part2, static_cast<int64_t>(nbn), L.part_d,
+                       static_cast<int64_t>(nbt), g->directed, L.out);
+    FJ_HIP(hipMemcpyAsync(h, L.out, sizeof(double) * kOutSlots, hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    return FJ_OK;
 }
 
 }  // namespace
@@ -271,27 +332,61 @@ extern "C" fj_status fj_metrics(const fj_graph* g, const double* s, const double
         return FJ_ERR_WORKSPACE_TOO_SMALL;
     }
     Carver cv(ws);
-    MetricsLayout L = carve_metrics(cv, g);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t n = g->n;
-    double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (n > 0) {
-        const unsigned nbn = nblocks_nodes(n), nbt = nblocks_edges(g);
-        hipLaunchKernelGGL(k_metrics_nodes, dim3(nbn), dim3(kBlock), 0, st, n, s, z, L.part1);
-        hipLaunchKernelGGL(k_metrics_edges, dim3(nbt), dim3(kBlock), 0, st, tile_view_all(g->tiles_a), g->row_ptr,
-                           g->col, g->w, z, L.part_d);
-        hipLaunchKernelGGL(k_metrics_mean, dim3(1), dim3(1024), 0, st, L.part1, static_cast<int64_t>(nbn), n, L.out);
-        hipLaunchKernelGGL(k_metrics_centred, dim3(nbn), dim3(kBlock), 0, st, n, z, L.out + 4, L.part2);
-        hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(1024), 0, st, L.part2, static_cast<int64_t>(nbn), L.part_d,
-                           static_cast<int64_t>(nbt), g->directed, L.out);
-        FJ_HIP(hipMemcpyAsync(h, L.out, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
-        FJ_HIP(hipStreamSynchronize(st));
+    const MetricsLayout L = carve_metrics(cv, g);
+    double h[kOutSlots];
+    const fj_status rc = metrics_passes(g, s, z, 0.0, L, static_cast<hipStream_t>(stream), h);
+    if (rc != FJ_OK) return rc;
+    out->P = h[kOutP];
+    out->D = h[kOutD];
+    out->I = h[kOutI];
+    out->C = h[kOutC];
+    out->mean = h[kOutMean];
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_metrics_bounds(const fj_graph* g, const double* s, const double* z, double c,
+                                       fj_metrics_out* out, fj_metrics_out* bound, double* tau, void* ws,
+                                       size_t ws_bytes, void* stream) {
+    if (!g || !out || !bound || !ws || ((!s || !z) && g->n > 0)) {
+        set_error("fj_metrics_bounds: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
     }
-    out->P = h[0];
-    out->D = h[1];
-    out->I = h[2];
-    out->C = h[3];
-    out->mean = h[4];
+    if (!(c >= 0.0) || !std::isfinite(c)) {
+        set_error("fj_metrics_bounds: need finite c >= 0");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (ws_bytes < fj_metrics_workspace_bytes(g)) {
+        set_error("fj_metrics_bounds: workspace too small");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // residual level first (its workspace is reused by the passes after it)
+    double t = 0.0;
+    if (g->n > 0) {
+        const fj_status rc = residual_level(g, s, z, c, ws, ws_bytes, st, &t);
+        if (rc != FJ_OK) return rc;
+    }
+    Carver cv(ws);
+    const MetricsLayout L = carve_metrics(cv, g);
+    double h[kOutSlots];
+    const fj_status rc = metrics_passes(g, s, z, c, L, st, h);
+    if (rc != FJ_OK) return rc;
+    out->P = h[kOutP];
+    out->D = h[kOutD];
+    out->I = h[kOutI];
+    out->C = h[kOutC];
+    out->mean = h[kOutMean];
+    if (tau) *tau = t;
+    if (!(t < 1.0)) {  // no bound (also for a non-finite level)
+        bound->P = bound->D = bound->I = bound->C = bound->mean = INFINITY;
+        return FJ_OK;
+    }
+    const double k = t / (1.0 - t), k2 = k * k;
+    bound->C = k * h[kOutC1] + k2 * h[kOutQ];
+    bound->I = k * h[kOutI1] + k2 * h[kOutQ];
+    bound->P = k * h[kOutP1] + k2 * h[kOutQ];
+    bound->D = k * h[kOutD1] + k2 * h[kOutD2];
+    bound->mean = k * h[kOutUbar];
     return FJ_OK;
 }
 

@@ -1006,6 +1006,25 @@ size_t certify_ws_bytes(const fj_graph* g) {
     return cv.bytes();
 }
 
+// tau = max_v |s_v - ((I+L) z)_v| / (s_v + c): the certificate's ratio with eps' = 1
+fj_status residual_level(const fj_graph* g, const double* s, const double* z, double c, void* ws, size_t ws_bytes,
+                         hipStream_t st, double* tau) {
+    if (ws_bytes < certify_ws_bytes(g)) {
+        set_error("residual level: workspace too small");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    Carver cv(ws);
+    CertLayout C = carve_cert(cv, g);
+    SolveLayout L{};
+    L.partial = C.partial;
+    L.part_max = C.part_max;
+    L.part_viol = C.part_viol;
+    L.cert_max = C.cert_max;
+    L.cert_viol = C.cert_viol;
+    long long viol = 0;
+    return certify<double>(g, s, 0.0, c, 1.0, z, static_cast<double*>(nullptr), L, st, tau, &viol);
+}
+
 }  // namespace fj
 
 using namespace fj;

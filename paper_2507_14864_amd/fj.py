@@ -108,6 +108,9 @@ def lib():
         L.fj_metrics_workspace_bytes.restype = sz
         L.fj_metrics.argtypes = [vp, vp, vp, P(MetricsOut), vp, sz, vp]
         L.fj_metrics.restype = i32
+        L.fj_metrics_bounds.argtypes = [vp, vp, vp, ctypes.c_double, P(MetricsOut), P(MetricsOut),
+                                        P(ctypes.c_double), vp, sz, vp]
+        L.fj_metrics_bounds.restype = i32
         L.fj_optimal_omega.argtypes = [dbl]
         L.fj_optimal_omega.restype = dbl
         L.fj_omega_workspace_bytes.argtypes = [vp]
@@ -276,6 +279,21 @@ def metrics(graph: Graph, s: torch.Tensor, z: torch.Tensor) -> dict:
     _check(lib().fj_metrics(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
                             ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def metrics_bounds(graph: Graph, s: torch.Tensor, z: torch.Tensor, c: float = 1e-5) -> tuple:
+    """The measures of z, a-posteriori bounds on their distance from those of
+    the exact solution (from the residual level tau by Lemma 7), and tau."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(z, torch.float64, n, "z")
+    ws = _metrics_ws(graph)
+    out, bound, tau = MetricsOut(), MetricsOut(), ctypes.c_double()
+    _check(lib().fj_metrics_bounds(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                   float(c), ctypes.byref(out), ctypes.byref(bound), ctypes.byref(tau),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return ({k: getattr(out, k) for k, _ in out._fields_}, {k: getattr(bound, k) for k, _ in bound._fields_},
+            tau.value)
 
 
 def optimal_omega(mu: float) -> float:

@@ -441,3 +441,39 @@ def test_tiny_thresholds_at_hubs(precision):
     z, st = fj.solve(G, to_dev(s), eps=1e-6, omega=1.5, schedule="sor", precision=precision)
     assert st["certified"] == 1
     check_solution(g, s, z, zt, 1e-6)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_metric_bounds_match_oracle(directed):
+    """A-posteriori bounds on the measures (Lemma 7 from the residual level)
+    against the oracle on the same z, heavy rows included; the measures equal
+    fj_metrics bit for bit, and a certified solve's bounds hold the exact
+    measures."""
+    fj = fjmod()
+    c = 1e-5
+    g = synth.chung_lu(20000, 120000, 2.2, 181 + directed, directed=directed, weighted=True)
+    assert np.diff(g.row_ptr).max() > 256
+    s = synth.opinions(g.n, "uniform", 183)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    rng = np.random.default_rng(184)
+    for rel in (1e-8, 1e-6):
+        z = zt * (1.0 + rel * rng.uniform(-1, 1, g.n))
+        zd = to_dev(z)
+        m, b, tau = fj.metrics_bounds(G, sd, zd, c=c)
+        assert m == fj.metrics(G, sd, zd)
+        bo, to = oracle.metrics_bounds(g, s, z, c)
+        assert to < 1.0 and abs(tau - to) <= 1e-6 * to
+        for k in ("P", "D", "I", "C", "mean"):
+            assert abs(b[k] - bo[k]) <= 1e-6 * bo[k], (k, b[k], bo[k])
+    _, b, tau = fj.metrics_bounds(G, sd, to_dev(np.full(g.n, 5.0)), c=c)
+    assert tau >= 1.0 and all(np.isinf(v) for v in b.values())
+    eps = 1e-4
+    z, st = fj.solve(G, sd, eps=eps, omega=1.0 if directed else 1.5, schedule="sor")
+    assert st["certified"] == 1
+    m, b, tau = fj.metrics_bounds(G, sd, z, c=c)
+    assert tau <= 1e-5 * eps / (c + 1e-5) * (1 + 1e-9)
+    mt = oracle.metrics(g, s, zt)
+    for k in ("P", "D", "I", "C", "mean"):
+        assert abs(m[k] - mt[k]) <= b[k] + 1e-12 * abs(mt[k]), k

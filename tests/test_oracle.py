@@ -426,3 +426,132 @@ def test_optimal_omega_equals_young_form(mu):
     t = sqrt(1-mu^2), 1 + q^2 = (1 + 2t + t^2 + mu^2)/(1+t)^2 = 2/(1+t)."""
     assert abs(oracle.optimal_omega(mu) - 2.0 / (1.0 + np.sqrt(1.0 - mu * mu))) <= 1e-14
     assert 1.0 <= oracle.optimal_omega(mu) < 2.0
+
+
+# ------------------------------------------------- a-posteriori metric bounds
+def _measures_dense(g, s, z):
+    return dict(**_metrics_by_definition(g, s, z), mean=float(np.mean(z)))
+
+
+def _box(g, s, zh, c):
+    """Residual level and per-node radius from the dense matrix (Lemma 7)."""
+    r = s - oracle.dense_matrix(g) @ zh
+    tau = float(np.max(np.abs(r) / (s + c)))
+    return tau, tau * (zh + c) / (1.0 - tau)
+
+
+@pytest.mark.parametrize("directed,weighted", [(False, False), (True, True), (False, True)])
+def test_bounds_contain_exact_measures(directed, weighted):
+    """The measures of the exact z lie within the bounds around a perturbed z,
+    and the exact z within the per-node radius of Lemma 7."""
+    c = 1e-5
+    g = graphs.random_graph(30, 0.2, 131, directed=directed, weighted=weighted)
+    s = synth.opinions(g.n, "uniform", 132)
+    zt = oracle.dense_solve(g, s)
+    rng = np.random.default_rng(133)
+    for rel in (1e-6, 1e-4, 1e-3):
+        zh = zt * (1.0 + rel * rng.uniform(-1, 1, g.n))
+        bound, tau = oracle.metrics_bounds(g, s, zh, c)
+        t2, b = _box(g, s, zh, c)
+        assert tau < 1.0 and np.isclose(tau, t2, rtol=1e-9)
+        assert np.all(np.abs(zh - zt) <= b * (1 + 1e-12))
+        mh, mt = _measures_dense(g, s, zh), _measures_dense(g, s, zt)
+        for k in ("P", "D", "I", "C", "mean"):
+            assert abs(mh[k] - mt[k]) <= bound[k] * (1 + 1e-12) + 1e-15, (rel, k)
+
+
+@pytest.mark.parametrize("directed,seed", [(False, 141), (True, 142), (False, 143)])
+def test_bounds_against_brute_force_over_box_vertices(directed, seed):
+    """Over all 2^n moves e_v = +-b_v: the C, I and mean bounds equal the
+    largest change, the P and D bounds are at least as large (the convex
+    measures take their largest increase at a vertex of the box)."""
+    c = 1e-5
+    g = graphs.random_graph(7, 0.5, seed, directed=directed, weighted=True)
+    s = synth.opinions(g.n, "uniform", seed + 1)
+    zt = oracle.dense_solve(g, s)
+    zh = zt * (1.0 + 1e-3 * np.random.default_rng(seed + 2).uniform(-1, 1, g.n))
+    bound, tau = oracle.metrics_bounds(g, s, zh, c)
+    assert tau < 1.0
+    _, b = _box(g, s, zh, c)
+    base = _measures_dense(g, s, zh)
+    worst = dict.fromkeys(base, 0.0)
+    for signs in itertools.product((-1.0, 1.0), repeat=g.n):
+        m = _measures_dense(g, s, zh + np.array(signs) * b)
+        for k in worst:
+            worst[k] = max(worst[k], abs(m[k] - base[k]))
+    for k in ("C", "I", "mean"):
+        assert np.isclose(bound[k], worst[k], rtol=1e-9), k
+    for k in ("P", "D"):
+        assert bound[k] >= worst[k] * (1 - 1e-12), k
+
+
+@pytest.mark.parametrize("n", [2, 6])
+def test_polarization_bound_attained_at_a_constant_estimate(n):
+    """With every z_v equal the first-order change of P vanishes and moves of
+    alternating sign keep the mean: the P bound is the largest change."""
+    c = 1e-5
+    g = graphs.cycle(n) if n > 2 else graphs.from_arcs(2, [(0, 1)])
+    s = np.full(n, 0.4)  # z_exact = s (L 1 = 0)
+    zh = np.full(n, 0.4 * (1.0 + 1e-3))
+    bound, tau = oracle.metrics_bounds(g, s, zh, c)
+    assert tau < 1.0
+    _, b = _box(g, s, zh, c)
+    base = _measures_dense(g, s, zh)["P"]
+    worst = max(abs(_measures_dense(g, s, zh + np.array(sg) * b)["P"] - base)
+                for sg in itertools.product((-1.0, 1.0), repeat=n))
+    assert np.isclose(bound["P"], worst, rtol=1e-9)
+
+
+@pytest.mark.parametrize("w", [1.0, 0.3])
+def test_disagreement_bound_attained_on_one_edge(w):
+    """On a single edge the two ends can move apart by b_1 + b_2: the D bound
+    is the change itself (an undirected edge counted once)."""
+    c = 1e-5
+    g = graphs.from_arcs(2, [(0, 1)], [w])
+    s = np.array([0.9, 0.2])
+    zt = oracle.dense_solve(g, s)
+    zh = zt + np.array([2e-3, -1e-3])
+    bound, _ = oracle.metrics_bounds(g, s, zh, c)
+    _, b = _box(g, s, zh, c)
+    sgn = np.sign(zh[0] - zh[1])
+    moved = _measures_dense(g, s, zh + np.array([sgn * b[0], -sgn * b[1]]))
+    assert np.isclose(bound["D"], abs(moved["D"] - _measures_dense(g, s, zh)["D"]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_bounds_equality_case_of_lemma7(directed):
+    """z' = (1 - t) z_exact' leaves the residual t s', so tau = t, the radius
+    b_v equals the error z_exact_v - z_v, and the C bound is the change in C."""
+    c, t = 1e-5, 2e-3
+    g = graphs.random_graph(25, 0.25, 151, directed=directed, weighted=True)
+    s = synth.opinions(g.n, "uniform", 152)
+    zt = oracle.dense_solve(g, s)
+    zh = (1.0 - t) * (zt + c) - c
+    bound, tau = oracle.metrics_bounds(g, s, zh, c)
+    assert np.isclose(tau, t, rtol=1e-9)
+    m0, m1 = _measures_dense(g, s, zh), _measures_dense(g, s, zt)
+    assert np.isclose(bound["C"], m1["C"] - m0["C"], rtol=1e-8)
+    assert np.isclose(bound["mean"], m1["mean"] - m0["mean"], rtol=1e-8)
+
+
+def test_bounds_of_a_certified_push():
+    """A push certified at eps has tau <= eps' = sigma eps / (c + sigma), and
+    the exact measures lie within the bounds around its z."""
+    g = synth.chung_lu(2000, 10000, 2.3, 161, weighted=True)
+    s = synth.opinions(g.n, "uniform", 162)
+    zt = oracle.exact(g, s)
+    eps = 1e-3
+    p = oracle.push(g, s, eps, omega=1.3, **EPS_SIGMA_C)
+    bound, tau = oracle.metrics_bounds(g, s, p["z"], EPS_SIGMA_C["c"])
+    epsp = EPS_SIGMA_C["sigma"] * eps / (EPS_SIGMA_C["c"] + EPS_SIGMA_C["sigma"])
+    assert tau <= epsp * (1 + 1e-9)
+    mh, mt = oracle.metrics(g, s, p["z"]), oracle.metrics(g, s, zt)
+    for k in ("P", "D", "I", "C", "mean"):
+        assert abs(mh[k] - mt[k]) <= bound[k], k
+
+
+def test_bounds_infinite_without_a_contraction():
+    g = graphs.complete(4)
+    s = np.array([0.1, 0.2, 0.3, 0.4])
+    bound, tau = oracle.metrics_bounds(g, s, np.full(4, 5.0), 1e-5)
+    assert tau >= 1.0 and all(np.isinf(v) for v in bound.values())
