@@ -62,15 +62,19 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
     fixed-point copy write 4); per arc 4 B column index plus the gathered
     value, 8 B (FP64) or 4 B in the sweeps that gather the fixed-point copy
     (heavy rows read 8 B there too: counted as 4, so the figure is low);
-    +4 B per arc with weights.
+    +4 B per arc with weights.  A row skipped as quiet counts only its
+    dirty bit (1/8 B), and its arcs are not gathered.
     Push round: per node scanned 8 B (r, h), per push 44 B (row_ptr 8, r
     exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + residual
     atomic RMW 8), +4 B with weights."""
     if schedule == "sor" or gather_rounds:
         arcs = stats["edge_visits"]
-        mirror_arcs = stats.get("mirror_rounds", 0) * nnz
+        mirror_arcs = stats["mirror_edge_visits"] if schedule == "sor" else stats.get("mirror_rounds", 0) * nnz
         gather = 8 * (arcs - mirror_arcs) + 4 * mirror_arcs
-        return 28 * stats["rounds"] * n + 20 * stats["pushes"] + 4 * arcs + gather + (4 * arcs if weighted else 0)
+        skipped = stats.get("skipped_rows", 0)
+        rows = stats["rounds"] * n - skipped
+        return (28 * rows + skipped // 8 + 20 * stats["pushes"] + 4 * arcs + gather
+                + (4 * arcs if weighted else 0))
     per_arc = 16 if weighted else 12
     return 8 * stats["rounds"] * n + 44 * stats["pushes"] + per_arc * stats["edge_visits"]
 
@@ -266,6 +270,11 @@ def main():
                     help="one launch per colour class, never a merged tail")
     ap.add_argument("--persistent", action="store_true",
                     help="SOR as one cooperative launch with grid barriers between colour classes")
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="sweeps enqueued between host checks of progress")
+    ap.add_argument("--skip-below", type=float, default=0.0,
+                    help="quiet-row skipping once a sweep updates fewer than this fraction of rows "
+                         "(0: the library default, negative: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -321,7 +330,8 @@ def main():
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
                           out=z, profile=profile, persistent=args.persistent, gather_bits=args.gather_bits,
-                          tail_merge=not args.no_tail_merge, push_scatter=args.push_scatter)
+                          tail_merge=not args.no_tail_merge, push_scatter=args.push_scatter,
+                          skip_below=args.skip_below, check_every=args.check_every)
         m = fj.metrics(G, sd, zz)
         return st, m
 
@@ -401,6 +411,7 @@ def main():
                    "omega_choice": omega_mode or "fixed", "omega_search": omega_info,
                    "schedule": args.schedule, "precision": precision, "colours": info["num_colours"],
                    "sweeps_or_rounds": st["rounds"], "merged_tail_classes": st.get("merged_classes", 0),
+                   "skipped_row_visits": st.get("skipped_rows", 0),
                    "certified": st["certified"],
                    "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),
                    "metrics": {k: m[k] for k in ("P", "D", "I", "C")},

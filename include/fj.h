@@ -144,11 +144,22 @@ typedef struct {
                                 when every such row's coupling to them, sum_j a_ij / (1 + d_i),
                                 is below 0.9 (2/omega - 1): the Householder-John condition for
                                 convergence of the resulting splitting */
+    double skip_below;       /* FJ_SCHED_SOR on an undirected graph, quiet-row skipping.  After a
+                                batch of check_every sweeps that averaged at most
+                                max(0.1, skip_below) * n updates, a sweep that follows one with fewer than
+                                skip_below * n updates has its updates mark their rows and
+                                neighbours; from the sweep after that, a row left unmarked
+                                (its value and its neighbours' values unchanged since its last
+                                sweep) keeps its value without gathering.  Its residual, hence
+                                its no-update decision, would be the same: the result is bit
+                                for bit the one without skipping.  0 selects 0.002;
+                                negative: never */
 } fj_solve_opts;
 
 typedef struct {
     int64_t pushes;       /* node updates (pushes / row relaxations) */
-    int64_t edge_visits;  /* arcs read by those updates */
+    int64_t edge_visits;  /* arcs read by those updates (SOR: sweeps x nnz less the arcs of
+                             skipped rows) */
     int64_t rounds;       /* push rounds or full sweeps */
     int64_t launches;     /* kernel launches of the iteration */
     int32_t refinements;  /* certificate failures that re-seeded the residual */
@@ -160,6 +171,9 @@ typedef struct {
     int32_t num_colours;  /* colour classes swept (SOR), 0 for push */
     int64_t mirror_rounds; /* SOR sweeps whose light rows gathered the 32-bit fixed-point copy */
     int32_t merged_classes; /* colour classes swept together as a merged tail (0: none) */
+    int64_t skipped_rows;   /* row visits skipped by quiet-row skipping */
+    int64_t skipped_arcs;   /* the arcs of those rows */
+    int64_t mirror_edge_visits; /* arcs gathered in the sweeps that read the fixed-point copy */
 } fj_solve_stats;
 
 /* Bytes of solve workspace for this graph and options. */

@@ -399,7 +399,12 @@ struct SolveLayout {
     double* partial; void* heavy_coef; unsigned* barrier; int* abort;
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
     unsigned long long* hacc; unsigned long long* zmax_bits; double* zsh; int32_t* zqsh;
+    uint32_t* dirty; uint32_t* dirty2; int* modes; unsigned long long* snaps;
 };
+
+// dirty bits of quiet-row skipping: one bit per row plus room for a tile's
+// three-word mask at the end
+int64_t chg_words(int64_t n) { return n / 32 + 4; }
 
 int64_t cert_parts(const fj_graph* g) {
     return waves_to_blocks(g->tiles_a.nchunks + g->tiles_a.ntiles) + waves_to_blocks(g->tiles_a.nheavy) + 2;
@@ -428,6 +433,10 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     L.zmax_bits = cv.take<unsigned long long>(1);
     L.zsh = cv.take<double>(n + 1);  // merged tail, or every row in gather-form rounds
     L.zqsh = cv.take<int32_t>(n + 1);
+    L.dirty = cv.take<uint32_t>(chg_words(n));
+    L.dirty2 = cv.take<uint32_t>(chg_words(n));
+    L.modes = cv.take<int>(kMaxRounds);
+    L.snaps = cv.take<unsigned long long>(kMaxRounds);
     int64_t nb = cert_parts(g);
     L.part_max = cv.take<double>(nb);
     L.part_viol = cv.take<long long>(nb);
@@ -471,17 +480,20 @@ struct LaunchTimer {
 };
 
 struct HostStats {
-    unsigned long long pushes = 0, visits = 0;
+    unsigned long long pushes = 0, visits = 0, skipped = 0, skipped_arcs_fix = 0, skipped_arcs_fp64 = 0;
 };
 
 fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
     std::vector<unsigned long long> buf(kStripes * kStripeStride);
     FJ_HIP(hipMemcpyAsync(buf.data(), L.stats, sizeof(unsigned long long) * buf.size(), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
-    hs->pushes = hs->visits = 0;
+    hs->pushes = hs->visits = hs->skipped = hs->skipped_arcs_fix = hs->skipped_arcs_fp64 = 0;
     for (int k = 0; k < kStripes; ++k) {
         hs->pushes += buf[k * kStripeStride + 0];
         hs->visits += buf[k * kStripeStride + 1];
+        hs->skipped += buf[k * kStripeStride + 2];
+        hs->skipped_arcs_fix += buf[k * kStripeStride + 3];
+        hs->skipped_arcs_fp64 += buf[k * kStripeStride + 4];
     }
     return FJ_OK;
 }
@@ -679,11 +691,11 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
                 fj_status rc0 = timer.before();
                 if (rc0) return rc0;
                 if (mirror)
-                    hipLaunchKernelGGL((k_sor_class<true, true>), dim3(grid), dim3(kBlock), 0, st, tv, g->row_ptr,
-                                       g->col, g->w, SMIR, prev, cur, L.bad, L.stats);
+                    hipLaunchKernelGGL((k_sor_class<true, true, false>), dim3(grid), dim3(kBlock), 0, st, tv,
+                                       g->row_ptr, g->col, g->w, SMIR, prev, cur, L.bad, L.stats, nullptr);
                 else
-                    hipLaunchKernelGGL((k_sor_class<false, true>), dim3(grid), dim3(kBlock), 0, st, tv, g->row_ptr,
-                                       g->col, g->w, S64, prev, cur, L.bad, L.stats);
+                    hipLaunchKernelGGL((k_sor_class<false, true, false>), dim3(grid), dim3(kBlock), 0, st, tv,
+                                       g->row_ptr, g->col, g->w, S64, prev, cur, L.bad, L.stats, nullptr);
                 hipLaunchKernelGGL(k_sor_commit, dim3(grid1d(n, bs)), dim3(bs), 0, st, static_cast<int64_t>(0), n,
                                    L.zsh, L.zqsh, L.zh, L.zq, prev);
                 launches += 2;
@@ -741,6 +753,19 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
         return FJ_ERR_NOT_CONVERGED;
     }
     return FJ_OK;
+}
+
+// One launch of k_sor_class over tv: the skipping variant when `mode` is set.
+template <bool MIRROR, bool SHADOW>
+void launch_sor_class(const TileView& tv, const fj_graph* g, const SorState& S, const int* prev, int* cur,
+                      const SolveLayout& L, const int* mode, hipStream_t st) {
+    const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
+    if (mode)
+        hipLaunchKernelGGL((k_sor_class<MIRROR, SHADOW, true>), dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
+                           g->pcol, g->pw, S, prev, cur, L.bad, L.stats, mode);
+    else
+        hipLaunchKernelGGL((k_sor_class<MIRROR, SHADOW, false>), dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
+                           g->pcol, g->pw, S, prev, cur, L.bad, L.stats, static_cast<const int*>(nullptr));
 }
 
 fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, double epsp, double* z,
@@ -836,8 +861,25 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     sa.gs.abort = L.abort;
     const int KP = std::max(K, 32);
     std::vector<int> hfp(KP);
+    // Quiet-row skipping: an update marks the rows of A that read the updated
+    // value through the updated row's own arcs, which needs a symmetric
+    // pattern; every class must run in k_sor_class (which keeps the bits).
+    // Considered from the second sweep of each phase (fixed-point sweeps,
+    // FP64 sweeps, each refinement), once a sweep updated fewer than `limit`
+    // rows.
+    bool skipping = o->skip_below >= 0.0 && n > 0 && !g->directed;
+    for (int k = 0; k < nc && skipping; ++k)
+        if (!g->class_packed[k]) skipping = false;
+    const double limit = (o->skip_below > 0.0 ? o->skip_below : kSkipBelow) * static_cast<double>(n);
+    // The skipping variant runs in the batches of sweeps that follow a batch
+    // averaging at most batch_limit * n updates; elsewhere the plain one.
+    const double batch_limit = std::max(kSkipBatch, o->skip_below);
+    std::vector<unsigned long long> hstats(kStripes * kStripeStride);
+    unsigned long long upd_seen = 0;
     while (true) {
         bool quiet = false;
+        bool skip_batch = false;      // this batch runs the skipping variant
+        int64_t skip_run_start = -1;  // first sweep of the current run of such batches
         while (!quiet && coop_grid > 0 && !mirror) {
             if (sweeps + KP > kMaxRounds || (sweeps + KP) * (g->nnz + n) > cap) break;
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * KP, st));
@@ -874,24 +916,34 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
         if (diverged) break;
         while (!quiet) {
             if (sweeps + K > kMaxRounds || (sweeps + K) * (g->nnz + n) > cap) { capped = true; break; }
+            if (skip_batch && skip_run_start < 0) skip_run_start = sweeps;
+            if (!skip_batch) skip_run_start = -1;
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * K, st));
             for (int b = 0; b < K; ++b) {
                 int* cur = L.flags + sweeps + b;
                 const int* prev = b > 0 ? cur - 1 : nullptr;
+                SorState SW = mirror ? SMIR : S64;
+                const int* mode = nullptr;
+                if (skip_batch) {
+                    mode = L.modes + sweeps + b;
+                    SW.dirty = L.dirty;
+                    SW.dirty_tail = L.dirty2;
+                    const int64_t tail_start = merge_T < nc ? g->class_off[merge_T] : n;
+                    hipLaunchKernelGGL(k_sweep_begin, dim3(std::min<int64_t>(grid1d(chg_words(n), bs), 256)),
+                                       dim3(bs), 0, st, prev, sweeps + b, L.dirty, L.dirty2, chg_words(n),
+                                       tail_start, L.stats, L.snaps, L.modes, sweeps + b > skip_run_start ? 1 : 0,
+                                       limit);
+                    ++launches;
+                }
                 for (int k = 0; k < merge_T; ++k) {
                     const TileView& tv = views[k];
                     if (tv.ntiles == 0) continue;
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
-                    const SorState& S = mirror ? SMIR : S64;
+                    const SorState& S = SW;
                     if (g->class_packed[k]) {
-                        const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
-                        if (mirror)
-                            hipLaunchKernelGGL((k_sor_class<true, false>), dim3(grid), dim3(kBlock), 0, st, tv,
-                                               g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
-                        else
-                            hipLaunchKernelGGL((k_sor_class<false, false>), dim3(grid), dim3(kBlock), 0, st, tv,
-                                               g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                        if (mirror) launch_sor_class<true, false>(tv, g, S, prev, cur, L, mode, st);
+                        else launch_sor_class<false, false>(tv, g, S, prev, cur, L, mode, st);
                         ++launches;
                     } else {
                         const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
@@ -914,14 +966,9 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                 if (merge_T < nc) {  // the merged tail, then its commit
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
-                    const SorState& S = mirror ? SMIR : S64;
-                    const unsigned grid = waves_to_blocks(tail.nchunks + tail.ntiles);
-                    if (mirror)
-                        hipLaunchKernelGGL((k_sor_class<true, true>), dim3(grid), dim3(kBlock), 0, st, tail,
-                                           g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
-                    else
-                        hipLaunchKernelGGL((k_sor_class<false, true>), dim3(grid), dim3(kBlock), 0, st, tail,
-                                           g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats);
+                    const SorState& S = SW;
+                    if (mirror) launch_sor_class<true, true>(tail, g, S, prev, cur, L, mode, st);
+                    else launch_sor_class<false, true>(tail, g, S, prev, cur, L, mode, st);
                     hipLaunchKernelGGL(k_sor_commit, dim3(grid1d(tail_rows, bs)), dim3(bs), 0, st,
                                        g->class_off[merge_T], n, L.zsh, L.zqsh, L.zh, L.zq, prev);
                     launches += 2;
@@ -931,6 +978,9 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
             }
             FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
             FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+            if (skipping)
+                FJ_HIP(hipMemcpyAsync(hstats.data(), L.stats, sizeof(unsigned long long) * hstats.size(),
+                                      hipMemcpyDeviceToHost, st));
             FJ_HIP(hipStreamSynchronize(st));
             if (hbad) { diverged = true; break; }
             int used = K;
@@ -938,6 +988,12 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                 if (hf[b] == 0) { used = b + 1; quiet = true; break; }
             sweeps += used;
             if (mirror) mirror_sweeps += used;
+            if (skipping) {
+                unsigned long long upd = 0;
+                for (int q = 0; q < kStripes; ++q) upd += hstats[q * kStripeStride];
+                skip_batch = static_cast<double>(upd - upd_seen) <= batch_limit * static_cast<double>(n) * used;
+                upd_seen = upd;
+            }
             if (n == 0) quiet = true;
         }
         if (capped || diverged) break;
@@ -968,8 +1024,11 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     out->num_colours = nc;
     out->mirror_rounds = mirror_sweeps;
     out->merged_classes = merge_T < nc ? nc - merge_T : 0;
+    out->skipped_rows = static_cast<int64_t>(hs.skipped);
+    out->skipped_arcs = static_cast<int64_t>(hs.skipped_arcs_fix + hs.skipped_arcs_fp64);
+    out->mirror_edge_visits = mirror_sweeps * g->nnz - static_cast<int64_t>(hs.skipped_arcs_fix);
     out->pushes = static_cast<int64_t>(hs.pushes);
-    out->edge_visits = sweeps * g->nnz;
+    out->edge_visits = sweeps * g->nnz - static_cast<int64_t>(hs.skipped_arcs_fix + hs.skipped_arcs_fp64);
     out->rounds = sweeps;
     out->launches = launches;
     out->refinements = refinements;

@@ -48,6 +48,14 @@ struct SorState {
     double* zsh;                          // merged tail: new zhat' of rows >= sh_base (shadow)
     int32_t* zqsh;                        // merged tail: new fixed-point copy (shadow)
     int64_t sh_base;
+    // Quiet-row skipping (k_sor_class, symmetric pattern): a row whose own
+    // value and whose neighbours' values are all unchanged since its last
+    // sweep has the same residual as then, so it would again not update; it
+    // keeps its value without gathering.  Every update sets the "dirty" bit of
+    // the row itself and of each neighbour; a row reads and consumes its own.
+    // The sweep's mode (k_sweep_begin) is a separate kernel argument.
+    uint32_t* dirty;       // bit i: row i must be swept
+    uint32_t* dirty_tail;  // marks made inside a merged-tail launch, merged at the next sweep's start
 };
 
 // Grid-stride over the nodes; one atomic per block for the magnitude bound.
@@ -125,6 +133,46 @@ __device__ __forceinline__ bool sor_row_with(int64_t i, const RowData& d, double
 __device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S, bool* nonfinite) {
     return sor_row_with(i, row_load(i, S), sum, S, nonfinite);
 }
+// A skipped row keeps its value; in a merged tail launch it still writes it
+// to the shadow arrays, which the commit copies back.
+template <bool SHADOW>
+__device__ __forceinline__ void keep_row(int64_t i, const RowData& d, const SorState& S) {
+    if constexpr (SHADOW) {
+        S.zsh[i - S.sh_base] = d.z;
+        S.zqsh[i - S.sh_base] = fix_enc(d.z);
+    }
+}
+
+// Bits of the rows r0 .. r0 + nrows - 1: set those whose lane bit is set in
+// um and clear the others (assign), or only set (assign = false).  A tile's
+// rows span at most three words.
+__device__ __forceinline__ void tile_bits(uint32_t* bits, int64_t r0, int nrows, uint64_t um, bool assign) {
+    const int64_t w = r0 >> 5;
+    const int sh = static_cast<int>(r0 & 31);
+    const uint64_t rows = nrows >= 64 ? ~0ull : ((1ull << nrows) - 1ull);
+    const unsigned __int128 set = static_cast<unsigned __int128>(um & rows) << sh;
+    const unsigned __int128 clr = static_cast<unsigned __int128>(rows & ~um) << sh;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const uint32_t sq = static_cast<uint32_t>(set >> (32 * q)), cq = static_cast<uint32_t>(clr >> (32 * q));
+        if (assign && cq) atomicAnd(&bits[w + q], ~cq);
+        if (sq) atomicOr(&bits[w + q], sq);
+    }
+}
+__device__ __forceinline__ void mark_row(uint32_t* bits, int64_t j) { atomicOr(&bits[j >> 5], 1u << (j & 31)); }
+// Mark the columns of arcs [beg, end) by the whole wave, U column loads in
+// flight per lane (the atomics return nothing, so only the loads wait).
+template <int U>
+__device__ __forceinline__ void mark_arcs(uint32_t* bits, const int32_t* __restrict__ pcol, int beg, int end) {
+    for (int k0 = beg + lane_id(); k0 < end; k0 += 64 * U) {
+        int j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = k0 + 64 * u < end ? pcol[k0 + 64 * u] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j[u] >= 0) mark_row(bits, j[u]);
+    }
+}
 
 // Row sums of a light tile.  FP64 sweeps gather zhat'; fixed-point sweeps
 // gather the 32-bit copy, except for rows the copy cannot resolve
@@ -133,7 +181,8 @@ __device__ __forceinline__ bool sor_row(int64_t i, double sum, const SorState& S
 template <bool MIRROR>
 __device__ __forceinline__ double light_tile_sums(const int32_t* __restrict__ prow_ptr, const int32_t* __restrict__ pcol,
                                                   const float* __restrict__ pw, const SorState& S, int32_t r0,
-                                                  int nrows, const RowData& rd, int* pre, double* acc, int* flag) {
+                                                  int nrows, const RowData& rd, int* pre, double* acc, int* flag,
+                                                  const int* must = nullptr) {
     const double* __restrict__ zh = S.zh;
     const int32_t* __restrict__ zq = S.zq;
     const int lane = lane_id();
@@ -141,6 +190,21 @@ __device__ __forceinline__ double light_tile_sums(const int32_t* __restrict__ pr
         double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
         return a * zh[__builtin_nontemporal_load(&pcol[k])];
     };
+    if (must) {  // only the rows that must be swept gather (wave-uniform branch)
+        if constexpr (MIRROR) {
+            flag[lane] = lane < nrows && fix_too_coarse(rd, S.epsp) ? 1 : 0;
+            auto arcq = [&](int k) {
+                double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
+                return a * fix_dec(zq[__builtin_nontemporal_load(&pcol[k])]);
+            };
+            return tile_row_sums(prow_ptr, r0, nrows, pre, acc, [&](int k, int slot) {
+                return must[slot] ? (flag[slot] ? arc64(k) : arcq(k)) : 0.0;
+            });
+        } else {
+            return tile_row_sums(prow_ptr, r0, nrows, pre, acc,
+                                 [&](int k, int slot) { return must[slot] ? arc64(k) : 0.0; });
+        }
+    }
     if constexpr (!MIRROR) {
         return tile_row_sums(prow_ptr, r0, nrows, pre, acc, arc64);
     } else {
@@ -254,15 +318,21 @@ __device__ __forceinline__ bool to_fixed128(double p, int F, __int128* out) {
 // so within the launch every gather sees values from before it.
 // A sweep that follows a quiet sweep (no row updated) would change nothing:
 // when *prev is 0 the launch returns at once.
-template <bool MIRROR, bool SHADOW>
+// SKIP: the variant with quiet-row skipping, whose sweep mode is *mode.
+template <bool MIRROR, bool SHADOW, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
                                                       SorState S, const int* prev, int* updated, int* bad,
-                                                      unsigned long long* stats) {
+                                                      unsigned long long* stats, const int* __restrict__ mode) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
     __shared__ int s_flag[kWavesPerBlock][64];
+    __shared__ int s_must[kWavesPerBlock][64];
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
+    // 0 plain, 1 mark, 2 mark and skip (quiet-row skipping); read before any
+    // other load so that the branches on it wait for nothing else
+    int md = 0;
+    if constexpr (SKIP) md = *mode;
     const int wid = threadIdx.x >> 6, lane = lane_id();
     const double* __restrict__ zh = S.zh;
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
@@ -278,9 +348,20 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
         // row, chunk count and the row's data load while the arcs stream
         const int32_t row = tv.heavy_row[h];
         const int nch = tv.heavy_chunk0[h + 1] - tv.heavy_chunk0[h];
+        // an unmarked heavy row is skipped by all its chunk waves alike (its
+        // bit does not change during the launch)
+        if (SKIP && md == 2 && !((S.dirty[row >> 5] >> (row & 31)) & 1u)) {
+            if (lane == 0 && cidx == tv.heavy_chunk0[h]) {
+                stripe_add(stats, 2, 1ull);
+                stripe_add(stats, MIRROR ? 3 : 4, static_cast<unsigned long long>(prow_ptr[row + 1] - prow_ptr[row]));
+                if constexpr (SHADOW) keep_row<SHADOW>(row, row_load(row, S), S);
+            }
+            return;
+        }
         RowData rd{};
         if (lane == 0) rd = row_load(row, S);
         const double part = chunk_sum(beg, end, arc64);
+        int fin_upd = 0;
         if (lane == 0) {
             const int F = heavy_frac_bits(rd.opd - 1.0, S.zmax_bits);
             __int128 P = 0;
@@ -314,9 +395,21 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
                 if (upd) {
                     flag_set(updated);
                     stripe_add(stats, 0, 1ull);
+                    fin_upd = 1;
+                }
+                if (SKIP && md >= 1) {  // the row's own bit: consumed, set again if it changed
+                    if constexpr (SHADOW) {
+                        if (upd) mark_row(S.dirty_tail, row);
+                    } else {
+                        if (upd) mark_row(S.dirty, row);
+                        else atomicAnd(&S.dirty[row >> 5], ~(1u << (row & 31)));
+                    }
                 }
             }
         }
+        // an updated heavy row marks its neighbours, the whole wave taking its arcs
+        if (SKIP && md >= 1 && __shfl(fin_upd, 0, 64))
+            mark_arcs<16>(SHADOW ? S.dirty_tail : S.dirty, pcol, prow_ptr[row], prow_ptr[row + 1]);
         return;
     }
     wv -= tv.nchunks;
@@ -327,15 +420,105 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     const int nrows = tv.tile_start[tix + 1] - r0;
     RowData rd{};
     if (lane < nrows) rd = row_load(r0 + lane, S);
+    const int* must = nullptr;
+    bool sweep_row = lane < nrows;
+    if (SKIP && md == 2) {
+        const int64_t i = r0 + lane;
+        sweep_row = lane < nrows && ((S.dirty[i >> 5] >> (i & 31)) & 1u);
+        const uint64_t skipped = __ballot(lane < nrows && !sweep_row);
+        if (skipped) {  // skipped rows and their arcs (counters 2 and 3 or 4)
+            int d = lane < nrows && !sweep_row ? prow_ptr[i + 1] - prow_ptr[i] : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+            if (lane == 0) {
+                stripe_add(stats, 2, static_cast<unsigned long long>(__popcll(skipped)));
+                stripe_add(stats, MIRROR ? 3 : 4, static_cast<unsigned long long>(d));
+            }
+        }
+        if (!__ballot(sweep_row)) {  // the whole tile is quiet (its bits are already clear)
+            if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
+            return;
+        }
+        s_must[wid][lane] = sweep_row ? 1 : 0;
+        wave_sync_lds();
+        must = s_must[wid];
+    }
     const double sum = light_tile_sums<MIRROR>(prow_ptr, pcol, pw, S, r0, nrows, rd, s_pre[wid], s_acc[wid],
-                                               s_flag[wid]);
+                                               s_flag[wid], must);
     bool upd = false, nonfinite = false;
-    if (lane < nrows) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite);
+    if (sweep_row) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite);
+    else if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
     uint64_t um = __ballot(upd);
     if (__ballot(nonfinite) && lane == 0) flag_set(bad);
     if (um && lane == 0) {
         flag_set(updated);
         stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
+    }
+    if (SKIP && md >= 1) {
+        // the rows' own bits: consumed, and set again where the row changed
+        // (a merged tail's rows are cleared at the next sweep's start instead)
+        if (lane == 0) {
+            if constexpr (SHADOW) {
+                if (um) tile_bits(S.dirty_tail, r0, nrows, um, false);
+            } else {
+                tile_bits(S.dirty, r0, nrows, um, true);
+            }
+        }
+        // neighbours of the updated rows: the whole wave takes one row at a time
+        uint32_t* tgt = SHADOW ? S.dirty_tail : S.dirty;
+        for (uint64_t rem = um; rem; rem &= rem - 1) {
+            const int64_t i = r0 + __builtin_ctzll(rem);
+            mark_arcs<4>(tgt, pcol, prow_ptr[i], prow_ptr[i + 1]);
+        }
+    }
+}
+
+// Start of sweep `sw` with quiet-row skipping.  The mode: 0 while `allow` is
+// 0 (first sweep of a phase) or the previous sweep updated `limit` rows or
+// more; otherwise 1 (mark only: every row is swept, so the bits are complete
+// afterwards) after a sweep in mode 0, else 2 (mark and skip).  The update
+// count comes from the striped counters, remembered per sweep in snaps.
+// Entering mode 1 clears both bitmaps; mode 2 first takes the marks of the
+// previous sweep's merged-tail launch: the tail rows' own bits (consumed by
+// that launch) are replaced by dirty_tail.  Every block takes the same
+// decision; block 0 records it.  Returns at once after a quiet sweep.
+__global__ void k_sweep_begin(const int* prev, int64_t sw, uint32_t* dirty, uint32_t* dirty_tail, int64_t nwords,
+                              int64_t tail_start, const unsigned long long* stats, unsigned long long* snaps,
+                              int* modes, int allow, double limit) {
+    if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
+    __shared__ int s_mode[2];
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int k = 0; k < kStripes; ++k) tot += stats[k * kStripeStride];
+        int m = 0, pm = 0;
+        if (allow) {
+            pm = modes[sw - 1];
+            if (static_cast<double>(tot - snaps[sw - 1]) < limit) m = pm >= 1 ? 2 : 1;
+        }
+        s_mode[0] = m;
+        s_mode[1] = pm;
+        if (blockIdx.x == 0) {
+            snaps[sw] = tot;
+            modes[sw] = m;
+        }
+    }
+    __syncthreads();
+    const int m = s_mode[0], pm = s_mode[1];
+    if (m == 0) return;
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < nwords;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (pm == 0) {
+            dirty[w] = 0u;
+            dirty_tail[w] = 0u;
+        } else {
+            const int64_t b0 = 32 * w;  // rows of this word at or after tail_start belong to the tail
+            uint32_t tm = 0u;
+            if (b0 + 32 <= tail_start) tm = 0u;
+            else if (b0 >= tail_start) tm = ~0u;
+            else tm = ~0u << static_cast<int>(tail_start - b0);
+            dirty[w] = (dirty[w] & ~tm) | dirty_tail[w];
+            dirty_tail[w] = 0u;
+        }
     }
 }
 

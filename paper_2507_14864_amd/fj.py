@@ -55,7 +55,7 @@ class SolveOpts(ctypes.Structure):
                 ("max_edge_visits", ctypes.c_int64), ("max_refinements", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("z0", ctypes.c_void_p), ("profile", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("gather_bits", ctypes.c_int32), ("push_scatter", ctypes.c_int32),
-                ("no_tail_merge", ctypes.c_int32)]
+                ("no_tail_merge", ctypes.c_int32), ("skip_below", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -63,7 +63,9 @@ class SolveStats(ctypes.Structure):
                 ("launches", ctypes.c_int64), ("refinements", ctypes.c_int32), ("certified", ctypes.c_int32),
                 ("max_ratio", ctypes.c_double), ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("kernel_launches", ctypes.c_int64), ("num_colours", ctypes.c_int32),
-                ("mirror_rounds", ctypes.c_int64), ("merged_classes", ctypes.c_int32)]
+                ("mirror_rounds", ctypes.c_int64), ("merged_classes", ctypes.c_int32),
+                ("skipped_rows", ctypes.c_int64), ("skipped_arcs", ctypes.c_int64),
+                ("mirror_edge_visits", ctypes.c_int64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -223,18 +225,21 @@ class Graph:
 
 def make_opts(eps=1e-4, omega=1.0, c=1e-5, sigma=1e-5, precision="fp32", schedule="auto",
               max_edge_visits=0, max_refinements=-1, check_every=8, z0=None, profile=False,
-              persistent=False, gather_bits=0, tail_merge=True, push_scatter=False) -> SolveOpts:
+              persistent=False, gather_bits=0, tail_merge=True, push_scatter=False,
+              skip_below=0.0) -> SolveOpts:
     return SolveOpts(float(eps), float(omega), float(c), float(sigma), PRECISIONS[precision],
                      SCHEDULES[schedule], int(max_edge_visits), int(max_refinements), int(check_every),
                      None if z0 is None else ctypes.c_void_p(z0.data_ptr()), 1 if profile else 0,
-                     1 if persistent else 0, int(gather_bits), 1 if push_scatter else 0, 0 if tail_merge else 1)
+                     1 if persistent else 0, int(gather_bits), 1 if push_scatter else 0, 0 if tail_merge else 1,
+                     float(skip_below))
 
 
 def solve(graph: Graph, s: torch.Tensor, eps: float = 1e-4, omega: float = 1.0, c: float = 1e-5,
           sigma: float = 1e-5, precision: str = "fp32", schedule: str = "auto", max_edge_visits: int = 0,
           max_refinements: int = -1, check_every: int = 8, z0: Optional[torch.Tensor] = None,
           out: Optional[torch.Tensor] = None, profile: bool = False, persistent: bool = False,
-          gather_bits: int = 0, tail_merge: bool = True, push_scatter: bool = False):
+          gather_bits: int = 0, tail_merge: bool = True, push_scatter: bool = False,
+          skip_below: float = 0.0):
     """ImprovedBLISOR on the GPU.  Returns (z, stats dict).
 
     Raises FJNotConverged (with .z and .stats) when the certificate could not
@@ -246,7 +251,7 @@ def solve(graph: Graph, s: torch.Tensor, eps: float = 1e-4, omega: float = 1.0, 
     z = out if out is not None else torch.empty(n, dtype=torch.float64, device=graph.device)
     _dev_ptr(z, torch.float64, n, "out")
     opts = make_opts(eps, omega, c, sigma, precision, schedule, max_edge_visits, max_refinements,
-                     check_every, z0, profile, persistent, gather_bits, tail_merge, push_scatter)
+                     check_every, z0, profile, persistent, gather_bits, tail_merge, push_scatter, skip_below)
     L = lib()
     nbytes = L.fj_solve_workspace_bytes(graph.handle, ctypes.byref(opts))
     if graph._solve_ws is None or graph._solve_ws.numel() < nbytes:

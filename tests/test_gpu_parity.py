@@ -477,3 +477,31 @@ def test_metric_bounds_match_oracle(directed):
     mt = oracle.metrics(g, s, zt)
     for k in ("P", "D", "I", "C", "mean"):
         assert abs(m[k] - mt[k]) <= b[k] + 1e-12 * abs(mt[k]), k
+
+
+@pytest.mark.parametrize("directed,precision,gather_bits", [(False, "fp32", 0), (True, "fp32", 0),
+                                                            (False, "fp64", 0), (False, "fp32", 64)])
+def test_quiet_row_skipping_is_bit_exact(directed, precision, gather_bits):
+    """A row whose value and neighbours are unchanged since its last sweep has
+    the same residual, so skipping it changes nothing: the same z bit for bit,
+    the same sweeps and updates, with and without skipping (marking from the
+    second sweep and skipping from the third with skip_below = 1, and at the
+    default); merged tail included.  Directed graphs never skip."""
+    fj = fjmod()
+    g = synth.chung_lu(200000, 2000000, 2.3, 191 + directed, directed=directed, weighted=directed)
+    s = synth.opinions(g.n, "bimodal", 192)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = to_dev(s)
+    kw = dict(eps=1e-5, omega=1.0 if directed else 1.6, schedule="sor", precision=precision,
+              gather_bits=gather_bits)
+    z0, st0 = fj.solve(G, sd, skip_below=-1.0, **kw)
+    assert st0["certified"] == 1 and st0["skipped_rows"] == 0
+    for below in (1.0, 0.0):
+        z1, st1 = fj.solve(G, sd, skip_below=below, **kw)
+        assert torch.equal(z0, z1), below
+        assert (st1["rounds"], st1["pushes"], st1["max_ratio"]) == (st0["rounds"], st0["pushes"], st0["max_ratio"])
+        if below == 1.0:  # marks follow the rows of A, so only a symmetric pattern skips
+            assert (st1["skipped_rows"] > 0) == (not directed)
+        # arcs gathered plus arcs of skipped rows cover every sweep
+        assert st1["edge_visits"] + st1["skipped_arcs"] == st1["rounds"] * g.nnz
+        assert 0 <= st1["mirror_edge_visits"] <= st1["mirror_rounds"] * g.nnz
