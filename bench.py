@@ -62,8 +62,10 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
     fixed-point copy write 4); per arc 4 B column index plus the gathered
     value, 8 B (FP64) or 4 B in the sweeps that gather the fixed-point copy
     (heavy rows read 8 B there too: counted as 4, so the figure is low);
-    +4 B per arc with weights.  A row skipped as quiet counts only its
-    dirty bit (1/8 B), and its arcs are not gathered.
+    +4 B per arc with weights.  A row skipped by its residual bound counts
+    its row data and the bound (28 + 8 B) and none of its arcs; keeping the
+    bounds (a write per swept row, an atomic add per arc of an updated row)
+    is not counted.
     Push round: per node scanned 8 B (r, h), per push 44 B (row_ptr 8, r
     exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + residual
     atomic RMW 8), +4 B with weights."""
@@ -72,8 +74,7 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
         mirror_arcs = stats["mirror_edge_visits"] if schedule == "sor" else stats.get("mirror_rounds", 0) * nnz
         gather = 8 * (arcs - mirror_arcs) + 4 * mirror_arcs
         skipped = stats.get("skipped_rows", 0)
-        rows = stats["rounds"] * n - skipped
-        return (28 * rows + skipped // 8 + 20 * stats["pushes"] + 4 * arcs + gather
+        return (28 * stats["rounds"] * n + 8 * skipped + 20 * stats["pushes"] + 4 * arcs + gather
                 + (4 * arcs if weighted else 0))
     per_arc = 16 if weighted else 12
     return 8 * stats["rounds"] * n + 44 * stats["pushes"] + per_arc * stats["edge_visits"]
@@ -273,12 +274,11 @@ def main():
     ap.add_argument("--check-every", type=int, default=8,
                     help="sweeps enqueued between host checks of progress")
     ap.add_argument("--skip-below", type=float, default=0.0,
-                    help="quiet-row skipping once a sweep updates fewer than this fraction of rows "
+                    help="bound skipping once a sweep updates fewer than this fraction of rows "
                          "(0: the library default, negative: off)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

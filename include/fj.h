@@ -133,7 +133,9 @@ typedef struct {
     int32_t persistent;      /* nonzero: SOR runs as one cooperative launch with a grid
                                 barrier per colour class instead of one launch per class */
     int32_t gather_bits;     /* FJ_FP32 sweeps: 0 or 32 = light rows gather the 32-bit fixed-point
-                                copy of zhat' until quiet, then FP64; 64 = FP64 from the start */
+                                copy of zhat' until quiet, then FP64; 64 = FP64 from the start.
+                                The copy holds |zhat'| < 2: it is used only when s' = s + c and
+                                the start are below 1.5, otherwise every sweep gathers FP64 */
     int32_t push_scatter;    /* FJ_SCHED_PUSH: nonzero = every active node scatters omega r/(1+d)
                                 to its in-neighbours with atomics; 0 = the same rounds in gather
                                 form (each row recomputes its residual from the round's start
@@ -144,16 +146,16 @@ typedef struct {
                                 when every such row's coupling to them, sum_j a_ij / (1 + d_i),
                                 is below 0.9 (2/omega - 1): the Householder-John condition for
                                 convergence of the resulting splitting */
-    double skip_below;       /* FJ_SCHED_SOR on an undirected graph, quiet-row skipping.  After a
-                                batch of check_every sweeps that averaged at most
-                                max(0.1, skip_below) * n updates, a sweep that follows one with fewer than
-                                skip_below * n updates has its updates mark their rows and
-                                neighbours; from the sweep after that, a row left unmarked
-                                (its value and its neighbours' values unchanged since its last
-                                sweep) keeps its value without gathering.  Its residual, hence
-                                its no-update decision, would be the same: the result is bit
-                                for bit the one without skipping.  0 selects 0.002;
-                                negative: never */
+    double skip_below;       /* FJ_SCHED_SOR on an undirected graph, bound skipping.  From the
+                                second batch of check_every sweeps on, a sweep that follows one
+                                with fewer than skip_below * n updates keeps a bound on every row's residual: the
+                                row's own |r| at its sweep ((1 - omega) |r| after its update,
+                                Eq. (sor2)), raised by a_ij |change of zhat'_j| for each later
+                                update of a neighbour j (Lemma 4).  From the sweep after that, a
+                                row whose bound, plus the rounding of its gathered sum, stays
+                                below its update threshold keeps its value without gathering.
+                                It would not have updated: the result is bit for bit the one
+                                without skipping.  0 selects 0.05; negative: never */
 } fj_solve_opts;
 
 typedef struct {
@@ -171,7 +173,7 @@ typedef struct {
     int32_t num_colours;  /* colour classes swept (SOR), 0 for push */
     int64_t mirror_rounds; /* SOR sweeps whose light rows gathered the 32-bit fixed-point copy */
     int32_t merged_classes; /* colour classes swept together as a merged tail (0: none) */
-    int64_t skipped_rows;   /* row visits skipped by quiet-row skipping */
+    int64_t skipped_rows;   /* row visits skipped by bound skipping */
     int64_t skipped_arcs;   /* the arcs of those rows */
     int64_t mirror_edge_visits; /* arcs gathered in the sweeps that read the fixed-point copy */
 } fj_solve_stats;

@@ -17,11 +17,8 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kStripes = 64;       // striped global counters (one 128 B line each)
 constexpr int kStripeStride = 16;  // u64 per stripe line
 constexpr int kMaxColours = 2048;  // colour classes supported by the permutation pass
-// quiet-row skipping starts once a sweep updated fewer than this fraction of
-// the rows; its kernels run only after a batch of sweeps that averaged fewer
-// than kSkipBatch of the rows
-constexpr double kSkipBelow = 0.002;
-constexpr double kSkipBatch = 0.1;
+// bound skipping starts once a sweep updated fewer than this fraction of the rows
+constexpr double kSkipBelow = 0.05;
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string& msg);

@@ -399,12 +399,9 @@ struct SolveLayout {
     double* partial; void* heavy_coef; unsigned* barrier; int* abort;
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
     unsigned long long* hacc; unsigned long long* zmax_bits; double* zsh; int32_t* zqsh;
-    uint32_t* dirty; uint32_t* dirty2; int* modes; unsigned long long* snaps;
+    double* ub; double* ub_tail; int* modes; unsigned long long* snaps;
 };
 
-// dirty bits of quiet-row skipping: one bit per row plus room for a tile's
-// three-word mask at the end
-int64_t chg_words(int64_t n) { return n / 32 + 4; }
 
 int64_t cert_parts(const fj_graph* g) {
     return waves_to_blocks(g->tiles_a.nchunks + g->tiles_a.ntiles) + waves_to_blocks(g->tiles_a.nheavy) + 2;
@@ -433,8 +430,8 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     L.zmax_bits = cv.take<unsigned long long>(1);
     L.zsh = cv.take<double>(n + 1);  // merged tail, or every row in gather-form rounds
     L.zqsh = cv.take<int32_t>(n + 1);
-    L.dirty = cv.take<uint32_t>(chg_words(n));
-    L.dirty2 = cv.take<uint32_t>(chg_words(n));
+    L.ub = cv.take<double>(n + 1);       // bound skipping: residual bound per row
+    L.ub_tail = cv.take<double>(n + 1);  // and the merged tail's collected adds
     L.modes = cv.take<int>(kMaxRounds);
     L.snaps = cv.take<unsigned long long>(kMaxRounds);
     int64_t nb = cert_parts(g);
@@ -637,6 +634,17 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
     return FJ_OK;
 }
 
+// The 32-bit copy of the SOR kernels holds |zhat'| < 2.  The iterates stay
+// within the range of s' and of the start, up to the overshoot of
+// over-relaxation, so the copy is used only when that range (the init
+// kernel's magnitude bound, as bits) is below 1.5; otherwise every sweep
+// gathers FP64.
+bool fix_range_ok(unsigned long long zmax_bits) {
+    double m;
+    std::memcpy(&m, &zmax_bits, sizeof(m));
+    return m < 1.5;
+}
+
 // Bulk rounds (Alg. 1 / Alg. 3 with the FIFO order relaxed to the round sets
 // of the proof of Thm. 5) in gather form: every round recomputes each row's
 // residual r_i = s'_i - (1+d_i) zhat'_i + sum_j a_ij zhat'_j from the estimate
@@ -656,7 +664,9 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
                            static_cast<const int32_t*>(nullptr), s, o->z0, o->c, L.sp, L.zh, L.zq, L.bad,
                            L.zmax_bits);
     int hbad = 0;
+    unsigned long long hzmax = 0;
     FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipMemcpyAsync(&hzmax, L.zmax_bits, sizeof(hzmax), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
     if (hbad) {
         set_error("s must be finite and >= 0, and z0 finite");
@@ -670,7 +680,7 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
                  L.zsh, L.zqsh, 0};
     SorState SMIR = S64;
     SMIR.thr = 0.95;
-    bool mirror = o->precision == FJ_FP32 && o->gather_bits != 64;
+    bool mirror = o->precision == FJ_FP32 && o->gather_bits != 64 && fix_range_ok(hzmax);
     int64_t rounds = 0, launches = 0, mirror_rounds = 0;
     int refinements = 0;
     bool converged = false, capped = false, diverged = false;
@@ -778,7 +788,9 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
         hipLaunchKernelGGL(k_sor_init, dim3(std::min<unsigned>(grid1d(n, bs), 2048u)), dim3(bs), 0, st, n, g->perm, s,
                            o->z0, o->c, L.sp, L.zh, L.zq, L.bad, L.zmax_bits);
     int hbad = 0;
+    unsigned long long hzmax = 0;
     FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipMemcpyAsync(&hzmax, L.zmax_bits, sizeof(hzmax), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
     if (hbad) {
         set_error("s must be finite and >= 0, and z0 finite");
@@ -853,7 +865,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     // certificate holds when these sweeps go quiet.  FP64 sweeps follow if not.
     SorState SMIR = S64;
     SMIR.thr = 0.95;
-    bool mirror = o->precision == FJ_FP32 && o->gather_bits != 64;
+    bool mirror = o->precision == FJ_FP32 && o->gather_bits != 64 && fix_range_ok(hzmax);
     sa.S = S64;
     sa.bad = L.bad;
     sa.stats = L.stats;
@@ -861,25 +873,23 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     sa.gs.abort = L.abort;
     const int KP = std::max(K, 32);
     std::vector<int> hfp(KP);
-    // Quiet-row skipping: an update marks the rows of A that read the updated
-    // value through the updated row's own arcs, which needs a symmetric
-    // pattern; every class must run in k_sor_class (which keeps the bits).
-    // Considered from the second sweep of each phase (fixed-point sweeps,
-    // FP64 sweeps, each refinement), once a sweep updated fewer than `limit`
-    // rows.
+    // Bound skipping: an update raises the bounds of the rows of A that read
+    // the updated value through the updated row's own arcs, which needs a
+    // symmetric pattern; every class must run in k_sor_class (which keeps the
+    // bounds).  Considered from the second sweep of each phase (fixed-point
+    // sweeps, FP64 sweeps, each refinement), once a sweep updated fewer than
+    // `limit` rows.
     bool skipping = o->skip_below >= 0.0 && n > 0 && !g->directed;
     for (int k = 0; k < nc && skipping; ++k)
         if (!g->class_packed[k]) skipping = false;
     const double limit = (o->skip_below > 0.0 ? o->skip_below : kSkipBelow) * static_cast<double>(n);
-    // The skipping variant runs in the batches of sweeps that follow a batch
-    // averaging at most batch_limit * n updates; elsewhere the plain one.
-    const double batch_limit = std::max(kSkipBatch, o->skip_below);
-    std::vector<unsigned long long> hstats(kStripes * kStripeStride);
-    unsigned long long upd_seen = 0;
+    // The first batch of sweeps of each phase runs the plain kernel (every row
+    // updates early on); the batches after it run the skipping variant, whose
+    // mode k_sweep_begin sets per sweep from the update counts.
     while (true) {
         bool quiet = false;
         bool skip_batch = false;      // this batch runs the skipping variant
-        int64_t skip_run_start = -1;  // first sweep of the current run of such batches
+        int64_t phase_start = -1;     // first sweep of this phase in per-class launches
         while (!quiet && coop_grid > 0 && !mirror) {
             if (sweeps + KP > kMaxRounds || (sweeps + KP) * (g->nnz + n) > cap) break;
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * KP, st));
@@ -916,8 +926,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
         if (diverged) break;
         while (!quiet) {
             if (sweeps + K > kMaxRounds || (sweeps + K) * (g->nnz + n) > cap) { capped = true; break; }
-            if (skip_batch && skip_run_start < 0) skip_run_start = sweeps;
-            if (!skip_batch) skip_run_start = -1;
+            if (phase_start < 0) phase_start = sweeps;
             FJ_HIP(hipMemsetAsync(L.flags + sweeps, 0, sizeof(int) * K, st));
             for (int b = 0; b < K; ++b) {
                 int* cur = L.flags + sweeps + b;
@@ -926,13 +935,17 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                 const int* mode = nullptr;
                 if (skip_batch) {
                     mode = L.modes + sweeps + b;
-                    SW.dirty = L.dirty;
-                    SW.dirty_tail = L.dirty2;
+                    SW.ub = L.ub;
+                    SW.ub_tail = L.ub_tail;
                     const int64_t tail_start = merge_T < nc ? g->class_off[merge_T] : n;
-                    hipLaunchKernelGGL(k_sweep_begin, dim3(std::min<int64_t>(grid1d(chg_words(n), bs), 256)),
-                                       dim3(bs), 0, st, prev, sweeps + b, L.dirty, L.dirty2, chg_words(n),
-                                       tail_start, L.stats, L.snaps, L.modes, sweeps + b > skip_run_start ? 1 : 0,
-                                       limit);
+                    hipLaunchKernelGGL(k_sweep_begin,
+                                       dim3(std::max<int64_t>(1, std::min<int64_t>(grid1d(n - tail_start, bs), 256))),
+                                       dim3(bs), 0, st, prev, sweeps + b, L.ub, L.ub_tail, tail_start, n, L.stats,
+                                       L.snaps, L.modes, sweeps + b > phase_start ? 1 : 0, limit);
+                    ++launches;
+                } else if (skipping) {
+                    hipLaunchKernelGGL(k_sweep_snap, dim3(1), dim3(64), 0, st, prev, sweeps + b, L.stats, L.snaps,
+                                       L.modes);
                     ++launches;
                 }
                 for (int k = 0; k < merge_T; ++k) {
@@ -978,9 +991,6 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
             }
             FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
             FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
-            if (skipping)
-                FJ_HIP(hipMemcpyAsync(hstats.data(), L.stats, sizeof(unsigned long long) * hstats.size(),
-                                      hipMemcpyDeviceToHost, st));
             FJ_HIP(hipStreamSynchronize(st));
             if (hbad) { diverged = true; break; }
             int used = K;
@@ -988,12 +998,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                 if (hf[b] == 0) { used = b + 1; quiet = true; break; }
             sweeps += used;
             if (mirror) mirror_sweeps += used;
-            if (skipping) {
-                unsigned long long upd = 0;
-                for (int q = 0; q < kStripes; ++q) upd += hstats[q * kStripeStride];
-                skip_batch = static_cast<double>(upd - upd_seen) <= batch_limit * static_cast<double>(n) * used;
-                upd_seen = upd;
-            }
+            if (skipping) skip_batch = true;
             if (n == 0) quiet = true;
         }
         if (capped || diverged) break;

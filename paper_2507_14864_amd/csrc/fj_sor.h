@@ -48,14 +48,17 @@ struct SorState {
     double* zsh;                          // merged tail: new zhat' of rows >= sh_base (shadow)
     int32_t* zqsh;                        // merged tail: new fixed-point copy (shadow)
     int64_t sh_base;
-    // Quiet-row skipping (k_sor_class, symmetric pattern): a row whose own
-    // value and whose neighbours' values are all unchanged since its last
-    // sweep has the same residual as then, so it would again not update; it
-    // keeps its value without gathering.  Every update sets the "dirty" bit of
-    // the row itself and of each neighbour; a row reads and consumes its own.
+    // Bound skipping (k_sor_class, symmetric pattern).  ub[i] bounds |r_i|
+    // for the current estimate: the row's own residual at its last sweep
+    // (after its own update, (1 - omega) of it, Eq. (sor2)), plus
+    // a_ij |change of zhat'_j| for every neighbour update since (Lemma 4: a
+    // change of zhat'_j moves r_i by a_ij times it).  A row whose bound plus
+    // its gather error stays below the update threshold would not update, so
+    // it keeps its value without gathering: the same iteration, bit for bit.
     // The sweep's mode (k_sweep_begin) is a separate kernel argument.
-    uint32_t* dirty;       // bit i: row i must be swept
-    uint32_t* dirty_tail;  // marks made inside a merged-tail launch, merged at the next sweep's start
+    double* ub;       // [n]
+    double* ub_tail;  // [n - sh_base]: adds made inside a merged-tail launch to
+                      // its own rows, merged into ub at the next sweep's start
 };
 
 // Grid-stride over the nodes; one atomic per block for the magnitude bound.
@@ -116,11 +119,13 @@ __device__ __forceinline__ RowData row_load(int64_t i, const SorState& S) {
 // the shadow arrays, so rows of the launch gather only values from before it.
 template <bool SHADOW = false>
 __device__ __forceinline__ bool sor_row_with(int64_t i, const RowData& d, double sum, const SorState& S,
-                                             bool* nonfinite, double slack = 0.0) {
+                                             bool* nonfinite, double* r_out = nullptr, double* z_out = nullptr) {
     const double ri = d.sp - d.opd * d.z + sum;
     *nonfinite = !isfinite(ri);
-    const bool upd = fabs(ri) > S.thr * S.epsp * d.sp + slack;
+    const bool upd = fabs(ri) > S.thr * S.epsp * d.sp;
     const double z = upd ? d.z + S.omega * ri * d.inv : d.z;
+    if (r_out) *r_out = ri;
+    if (z_out) *z_out = z;
     if constexpr (SHADOW) {
         S.zsh[i - S.sh_base] = z;
         S.zqsh[i - S.sh_base] = fix_enc(z);
@@ -143,35 +148,51 @@ __device__ __forceinline__ void keep_row(int64_t i, const RowData& d, const SorS
     }
 }
 
-// Bits of the rows r0 .. r0 + nrows - 1: set those whose lane bit is set in
-// um and clear the others (assign), or only set (assign = false).  A tile's
-// rows span at most three words.
-__device__ __forceinline__ void tile_bits(uint32_t* bits, int64_t r0, int nrows, uint64_t um, bool assign) {
-    const int64_t w = r0 >> 5;
-    const int sh = static_cast<int>(r0 & 31);
-    const uint64_t rows = nrows >= 64 ? ~0ull : ((1ull << nrows) - 1ull);
-    const unsigned __int128 set = static_cast<unsigned __int128>(um & rows) << sh;
-    const unsigned __int128 clr = static_cast<unsigned __int128>(rows & ~um) << sh;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const uint32_t sq = static_cast<uint32_t>(set >> (32 * q)), cq = static_cast<uint32_t>(clr >> (32 * q));
-        if (assign && cq) atomicAnd(&bits[w + q], ~cq);
-        if (sq) atomicOr(&bits[w + q], sq);
-    }
+// Bound skipping.  The residual a sweep computes for row i differs from the
+// exact residual of the stored estimate by at most resid_err: the 32-bit copy
+// is off by at most 2^-31 per unit of arc weight, and the FP64 sums and the
+// update round far below that.
+__device__ __forceinline__ double resid_err(double opd) { return opd * 0x1p-30; }
+// the bound a row keeps after its own sweep: the exact residual is within
+// resid_err of the computed r; an update by omega r / (1 + d) leaves
+// (1 - omega) r plus the rounding of the update
+__device__ __forceinline__ double own_bound(double r, bool upd, double omega, double opd) {
+    const double e = resid_err(opd);
+    return upd ? (fabs(1.0 - omega) * fabs(r) + 2.0 * e) * (1.0 + 0x1p-40) : fabs(r) + e;
 }
-__device__ __forceinline__ void mark_row(uint32_t* bits, int64_t j) { atomicOr(&bits[j >> 5], 1u << (j & 31)); }
-// Mark the columns of arcs [beg, end) by the whole wave, U column loads in
-// flight per lane (the atomics return nothing, so only the loads wait).
-template <int U>
-__device__ __forceinline__ void mark_arcs(uint32_t* bits, const int32_t* __restrict__ pcol, int beg, int end) {
+// true when the row provably would not update: its computed residual is at
+// most ub + resid_err, below the threshold
+__device__ __forceinline__ bool bound_quiet(double ub, const RowData& d, const SorState& S) {
+    return ub + resid_err(d.opd) < 0.999 * S.thr * S.epsp * d.sp;
+}
+// An update of zhat'_i by delta (mag >= |delta|) adds a_ji mag to the bound of
+// every neighbour j (the pattern is symmetric: the columns of row i).  The
+// whole wave takes the arcs [beg, end), U loads in flight per lane (the
+// atomics return nothing).  Inside a merged-tail launch the tail's own rows
+// collect in ub_tail, since they may be computing their bounds concurrently.
+template <int U, bool SHADOW>
+__device__ __forceinline__ void bound_arcs(const SorState& S, const int32_t* __restrict__ pcol,
+                                           const float* __restrict__ pw, int beg, int end, double mag) {
     for (int k0 = beg + lane_id(); k0 < end; k0 += 64 * U) {
         int j[U];
+        double a[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = k0 + 64 * u < end ? pcol[k0 + 64 * u] : -1;
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + 64 * u;
+            j[u] = k < end ? pcol[k] : -1;
+            a[u] = pw && k < end ? static_cast<double>(pw[k]) : 1.0;
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (j[u] >= 0) mark_row(bits, j[u]);
+        for (int u = 0; u < U; ++u) {
+            if (j[u] < 0) continue;
+            if (SHADOW && j[u] >= S.sh_base) atomic_add_noret(&S.ub_tail[j[u] - S.sh_base], a[u] * mag);
+            else atomic_add_noret(&S.ub[j[u]], a[u] * mag);
+        }
     }
+}
+// |zhat'_new - zhat'_old|, rounded up
+__device__ __forceinline__ double change_mag(double znew, double zold) {
+    return fabs(znew - zold) * (1.0 + 0x1p-40);
 }
 
 // Row sums of a light tile.  FP64 sweeps gather zhat'; fixed-point sweeps
@@ -318,7 +339,7 @@ __device__ __forceinline__ bool to_fixed128(double p, int F, __int128* out) {
 // so within the launch every gather sees values from before it.
 // A sweep that follows a quiet sweep (no row updated) would change nothing:
 // when *prev is 0 the launch returns at once.
-// SKIP: the variant with quiet-row skipping, whose sweep mode is *mode.
+// SKIP: the variant with bound skipping, whose sweep mode is *mode.
 template <bool MIRROR, bool SHADOW, bool SKIP>
 __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
@@ -329,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     __shared__ int s_flag[kWavesPerBlock][64];
     __shared__ int s_must[kWavesPerBlock][64];
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
-    // 0 plain, 1 mark, 2 mark and skip (quiet-row skipping); read before any
+    // 0 plain, 1 bounds, 2 bounds and skipping (bound skipping); read before any
     // other load so that the branches on it wait for nothing else
     int md = 0;
     if constexpr (SKIP) md = *mode;
@@ -348,20 +369,27 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
         // row, chunk count and the row's data load while the arcs stream
         const int32_t row = tv.heavy_row[h];
         const int nch = tv.heavy_chunk0[h + 1] - tv.heavy_chunk0[h];
-        // an unmarked heavy row is skipped by all its chunk waves alike (its
-        // bit does not change during the launch)
-        if (SKIP && md == 2 && !((S.dirty[row >> 5] >> (row & 31)) & 1u)) {
-            if (lane == 0 && cidx == tv.heavy_chunk0[h]) {
-                stripe_add(stats, 2, 1ull);
-                stripe_add(stats, MIRROR ? 3 : 4, static_cast<unsigned long long>(prow_ptr[row + 1] - prow_ptr[row]));
-                if constexpr (SHADOW) keep_row<SHADOW>(row, row_load(row, S), S);
-            }
-            return;
-        }
+        // a heavy row whose bound shows it quiet is skipped by all its chunk
+        // waves alike (nothing writes its bound during the launch before its
+        // chunks have all arrived, and a skipped row has no arrivals)
         RowData rd{};
-        if (lane == 0) rd = row_load(row, S);
+        if (SKIP && md == 2) {
+            rd = row_load(row, S);  // the same address in every lane
+            if (bound_quiet(S.ub[row], rd, S)) {
+                if (lane == 0 && cidx == tv.heavy_chunk0[h]) {
+                    stripe_add(stats, 2, 1ull);
+                    stripe_add(stats, MIRROR ? 3 : 4,
+                               static_cast<unsigned long long>(prow_ptr[row + 1] - prow_ptr[row]));
+                    if constexpr (SHADOW) keep_row<SHADOW>(row, rd, S);
+                }
+                return;
+            }
+        } else if (lane == 0) {
+            rd = row_load(row, S);
+        }
         const double part = chunk_sum(beg, end, arc64);
         int fin_upd = 0;
+        double mag = 0.0;
         if (lane == 0) {
             const int F = heavy_frac_bits(rd.opd - 1.0, S.zmax_bits);
             __int128 P = 0;
@@ -390,26 +418,23 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
                 const double tot = ldexp(static_cast<double>(static_cast<long long>(th) >> kPackedCountBits), 32 - F) +
                                    ldexp(static_cast<double>(tl >> kPackedCountBits), -F);
                 bool nonfinite = false;
-                bool upd = sor_row_with<SHADOW>(row, rd, tot, S, &nonfinite);
+                double rr = 0.0, zn = 0.0;
+                bool upd = sor_row_with<SHADOW>(row, rd, tot, S, &nonfinite, &rr, &zn);
                 if (nonfinite) flag_set(bad);
                 if (upd) {
                     flag_set(updated);
                     stripe_add(stats, 0, 1ull);
                     fin_upd = 1;
                 }
-                if (SKIP && md >= 1) {  // the row's own bit: consumed, set again if it changed
-                    if constexpr (SHADOW) {
-                        if (upd) mark_row(S.dirty_tail, row);
-                    } else {
-                        if (upd) mark_row(S.dirty, row);
-                        else atomicAnd(&S.dirty[row >> 5], ~(1u << (row & 31)));
-                    }
+                if (SKIP && md >= 1) {  // the row's own bound
+                    S.ub[row] = own_bound(rr, upd, S.omega, rd.opd);
+                    if (upd) mag = change_mag(zn, rd.z);
                 }
             }
         }
-        // an updated heavy row marks its neighbours, the whole wave taking its arcs
+        // an updated heavy row raises its neighbours' bounds, the whole wave taking its arcs
         if (SKIP && md >= 1 && __shfl(fin_upd, 0, 64))
-            mark_arcs<16>(SHADOW ? S.dirty_tail : S.dirty, pcol, prow_ptr[row], prow_ptr[row + 1]);
+            bound_arcs<16, SHADOW>(S, pcol, pw, prow_ptr[row], prow_ptr[row + 1], __shfl(mag, 0, 64));
         return;
     }
     wv -= tv.nchunks;
@@ -424,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     bool sweep_row = lane < nrows;
     if (SKIP && md == 2) {
         const int64_t i = r0 + lane;
-        sweep_row = lane < nrows && ((S.dirty[i >> 5] >> (i & 31)) & 1u);
+        sweep_row = lane < nrows && !bound_quiet(S.ub[i], rd, S);
         const uint64_t skipped = __ballot(lane < nrows && !sweep_row);
         if (skipped) {  // skipped rows and their arcs (counters 2 and 3 or 4)
             int d = lane < nrows && !sweep_row ? prow_ptr[i + 1] - prow_ptr[i] : 0;
@@ -435,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
                 stripe_add(stats, MIRROR ? 3 : 4, static_cast<unsigned long long>(d));
             }
         }
-        if (!__ballot(sweep_row)) {  // the whole tile is quiet (its bits are already clear)
+        if (!__ballot(sweep_row)) {  // the whole tile is quiet
             if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
             return;
         }
@@ -446,7 +471,8 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     const double sum = light_tile_sums<MIRROR>(prow_ptr, pcol, pw, S, r0, nrows, rd, s_pre[wid], s_acc[wid],
                                                s_flag[wid], must);
     bool upd = false, nonfinite = false;
-    if (sweep_row) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite);
+    double rr = 0.0, zn = 0.0;
+    if (sweep_row) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite, &rr, &zn);
     else if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
     uint64_t um = __ballot(upd);
     if (__ballot(nonfinite) && lane == 0) flag_set(bad);
@@ -455,36 +481,30 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
         stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
     }
     if (SKIP && md >= 1) {
-        // the rows' own bits: consumed, and set again where the row changed
-        // (a merged tail's rows are cleared at the next sweep's start instead)
-        if (lane == 0) {
-            if constexpr (SHADOW) {
-                if (um) tile_bits(S.dirty_tail, r0, nrows, um, false);
-            } else {
-                tile_bits(S.dirty, r0, nrows, um, true);
-            }
-        }
-        // neighbours of the updated rows: the whole wave takes one row at a time
-        uint32_t* tgt = SHADOW ? S.dirty_tail : S.dirty;
+        // the swept rows' own bounds; then the neighbours of the updated rows,
+        // the whole wave taking one row at a time
+        if (sweep_row) S.ub[r0 + lane] = own_bound(rr, upd, S.omega, rd.opd);
+        const double mag = upd ? change_mag(zn, rd.z) : 0.0;
         for (uint64_t rem = um; rem; rem &= rem - 1) {
-            const int64_t i = r0 + __builtin_ctzll(rem);
-            mark_arcs<4>(tgt, pcol, prow_ptr[i], prow_ptr[i + 1]);
+            const int l = __builtin_ctzll(rem);
+            const int64_t i = r0 + l;
+            bound_arcs<4, SHADOW>(S, pcol, pw, prow_ptr[i], prow_ptr[i + 1], __shfl(mag, l, 64));
         }
     }
 }
 
-// Start of sweep `sw` with quiet-row skipping.  The mode: 0 while `allow` is
-// 0 (first sweep of a phase) or the previous sweep updated `limit` rows or
-// more; otherwise 1 (mark only: every row is swept, so the bits are complete
-// afterwards) after a sweep in mode 0, else 2 (mark and skip).  The update
-// count comes from the striped counters, remembered per sweep in snaps.
-// Entering mode 1 clears both bitmaps; mode 2 first takes the marks of the
-// previous sweep's merged-tail launch: the tail rows' own bits (consumed by
-// that launch) are replaced by dirty_tail.  Every block takes the same
-// decision; block 0 records it.  Returns at once after a quiet sweep.
-__global__ void k_sweep_begin(const int* prev, int64_t sw, uint32_t* dirty, uint32_t* dirty_tail, int64_t nwords,
-                              int64_t tail_start, const unsigned long long* stats, unsigned long long* snaps,
-                              int* modes, int allow, double limit) {
+// Start of sweep `sw` with bound skipping.  The mode: 0 while `allow` is 0
+// (first sweep of a phase) or the previous sweep updated `limit` rows or
+// more; otherwise 1 (bounds only: every row is swept, so every bound is set
+// afterwards) after a sweep in mode 0, else 2 (bounds and skipping).  The
+// update count comes from the striped counters, remembered per sweep in
+// snaps.  Entering mode 1 clears the merged tail's collected adds; mode 2
+// first adds those of the previous sweep's merged-tail launch to the tail
+// rows' bounds.  Every block takes the same decision; block 0 records it.
+// Returns at once after a quiet sweep.
+__global__ void k_sweep_begin(const int* prev, int64_t sw, double* ub, double* ub_tail, int64_t tail_start,
+                              int64_t n, const unsigned long long* stats, unsigned long long* snaps, int* modes,
+                              int allow, double limit) {
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
     __shared__ int s_mode[2];
     if (threadIdx.x == 0) {
@@ -505,21 +525,24 @@ __global__ void k_sweep_begin(const int* prev, int64_t sw, uint32_t* dirty, uint
     __syncthreads();
     const int m = s_mode[0], pm = s_mode[1];
     if (m == 0) return;
-    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < nwords;
-         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        if (pm == 0) {
-            dirty[w] = 0u;
-            dirty_tail[w] = 0u;
-        } else {
-            const int64_t b0 = 32 * w;  // rows of this word at or after tail_start belong to the tail
-            uint32_t tm = 0u;
-            if (b0 + 32 <= tail_start) tm = 0u;
-            else if (b0 >= tail_start) tm = ~0u;
-            else tm = ~0u << static_cast<int>(tail_start - b0);
-            dirty[w] = (dirty[w] & ~tm) | dirty_tail[w];
-            dirty_tail[w] = 0u;
-        }
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n - tail_start;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (pm != 0) ub[tail_start + t] += ub_tail[t];
+        ub_tail[t] = 0.0;
     }
+}
+
+// Start of a sweep of the plain kernel while bound skipping is enabled:
+// records the update count so far and mode 0, so that the sweep after it
+// may start the bounds.
+__global__ void k_sweep_snap(const int* prev, int64_t sw, const unsigned long long* stats, unsigned long long* snaps,
+                             int* modes) {
+    if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
+    if (threadIdx.x != 0) return;
+    unsigned long long tot = 0;
+    for (int k = 0; k < kStripes; ++k) tot += stats[k * kStripeStride];
+    snaps[sw] = tot;
+    modes[sw] = 0;
 }
 
 // after a merged tail launch: the shadow values become the estimate

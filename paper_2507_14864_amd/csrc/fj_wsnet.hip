@@ -135,46 +135,86 @@ __global__ void k_inv_deg(int64_t n, const double* __restrict__ opd, float* invd
 
 // ------------------------------------------------------------ aggregation
 // M_v = sum_j a_vj X_j / d_v over CSR(A) rows, X bf16 [n][D] -> M bf16 [n][D].
-// A wave owns a row; each lane holds two features (bf16x2), so one arc takes
-// D/2 lanes and a wave reads 128/D arcs per step.  Rows longer than
-// kArcBudget are done by k_agg_heavy (one 1024-thread block per row).
+// Every lane loads 16 bytes (8 features) of a gathered row, so one arc takes
+// D/8 lanes.  Rows longer than kArcBudget are done by k_agg_heavy (one
+// 1024-thread block per row); the light kernels skip them.
+struct Acc8 {
+    float v[8];
+};
+__device__ __forceinline__ void acc8_add(Acc8& acc, float a, uint4 x) {
+    const uint32_t q[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc.v[2 * t] += a * bf2f(static_cast<uint16_t>(q[t] & 0xffffu));
+        acc.v[2 * t + 1] += a * bf2f(static_cast<uint16_t>(q[t] >> 16));
+    }
+}
+__device__ __forceinline__ uint4 acc8_pack(const Acc8& acc, float sc) {
+    uint32_t q[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        q[t] = static_cast<uint32_t>(f2bf(acc.v[2 * t] * sc)) | (static_cast<uint32_t>(f2bf(acc.v[2 * t + 1] * sc)) << 16);
+    return uint4{q[0], q[1], q[2], q[3]};
+}
+
+// lanes of one wave in groups of D/8; group g takes arcs b + start + g, + stride, ...
 template <int D>
 __device__ __forceinline__ void agg_accum(int b, int e, int lane, const int32_t* __restrict__ col,
                                           const float* __restrict__ w, const uint16_t* __restrict__ X, int start,
-                                          int stride, float& a0, float& a1) {
-    constexpr int L = D / 2;              // lanes per arc
-    const int sub = lane / L, f2 = lane % L;
+                                          int stride, Acc8& acc) {
+    constexpr int L = D / 8;  // lanes per arc
+    const int sub = lane / L, part = lane % L;
     for (int k = b + start + sub; k < e; k += stride) {
         const int j = col[k];
         const float a = w ? w[k] : 1.0f;
-        const uint32_t pr = reinterpret_cast<const uint32_t*>(X + static_cast<int64_t>(j) * D)[f2];
-        a0 += a * bf2f(static_cast<uint16_t>(pr & 0xffffu));
-        a1 += a * bf2f(static_cast<uint16_t>(pr >> 16));
+        acc8_add(acc, a, reinterpret_cast<const uint4*>(X + static_cast<int64_t>(j) * D)[part]);
     }
 }
 
+// fold the 64 / (D/8) arc groups of a wave, fixed order; lanes < D/8 hold the row
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_agg_light(int64_t n, const int32_t* __restrict__ row_ptr,
+__device__ __forceinline__ void agg_fold(Acc8& acc) {
+#pragma unroll
+    for (int o = D / 8; o < 64; o <<= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
+}
+
+// D = 8: one lane per row (16 bytes per arc), grid-stride over rows.  Rows of
+// one wave are consecutive, so their arcs are neighbours in memory.
+__global__ __launch_bounds__(kBlock) void k_agg_rows8(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                     const float* __restrict__ invd, const uint16_t* __restrict__ X,
+                                                     uint16_t* M) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const int b = row_ptr[i], e = row_ptr[i + 1];
+        if (e - b > kArcBudget) continue;
+        Acc8 acc{};
+        for (int k = b; k < e; ++k) {
+            const int j = col[k];
+            const float a = w ? w[k] : 1.0f;
+            acc8_add(acc, a, reinterpret_cast<const uint4*>(X)[j]);
+        }
+        reinterpret_cast<uint4*>(M)[i] = acc8_pack(acc, invd[i]);
+    }
+}
+
+// D = 64: a wave per row, 8 lanes per arc (one 128-byte line), 8 arcs per step;
+// grid-stride over rows.
+__global__ __launch_bounds__(kBlock) void k_agg_rows64(int64_t n, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col, const float* __restrict__ w,
                                                       const float* __restrict__ invd, const uint16_t* __restrict__ X,
                                                       uint16_t* M) {
-    constexpr int L = D / 2, G = 64 / L;  // G arcs per step
     const int lane = lane_id();
-    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
-    if (i >= n) return;
-    const int b = row_ptr[i], e = row_ptr[i + 1];
-    if (e - b > kArcBudget) return;
-    float a0 = 0.f, a1 = 0.f;
-    agg_accum<D>(b, e, lane, col, w, X, 0, G, a0, a1);
-#pragma unroll
-    for (int o = L; o < 64; o <<= 1) {  // fold the G arc groups, fixed order
-        a0 += __shfl_xor(a0, o, 64);
-        a1 += __shfl_xor(a1, o, 64);
-    }
-    if (lane < L) {
-        const float s = invd[i];
-        const uint32_t pr = static_cast<uint32_t>(f2bf(a0 * s)) | (static_cast<uint32_t>(f2bf(a1 * s)) << 16);
-        reinterpret_cast<uint32_t*>(M + i * D)[lane] = pr;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); i < n; i += stride) {
+        const int b = row_ptr[i], e = row_ptr[i + 1];
+        if (e - b > kArcBudget) continue;  // uniform across the wave
+        Acc8 acc{};
+        agg_accum<kH>(b, e, lane, col, w, X, 0, 8, acc);
+        agg_fold<kH>(acc);
+        if (lane < 8) reinterpret_cast<uint4*>(M + i * kH)[lane] = acc8_pack(acc, invd[i]);
     }
 }
 
@@ -183,29 +223,31 @@ __global__ __launch_bounds__(1024) void k_agg_heavy(TileView tv, const int32_t* 
                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
                                                     const float* __restrict__ invd, const uint16_t* __restrict__ X,
                                                     uint16_t* M) {
-    constexpr int L = D / 2, G = 64 / L;
-    __shared__ float s0[16][64], s1[16][64];
+    constexpr int L = D / 8, G = 64 / L;  // lanes per arc, arcs per wave step
+    __shared__ Acc8 part[16][L];
     const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t hh = tv.h0 + blockIdx.x;
-    const int32_t i = tv.heavy_row[hh];
+    const int32_t i = tv.heavy_row[tv.h0 + blockIdx.x];
     const int b = row_ptr[i], e = row_ptr[i + 1];
-    float a0 = 0.f, a1 = 0.f;
-    agg_accum<D>(b, e, lane, col, w, X, wid * G, 16 * G, a0, a1);
-#pragma unroll
-    for (int o = L; o < 64; o <<= 1) {
-        a0 += __shfl_xor(a0, o, 64);
-        a1 += __shfl_xor(a1, o, 64);
-    }
-    s0[wid][lane] = a0;
-    s1[wid][lane] = a1;
+    Acc8 acc{};
+    agg_accum<D>(b, e, lane, col, w, X, wid * G, 16 * G, acc);
+    agg_fold<D>(acc);
+    if (lane < L) part[wid][lane] = acc;
     __syncthreads();
     if (wid == 0 && lane < L) {
-        float t0 = 0.f, t1 = 0.f;
-        for (int v = 0; v < 16; ++v) { t0 += s0[v][lane]; t1 += s1[v][lane]; }
-        const float sc = invd[i];
-        const uint32_t pr = static_cast<uint32_t>(f2bf(t0 * sc)) | (static_cast<uint32_t>(f2bf(t1 * sc)) << 16);
-        reinterpret_cast<uint32_t*>(M + static_cast<int64_t>(i) * D)[lane] = pr;
+        Acc8 t{};
+        for (int v = 0; v < 16; ++v)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t.v[q] += part[v][lane].v[q];
+        reinterpret_cast<uint4*>(M + static_cast<int64_t>(i) * D)[lane] = acc8_pack(t, invd[i]);
     }
+}
+
+// grid for the grid-stride kernels: enough waves to fill every CU, no more
+// than the work needs
+inline unsigned stride_blocks(int64_t waves, int per_cu = 16) {
+    const int64_t cap = 256 * static_cast<int64_t>(per_cu);  // blocks of 4 waves per CU
+    const int64_t need = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min(need, cap)));
 }
 
 // Backward of the aggregation: out_j = sum over u with a_uj > 0 of
@@ -273,75 +315,78 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int64_t n, const uint16_t* __re
     constexpr int K = KL + KR;
     static_assert(K % 16 == 0 && N % 16 == 0 && KL % 4 == 0, "tile shapes");
     __shared__ uint16_t Wt[N][K + 4];
-    for (int idx = threadIdx.x; idx < N * K; idx += kBlock) {
-        int j = idx / K, k = idx % K;
-        Wt[j][k] = (MODE == 3) ? W[j * K + k] : W[k * N + j];
+    for (int idx = threadIdx.x; idx < N * K; idx += kBlock) {  // coalesced reads of W
+        if constexpr (MODE == 3) Wt[idx / K][idx % K] = W[idx];
+        else Wt[idx % N][idx / N] = W[idx];
     }
     __syncthreads();
     const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 16;
-    if (row0 >= n) return;
     const int li = lane & 15, lk = (lane >> 4) * 4;
-    const int64_t ar = min(row0 + li, n - 1);
-    f32x4 acc[N / 16];
+    // grid-stride over 16-row tiles, so every block loads W once
+    const int64_t tile_stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock * 16;
+    for (int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 16; row0 < n;
+         row0 += tile_stride) {
+        const int64_t ar = min(row0 + li, n - 1);
+        f32x4 acc[N / 16];
 #pragma unroll
-    for (int t = 0; t < N / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < N / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < K / 16; ++ks) {
-        const int k = ks * 16 + lk;
-        bf16x4 a;
-        if (k < KL) a = *reinterpret_cast<const bf16x4*>(Al + ar * KL + k);
-        else a = *reinterpret_cast<const bf16x4*>(Ar + ar * KR + (k - KL));
+        for (int ks = 0; ks < K / 16; ++ks) {
+            const int k = ks * 16 + lk;
+            bf16x4 a;
+            if (k < KL) a = *reinterpret_cast<const bf16x4*>(Al + ar * KL + k);
+            else a = *reinterpret_cast<const bf16x4*>(Ar + ar * KR + (k - KL));
+#pragma unroll
+            for (int t = 0; t < N / 16; ++t) {
+                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Wt[t * 16 + li][k]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[t], 0, 0, 0);
+            }
+        }
+        if constexpr (MODE == 3) {
+#pragma unroll
+            for (int t = 0; t < N / 16; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = row0 + lk + q;
+                    if (r < n) Yout[r * N + t * 16 + li] = acc[t][q];
+                }
+            continue;
+        }
+        float p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < N / 16; ++t) {
-            const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Wt[t * 16 + li][k]);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[t], 0, 0, 0);
-        }
-    }
-    if constexpr (MODE == 3) {
-#pragma unroll
-        for (int t = 0; t < N / 16; ++t)
+            const int j = t * 16 + li;
+            const float bj = bias[j];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = row0 + lk + q;
-                if (r < n) Yout[r * N + t * 16 + li] = acc[t][q];
+                const float h = fmaxf(acc[t][q] + bj, 0.f);
+                const uint16_t hb = f2bf(h);
+                if constexpr (MODE == 0 || MODE == 1)
+                    if (r < n) Hout[r * N + j] = hb;
+                if constexpr (MODE == 1 || MODE == 2) p[q] += bf2f(hb) * u[j];
             }
-        return;
-    }
-    float p[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < N / 16; ++t) {
-        const int j = t * 16 + li;
-        const float bj = bias[j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t r = row0 + lk + q;
-            const float h = fmaxf(acc[t][q] + bj, 0.f);
-            const uint16_t hb = f2bf(h);
-            if constexpr (MODE == 0 || MODE == 1)
-                if (r < n) Hout[r * N + j] = hb;
-            if constexpr (MODE == 1 || MODE == 2) p[q] += bf2f(hb) * u[j];
         }
-    }
-    if constexpr (MODE == 1 || MODE == 2) {
+        if constexpr (MODE == 1 || MODE == 2) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) p[q] += __shfl_xor(p[q], o, 64);
-        if (li == 0) {
-            const double lo = stats[1], hi = stats[2];
+                for (int o = 1; o < 16; o <<= 1) p[q] += __shfl_xor(p[q], o, 64);
+            if (li == 0) {
+                const double lo = stats[1], hi = stats[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t r = row0 + lk + q;
-                if (r < n) {
-                    const float o = p[q] + c0[0];
-                    if (o_out) o_out[r] = o;
-                    const double sg = 1.0 / (1.0 + exp(-static_cast<double>(o)));
-                    z0[r] = lo + (hi - lo) * sg;
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = row0 + lk + q;
+                    if (r < n) {
+                        const float o = p[q] + c0[0];
+                        if (o_out) o_out[r] = o;
+                        const double sg = 1.0 / (1.0 + exp(-static_cast<double>(o)));
+                        z0[r] = lo + (hi - lo) * sg;
+                    }
                 }
             }
         }
-    }
+    }  // row tiles
 }
 
 // -------------------------------------------------- readout backward + loss
@@ -571,18 +616,17 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
     hipLaunchKernelGGL(k_inv_deg, dim3(g1d(n, bs)), dim3(bs), 0, st, n, g->opd, L.invd);
     hipLaunchKernelGGL(k_features, dim3(g1d(n, bs)), dim3(bs), 0, st, n, s, L.rs, g->opd, L.din, L.stats, L.X0);
     const TileView ta = tile_view_all(g->tiles_a);
-    const unsigned nb_rows = g1d(n * 64, kBlock);
-    hipLaunchKernelGGL(k_agg_light<kF>, dim3(nb_rows), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w, L.invd, L.X0,
-                       L.M0);
+    hipLaunchKernelGGL(k_agg_rows8, dim3(stride_blocks(g1d(n, 64))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
+                       g->w, L.invd, L.X0, L.M0);
     if (ta.h1 > ta.h0)
         hipLaunchKernelGGL(k_agg_heavy<kF>, dim3(ta.h1 - ta.h0), dim3(1024), 0, st, ta, g->row_ptr, g->col, g->w,
                            L.invd, L.X0, L.M0);
-    const unsigned nb_gemm = g1d(n, 16 * kWavesPerBlock);
+    const unsigned nb_gemm = stride_blocks(g1d(n, 16), 8);
     hipLaunchKernelGGL((k_gemm<kF, kF, kH, 0>), dim3(nb_gemm), dim3(kBlock), 0, st, n, L.X0, L.M0, L.w1b,
                        params + kOffB1, params + kOffU, params + kOffC0, L.stats, L.H1, static_cast<float*>(nullptr),
                        static_cast<float*>(nullptr), static_cast<double*>(nullptr));
-    hipLaunchKernelGGL(k_agg_light<kH>, dim3(nb_rows), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w, L.invd, L.H1,
-                       L.M1);
+    hipLaunchKernelGGL(k_agg_rows64, dim3(stride_blocks(n)), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w,
+                       L.invd, L.H1, L.M1);
     if (ta.h1 > ta.h0)
         hipLaunchKernelGGL(k_agg_heavy<kH>, dim3(ta.h1 - ta.h0), dim3(1024), 0, st, ta, g->row_ptr, g->col, g->w,
                            L.invd, L.H1, L.M1);
@@ -617,7 +661,7 @@ fj_status net_grad(const fj_graph* g, const double* s, const double* zt, const f
     hipLaunchKernelGGL(k_atb_final, dim3(g1d(129 * kH, 256)), dim3(256), 0, st, kAtbBlocks, 129 * kH, L.atb_part,
                        grad + kOffW2);
     // dA2 = dY2 W2^T (MFMA; W2 read as [N=128][K=64])
-    const unsigned nb_gemm = g1d(n, 16 * kWavesPerBlock);
+    const unsigned nb_gemm = stride_blocks(g1d(n, 16), 8);
     hipLaunchKernelGGL((k_gemm<kH, 0, 128, 3>), dim3(nb_gemm), dim3(kBlock), 0, st, n, L.dY2b,
                        static_cast<const uint16_t*>(nullptr), L.w2b, static_cast<const float*>(nullptr),
                        static_cast<const float*>(nullptr), static_cast<const float*>(nullptr),

@@ -385,6 +385,27 @@ def test_gather_precision_reaches_the_same_certificate(gather_bits):
     assert (st["mirror_rounds"] > 0) == (gather_bits == 32)
 
 
+@pytest.mark.parametrize("schedule", ["sor", "push"])
+@pytest.mark.parametrize("scale", [1.0, 1.4, 3.0, 250.0])
+def test_opinions_beyond_the_fixed_point_range(schedule, scale):
+    """The 32-bit copy holds |zhat'| < 2, so it is used only while s' and
+    the start stay below 1.5; larger opinions gather FP64 from the start.
+    Either way the result meets the same bound, and scaling s scales z
+    (the map s -> (I+L)^-1 s is linear, c scaled along)."""
+    fj = fjmod()
+    n = 20011
+    g = synth.chung_lu(n, 8 * n, 2.3, 131)
+    s = synth.opinions(n, "bimodal", 132) * scale
+    zt = oracle.exact(g, s, tol=1e-12 * scale)  # the residual scales with s
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    c = 1e-5 * scale
+    z, st = fj.solve(G, to_dev(s), eps=1e-4, omega=1.0 if schedule == "push" else 1.5, schedule=schedule,
+                     c=c, sigma=c)
+    assert st["certified"] == 1
+    check_solution(g, s, z, zt, 1e-4, c=c, sigma=c)
+    assert (st["mirror_rounds"] > 0) == (scale * (1 + 1e-5) < 1.5)
+
+
 @pytest.mark.parametrize("omega", [1.0, 1.6])
 def test_merged_tail_reaches_the_same_certificate(omega):
     """The trailing small colour classes swept as one launch (a Jacobi step
@@ -479,16 +500,19 @@ def test_metric_bounds_match_oracle(directed):
         assert abs(m[k] - mt[k]) <= b[k] + 1e-12 * abs(mt[k]), k
 
 
-@pytest.mark.parametrize("directed,precision,gather_bits", [(False, "fp32", 0), (True, "fp32", 0),
-                                                            (False, "fp64", 0), (False, "fp32", 64)])
-def test_quiet_row_skipping_is_bit_exact(directed, precision, gather_bits):
-    """A row whose value and neighbours are unchanged since its last sweep has
-    the same residual, so skipping it changes nothing: the same z bit for bit,
-    the same sweeps and updates, with and without skipping (marking from the
-    second sweep and skipping from the third with skip_below = 1, and at the
-    default); merged tail included.  Directed graphs never skip."""
+@pytest.mark.parametrize("directed,weighted,precision,gather_bits",
+                         [(False, False, "fp32", 0), (True, True, "fp32", 0), (False, True, "fp32", 0),
+                          (False, False, "fp64", 0), (False, False, "fp32", 64)])
+def test_bound_skipping_is_bit_exact(directed, weighted, precision, gather_bits):
+    """A row is skipped only while its residual bound (its own residual at its
+    last sweep, raised by a_ij |change| for every later neighbour update,
+    Lemma 4) plus its gather rounding stays below the threshold, so it would
+    not have updated: the same z bit for bit, the same sweeps and updates,
+    with and without skipping (bounds from the second sweep and skipping from
+    the third with skip_below = 1, and at the default); merged tail included.
+    Directed graphs never skip."""
     fj = fjmod()
-    g = synth.chung_lu(200000, 2000000, 2.3, 191 + directed, directed=directed, weighted=directed)
+    g = synth.chung_lu(200000, 2000000, 2.3, 191 + directed, directed=directed, weighted=weighted)
     s = synth.opinions(g.n, "bimodal", 192)
     G = fj.Graph.from_host(g, DEV, colour=True)
     sd = to_dev(s)
@@ -500,7 +524,7 @@ def test_quiet_row_skipping_is_bit_exact(directed, precision, gather_bits):
         z1, st1 = fj.solve(G, sd, skip_below=below, **kw)
         assert torch.equal(z0, z1), below
         assert (st1["rounds"], st1["pushes"], st1["max_ratio"]) == (st0["rounds"], st0["pushes"], st0["max_ratio"])
-        if below == 1.0:  # marks follow the rows of A, so only a symmetric pattern skips
+        if below == 1.0:  # bounds are raised along the rows of A, so only a symmetric pattern skips
             assert (st1["skipped_rows"] > 0) == (not directed)
         # arcs gathered plus arcs of skipped rows cover every sweep
         assert st1["edge_visits"] + st1["skipped_arcs"] == st1["rounds"] * g.nnz
