@@ -1,0 +1,167 @@
+"""Parity at the full workload sizes, in the configuration the benchmark times.
+
+Every output of the solve is compared with the oracle's exact solution (PCG or
+natural-order Gauss-Seidel until ||s - (I+L) z||_inf <= 1e-12, Lemma 1), the
+FP64 certificate is recomputed by the oracle (Lemma 7), and the Table 1
+measures are compared on the same z.  Inputs are the benchmark's own seeded
+generators.  The file sorts after the other GPU tests because each case takes
+tens of seconds of oracle time on the host.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+TOL = 1e-12  # the oracle's residual tolerance; its own error is at most this (Lemma 1: ||(I+L)^-1||_inf = 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.empty_cache()
+
+
+def _check(g, s, z, zt, eps, c=1e-5, sigma=1e-5):
+    """Lemma 7 entrywise after the shift, the relative-error claim for
+    z_v >= sigma, and the certificate recomputed in FP64 by the oracle."""
+    epsp = sigma * eps / (c + sigma)
+    assert np.all(np.isfinite(z))
+    worst = np.max(np.abs(z - zt) - epsp * (zt + c) * (1 + 1e-9) - 2 * TOL)
+    assert worst <= 0, f"Lemma 7 bound violated by {worst}"
+    assert oracle.max_rel_error(z, zt, floor=sigma) <= eps
+    assert oracle.certificate(g, s, z, eps, sigma=sigma, c=c) <= 1.0 + 1e-9
+
+
+def test_cl10m_as_benchmarked():
+    """10M nodes, ~200M stored arcs, omega 1.6, FP32 sweeps with the
+    fixed-point copy, merged tail and bound skipping: the benchmark's step."""
+    import bench
+    import paper_2507_14864_amd as fj
+    wl = bench.WORKLOADS["cl10m"]
+    g, s = bench.make_input(wl)
+    print(f"cl10m: n={g.n} nnz={g.nnz}", flush=True)
+    zt, _ = oracle.cg(g, s, TOL)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = torch.from_numpy(s).to(DEV)
+    z, st = fj.solve(G, sd, eps=wl["eps"], omega=wl["omega"], precision="fp32", schedule="sor")
+    assert st["certified"] == 1 and st["max_ratio"] <= 1.0
+    assert st["skipped_rows"] > 0 and st["merged_classes"] > 0 and st["mirror_rounds"] > 0
+    zc = z.cpu().numpy()
+    _check(g, s, zc, zt, wl["eps"])
+    # undirected: 1^T (I+L) = 1^T, so 1^T z - 1^T s = -1^T r exactly
+    r = oracle.residual(g, s, zc)
+    assert abs(zc.sum() - s.sum()) <= np.abs(r).sum() * (1 + 1e-6) + 1e-6
+    assert zc.min() >= s.min() * (1 - wl["eps"]) - 1e-5 and zc.max() <= s.max() * (1 + wl["eps"]) + 1e-5
+    # the benchmark repeats the step: bit for bit the same
+    z2, st2 = fj.solve(G, sd, eps=wl["eps"], omega=wl["omega"], precision="fp32", schedule="sor")
+    assert torch.equal(z, z2) and st2["rounds"] == st["rounds"]
+    m = fj.metrics(G, sd, z)
+    mo = oracle.metrics(g, s, zc)
+    for k in "PDIC":
+        assert abs(m[k] - mo[k]) <= 1e-10 * abs(mo[k]), (k, m[k], mo[k])
+    # the a-posteriori bounds hold the exact measures
+    mb, b, _ = fj.metrics_bounds(G, sd, z)
+    mt = oracle.metrics(g, s, zt)
+    for k in "PDIC":
+        assert abs(mb[k] - mt[k]) <= b[k] + 1e-12 * abs(mt[k]), k
+    del G, z, z2
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.2])
+def test_cl1m_directed_as_benchmarked(omega):
+    """1M nodes, 10M weighted arcs, directed: the colour-ordered sweep at the
+    two relaxation factors that converge, and the push rounds at omega 1."""
+    import bench
+    import paper_2507_14864_amd as fj
+    wl = bench.WORKLOADS["cl1m_directed"]
+    g, s = bench.make_input(wl)
+    zt, _ = oracle.gs(g, s, TOL)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = torch.from_numpy(s).to(DEV)
+    schedules = ("sor", "push") if omega == 1.0 else ("sor",)
+    for sched in schedules:
+        z, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision="fp32", schedule=sched)
+        assert st["certified"] == 1, sched
+        zc = z.cpu().numpy()
+        _check(g, s, zc, zt, wl["eps"])
+        m = fj.metrics(G, sd, z)
+        mo = oracle.metrics(g, s, zc)
+        for k in "PDIC":
+            assert abs(m[k] - mo[k]) <= 1e-10 * abs(mo[k]), (sched, k)
+    del G
+    torch.cuda.empty_cache()
+
+
+def test_heldout_5m_cold_and_network_start():
+    """The held-out directed graph (5M nodes, 50M arc samples): the cold
+    solve and the solve from the network's proposal reach the same bound."""
+    import paper_2507_14864_amd as fj
+    from paper_2507_14864_amd import warmstart
+    g, s = warmstart.heldout_problem()
+    print(f"held-out: n={g.n} nnz={g.nnz}", flush=True)
+    zt, _ = oracle.gs(g, s, TOL)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    sd = torch.from_numpy(s).to(DEV)
+    z, st = fj.solve(G, sd, eps=1e-4, omega=1.1, schedule="sor")
+    assert st["certified"] == 1
+    _check(g, s, z.cpu().numpy(), zt, 1e-4)
+    params = warmstart.load_params(DEV)
+    assert params is not None, "stored network weights are missing"
+    z0 = fj.wsnet_forward(G, sd, params)
+    z0c = z0.cpu().numpy()
+    assert np.all(np.isfinite(z0c)) and z0c.min() >= s.min() - 1e-6 and z0c.max() <= s.max() + 1e-6
+    zw, stw = fj.solve(G, sd, eps=1e-4, omega=1.1, schedule="sor", z0=z0)
+    assert stw["certified"] == 1 and stw["rounds"] < st["rounds"]
+    _check(g, s, zw.cpu().numpy(), zt, 1e-4)
+    del G
+    torch.cuda.empty_cache()
+
+
+def test_batch_as_benchmarked():
+    """64 vectors on the 2M-node graph plus 256 graphs of 1k-200k nodes, one
+    recorded sequence with tuned relaxation factors: every item certified,
+    sampled vectors and graphs against the oracle's exact solutions."""
+    import bench
+    import paper_2507_14864_amd as fj
+    big, S, smalls, ss = bench.batch_inputs()
+
+    def dev_graph(g):
+        return (torch.from_numpy(g.row_ptr).to(DEV), torch.from_numpy(g.col).to(DEV),
+                None if g.w is None else torch.from_numpy(g.w).to(DEV), g.directed)
+
+    B = fj.Batch([dev_graph(big)] + [dev_graph(g) for g in smalls], [64] + [1] * len(smalls), eps=1e-4,
+                 omega=1.5)
+    B.input(0).copy_(torch.from_numpy(S))
+    for i, s in enumerate(ss):
+        B.input(i + 1).copy_(torch.from_numpy(s))
+    B.tune([1.2, 1.4, 1.5, 1.6, 1.7])
+    B.solve_async()
+    B.solve_async()  # the benchmark's repeated steps: same inputs, same results
+    stats, mets = B.results()
+    assert all(st["certified"] == 1 for st in stats)
+    Z = B.output(0).cpu().numpy()
+    for q in (0, 21, 42, 63):  # one of each opinion law, and the last
+        zt, _ = oracle.cg(big, S[:, q], TOL)
+        _check(big, S[:, q], Z[:, q], zt, 1e-4)
+        mo = oracle.metrics(big, S[:, q], Z[:, q])
+        for k in "PDIC":
+            assert abs(mets[0][q][k] - mo[k]) <= 1e-10 * abs(mo[k]), (q, k)
+    for i in range(0, 256, 15):
+        g = smalls[i]
+        zt = oracle.exact(g, ss[i], TOL)
+        _check(g, ss[i], B.output(i + 1).cpu().numpy(), zt, 1e-4)
+    del B
+    torch.cuda.empty_cache()
