@@ -765,12 +765,17 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
     return FJ_OK;
 }
 
-// One launch of k_sor_class over tv: the skipping variant when `mode` is set.
+// One launch of k_sor_class over tv: the skipping variant when `mode` is set,
+// with kSkipGroupTiles light tiles per wave when `grouped` is also set.
 template <bool MIRROR, bool SHADOW>
 void launch_sor_class(const TileView& tv, const fj_graph* g, const SorState& S, const int* prev, int* cur,
-                      const SolveLayout& L, const int* mode, hipStream_t st) {
+                      const SolveLayout& L, const int* mode, hipStream_t st, bool grouped = false) {
     const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
-    if (mode)
+    if (mode && grouped)
+        hipLaunchKernelGGL((k_sor_class<MIRROR, SHADOW, true, kSkipGroupTiles>),
+                           dim3(waves_to_blocks(tv.nchunks + (tv.ntiles + kSkipGroupTiles - 1) / kSkipGroupTiles)),
+                           dim3(kBlock), 0, st, tv, g->prow_ptr, g->pcol, g->pw, S, prev, cur, L.bad, L.stats, mode);
+    else if (mode)
         hipLaunchKernelGGL((k_sor_class<MIRROR, SHADOW, true>), dim3(grid), dim3(kBlock), 0, st, tv, g->prow_ptr,
                            g->pcol, g->pw, S, prev, cur, L.bad, L.stats, mode);
     else
@@ -883,12 +888,14 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     for (int k = 0; k < nc && skipping; ++k)
         if (!g->class_packed[k]) skipping = false;
     const double limit = (o->skip_below > 0.0 ? o->skip_below : kSkipBelow) * static_cast<double>(n);
+    std::vector<int> hmodes(K, 0);
     // The first batch of sweeps of each phase runs the plain kernel (every row
     // updates early on); the batches after it run the skipping variant, whose
     // mode k_sweep_begin sets per sweep from the update counts.
     while (true) {
         bool quiet = false;
         bool skip_batch = false;      // this batch runs the skipping variant
+        bool grouped = false;         // ... with grouped light tiles (the last sweep skipped)
         int64_t phase_start = -1;     // first sweep of this phase in per-class launches
         while (!quiet && coop_grid > 0 && !mirror) {
             if (sweeps + KP > kMaxRounds || (sweeps + KP) * (g->nnz + n) > cap) break;
@@ -955,8 +962,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                     if (rc0) return rc0;
                     const SorState& S = SW;
                     if (g->class_packed[k]) {
-                        if (mirror) launch_sor_class<true, false>(tv, g, S, prev, cur, L, mode, st);
-                        else launch_sor_class<false, false>(tv, g, S, prev, cur, L, mode, st);
+                        if (mirror) launch_sor_class<true, false>(tv, g, S, prev, cur, L, mode, st, grouped);
+                        else launch_sor_class<false, false>(tv, g, S, prev, cur, L, mode, st, grouped);
                         ++launches;
                     } else {
                         const unsigned grid = waves_to_blocks(tv.nchunks + tv.ntiles);
@@ -980,8 +987,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                     fj_status rc0 = timer.before();
                     if (rc0) return rc0;
                     const SorState& S = SW;
-                    if (mirror) launch_sor_class<true, true>(tail, g, S, prev, cur, L, mode, st);
-                    else launch_sor_class<false, true>(tail, g, S, prev, cur, L, mode, st);
+                    if (mirror) launch_sor_class<true, true>(tail, g, S, prev, cur, L, mode, st, grouped);
+                    else launch_sor_class<false, true>(tail, g, S, prev, cur, L, mode, st, grouped);
                     hipLaunchKernelGGL(k_sor_commit, dim3(grid1d(tail_rows, bs)), dim3(bs), 0, st,
                                        g->class_off[merge_T], n, L.zsh, L.zqsh, L.zh, L.zq, prev);
                     launches += 2;
@@ -991,6 +998,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
             }
             FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
             FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+            if (skip_batch)
+                FJ_HIP(hipMemcpyAsync(hmodes.data(), L.modes + sweeps, sizeof(int) * K, hipMemcpyDeviceToHost, st));
             FJ_HIP(hipStreamSynchronize(st));
             if (hbad) { diverged = true; break; }
             int used = K;
@@ -998,6 +1007,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                 if (hf[b] == 0) { used = b + 1; quiet = true; break; }
             sweeps += used;
             if (mirror) mirror_sweeps += used;
+            // a batch whose last sweep skipped is followed by the grouped launches
+            if (skipping) grouped = skip_batch && hmodes[used - 1] == 2;
             if (skipping) skip_batch = true;
             if (n == 0) quiet = true;
         }

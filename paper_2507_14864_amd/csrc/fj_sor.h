@@ -331,6 +331,147 @@ __device__ __forceinline__ bool to_fixed128(double p, int F, __int128* out) {
     return true;
 }
 
+// One light tile (rows tv.tile_start[tix] .. tv.tile_start[tix + 1] - 1) of
+// k_sor_class, taken by the whole wave; md is the sweep's mode.  pre, acc,
+// flag and mustb are the wave's LDS scratch.
+template <bool MIRROR, bool SHADOW, bool SKIP>
+__device__ __forceinline__ void sor_light_tile(int64_t tix, int md, const TileView& tv,
+                                               const int32_t* __restrict__ prow_ptr, const int32_t* __restrict__ pcol,
+                                               const float* __restrict__ pw, const SorState& S, int* updated, int* bad,
+                                               unsigned long long* stats, int* pre, double* acc, int* flag,
+                                               int* mustb) {
+    const int lane = lane_id();
+    if (tv.tile_heavy[tix] >= 0) return;  // taken by the chunk waves
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    RowData rd{};
+    if (lane < nrows) rd = row_load(r0 + lane, S);
+    const int* must = nullptr;
+    bool sweep_row = lane < nrows;
+    if (SKIP && md == 2) {
+        const int64_t i = r0 + lane;
+        sweep_row = lane < nrows && !bound_quiet(S.ub[i], rd, S);
+        const uint64_t skipped = __ballot(lane < nrows && !sweep_row);
+        if (skipped) {  // skipped rows and their arcs (counters 2 and 3 or 4)
+            int d = lane < nrows && !sweep_row ? prow_ptr[i + 1] - prow_ptr[i] : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+            if (lane == 0) {
+                stripe_add(stats, 2, static_cast<unsigned long long>(__popcll(skipped)));
+                stripe_add(stats, MIRROR ? 3 : 4, static_cast<unsigned long long>(d));
+            }
+        }
+        if (!__ballot(sweep_row)) {  // the whole tile is quiet
+            if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
+            return;
+        }
+        mustb[lane] = sweep_row ? 1 : 0;
+        wave_sync_lds();
+        must = mustb;
+    }
+    const double sum = light_tile_sums<MIRROR>(prow_ptr, pcol, pw, S, r0, nrows, rd, pre, acc,
+                                               flag, must);
+    bool upd = false, nonfinite = false;
+    double rr = 0.0, zn = 0.0;
+    if (sweep_row) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite, &rr, &zn);
+    else if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
+    uint64_t um = __ballot(upd);
+    if (__ballot(nonfinite) && lane == 0) flag_set(bad);
+    if (um && lane == 0) {
+        flag_set(updated);
+        stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
+    }
+    if (SKIP && md >= 1) {
+        // the swept rows' own bounds; then the neighbours of the updated rows,
+        // the whole wave taking one row at a time
+        if (sweep_row) S.ub[r0 + lane] = own_bound(rr, upd, S.omega, rd.opd);
+        const double mag = upd ? change_mag(zn, rd.z) : 0.0;
+        for (uint64_t rem = um; rem; rem &= rem - 1) {
+            const int l = __builtin_ctzll(rem);
+            const int64_t i = r0 + l;
+            bound_arcs<4, SHADOW>(S, pcol, pw, prow_ptr[i], prow_ptr[i + 1], __shfl(mag, l, 64));
+        }
+    }
+}
+
+// Bound skipping with GT consecutive tiles per wave: one lane per row over
+// the group's rows (consecutive, at most 64 GT), so a quiet group costs one
+// round of coalesced loads instead of GT waves.  Returns the mask of tiles
+// holding a light row that is not provably quiet; sor_light_tile then sweeps
+// those tiles, repeating the check for its own rows.  The light rows of the
+// other tiles are counted as skipped here (and written to the shadow arrays
+// in a merged tail).  Heavy rows belong to their chunk waves.
+template <bool MIRROR, bool SHADOW, int GT>
+__device__ __forceinline__ uint32_t light_group_check(const TileView& tv, int64_t ta, int nt,
+                                                      const int32_t* __restrict__ prow_ptr, const SorState& S,
+                                                      unsigned long long* stats) {
+    constexpr int kSlices = GT;  // a tile holds at most 64 rows
+    const int lane = lane_id();
+    // lane q <= nt: first row of tile ta + q (lane nt: one past the group)
+    const int32_t ts = lane <= nt ? tv.tile_start[ta + lane] : 0;
+    int32_t tsk[GT + 1];  // the same, in every lane (all lanes are active here)
+#pragma unroll
+    for (int k = 0; k <= GT; ++k) tsk[k] = __shfl(ts, k, 64);
+    const int32_t R0 = tsk[0], R1 = __shfl(ts, nt, 64);
+    int tq[kSlices];     // the lane's row's tile within the group, -1: none or heavy
+    int dg[kSlices];     // its arc count
+    double zk[kSlices];  // its value (shadow copy of a merged tail)
+    uint32_t active = 0u;
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) {
+        tq[sl] = -1;
+        dg[sl] = 0;
+        zk[sl] = 0.0;
+        const int32_t i = R0 + 64 * sl + lane;
+        if (R0 + 64 * sl >= R1) continue;  // uniform
+        bool nq = false;
+        if (i < R1) {
+            const int d = prow_ptr[i + 1] - prow_ptr[i];
+            if (d <= kArcBudget) {
+                const double sp = __builtin_nontemporal_load(&S.sp[i]);
+                const double opd = __builtin_nontemporal_load(&S.popd[i]);
+                if constexpr (SHADOW) zk[sl] = __builtin_nontemporal_load(&S.zh[i]);
+                nq = !(S.ub[i] + resid_err(opd) < 0.999 * S.thr * S.epsp * sp);
+                int q = 0;
+#pragma unroll
+                for (int k = 1; k < GT; ++k) q += k < nt && i >= tsk[k] ? 1 : 0;
+                tq[sl] = q;
+                dg[sl] = d;
+            }
+        }
+        if (__ballot(nq))
+            for (int q = 0; q < nt; ++q)
+                if (__ballot(nq && tq[sl] == q)) active |= 1u << q;
+    }
+    // the light rows of the tiles left out: skipped
+    unsigned long long rows = 0, arcs = 0;
+#pragma unroll
+    for (int sl = 0; sl < kSlices; ++sl) {
+        const bool skip = tq[sl] >= 0 && !((active >> tq[sl]) & 1u);
+        if (skip) {
+            ++rows;
+            arcs += static_cast<unsigned long long>(dg[sl]);
+            if constexpr (SHADOW) {
+                const int64_t i = R0 + 64 * sl + lane;
+                S.zsh[i - S.sh_base] = zk[sl];
+                S.zqsh[i - S.sh_base] = fix_enc(zk[sl]);
+            }
+        }
+    }
+    if (__ballot(rows != 0)) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            rows += __shfl_xor(rows, o, 64);
+            arcs += __shfl_xor(arcs, o, 64);
+        }
+        if (lane == 0) {
+            stripe_add(stats, 2, rows);
+            stripe_add(stats, MIRROR ? 3 : 4, arcs);
+        }
+    }
+    return active;
+}
+
 // One colour class in a single launch: the first nchunks waves each sum one
 // heavy-row chunk (combined as above), the rest take one light tile each.
 // Used when no heavy row of the class has more than kMaxPackedChunks chunks.
@@ -340,7 +481,9 @@ __device__ __forceinline__ bool to_fixed128(double p, int F, __int128* out) {
 // A sweep that follows a quiet sweep (no row updated) would change nothing:
 // when *prev is 0 the launch returns at once.
 // SKIP: the variant with bound skipping, whose sweep mode is *mode.
-template <bool MIRROR, bool SHADOW, bool SKIP>
+// GT > 1 (with SKIP): each light wave takes GT consecutive tiles.
+constexpr int kSkipGroupTiles = 8;
+template <bool MIRROR, bool SHADOW, bool SKIP, int GT = 1>
 __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                       const int32_t* __restrict__ pcol, const float* __restrict__ pw,
                                                       SorState S, const int* prev, int* updated, int* bad,
@@ -438,58 +581,22 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
         return;
     }
     wv -= tv.nchunks;
-    if (wv >= tv.ntiles) return;
-    const int64_t tix = tv.t0 + wv;
-    if (tv.tile_heavy[tix] >= 0) return;  // taken by the chunk waves
-    const int32_t r0 = tv.tile_start[tix];
-    const int nrows = tv.tile_start[tix + 1] - r0;
-    RowData rd{};
-    if (lane < nrows) rd = row_load(r0 + lane, S);
-    const int* must = nullptr;
-    bool sweep_row = lane < nrows;
-    if (SKIP && md == 2) {
-        const int64_t i = r0 + lane;
-        sweep_row = lane < nrows && !bound_quiet(S.ub[i], rd, S);
-        const uint64_t skipped = __ballot(lane < nrows && !sweep_row);
-        if (skipped) {  // skipped rows and their arcs (counters 2 and 3 or 4)
-            int d = lane < nrows && !sweep_row ? prow_ptr[i + 1] - prow_ptr[i] : 0;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-            if (lane == 0) {
-                stripe_add(stats, 2, static_cast<unsigned long long>(__popcll(skipped)));
-                stripe_add(stats, MIRROR ? 3 : 4, static_cast<unsigned long long>(d));
-            }
-        }
-        if (!__ballot(sweep_row)) {  // the whole tile is quiet
-            if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
-            return;
-        }
-        s_must[wid][lane] = sweep_row ? 1 : 0;
-        wave_sync_lds();
-        must = s_must[wid];
-    }
-    const double sum = light_tile_sums<MIRROR>(prow_ptr, pcol, pw, S, r0, nrows, rd, s_pre[wid], s_acc[wid],
-                                               s_flag[wid], must);
-    bool upd = false, nonfinite = false;
-    double rr = 0.0, zn = 0.0;
-    if (sweep_row) upd = sor_row_with<SHADOW>(r0 + lane, rd, sum, S, &nonfinite, &rr, &zn);
-    else if (lane < nrows) keep_row<SHADOW>(r0 + lane, rd, S);
-    uint64_t um = __ballot(upd);
-    if (__ballot(nonfinite) && lane == 0) flag_set(bad);
-    if (um && lane == 0) {
-        flag_set(updated);
-        stripe_add(stats, 0, static_cast<unsigned long long>(__popcll(um)));
-    }
-    if (SKIP && md >= 1) {
-        // the swept rows' own bounds; then the neighbours of the updated rows,
-        // the whole wave taking one row at a time
-        if (sweep_row) S.ub[r0 + lane] = own_bound(rr, upd, S.omega, rd.opd);
-        const double mag = upd ? change_mag(zn, rd.z) : 0.0;
-        for (uint64_t rem = um; rem; rem &= rem - 1) {
-            const int l = __builtin_ctzll(rem);
-            const int64_t i = r0 + l;
-            bound_arcs<4, SHADOW>(S, pcol, pw, prow_ptr[i], prow_ptr[i + 1], __shfl(mag, l, 64));
-        }
+    if constexpr (GT == 1) {
+        if (wv >= tv.ntiles) return;
+        sor_light_tile<MIRROR, SHADOW, SKIP>(tv.t0 + wv, md, tv, prow_ptr, pcol, pw, S, updated, bad, stats,
+                                             s_pre[wid], s_acc[wid], s_flag[wid], s_must[wid]);
+    } else {
+        // GT consecutive tiles per wave: the launch shape for sweeps expected
+        // to skip; in modes 0 and 1 the wave sweeps its tiles one by one
+        const int64_t ta = tv.t0 + wv * GT;
+        const int64_t tend = tv.t0 + tv.ntiles;
+        if (ta >= tend) return;
+        const int nt = static_cast<int>(min(static_cast<int64_t>(GT), tend - ta));
+        uint32_t active = nt >= 32 ? ~0u : (1u << nt) - 1u;
+        if (md == 2) active = light_group_check<MIRROR, SHADOW, GT>(tv, ta, nt, prow_ptr, S, stats);
+        for (; active; active &= active - 1u)
+            sor_light_tile<MIRROR, SHADOW, SKIP>(ta + __builtin_ctz(active), md, tv, prow_ptr, pcol, pw, S, updated,
+                                                 bad, stats, s_pre[wid], s_acc[wid], s_flag[wid], s_must[wid]);
     }
 }
 
