@@ -180,23 +180,38 @@ __device__ __forceinline__ void agg_fold(Acc8& acc) {
         for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
 }
 
-// D = 8: one lane per row (16 bytes per arc), grid-stride over rows.  Rows of
-// one wave are consecutive, so their arcs are neighbours in memory.
+// D = 8: eight lanes per row (16 bytes per arc, lane p of a row takes its
+// arcs p, p + 8, ...), eight consecutive rows per wave, grid-stride over the
+// groups of eight rows.  The eight partial sums of a row are folded in a
+// fixed order.
 __global__ __launch_bounds__(kBlock) void k_agg_rows8(int64_t n, const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ col, const float* __restrict__ w,
                                                      const float* __restrict__ invd, const uint16_t* __restrict__ X,
                                                      uint16_t* M) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        const int b = row_ptr[i], e = row_ptr[i + 1];
-        if (e - b > kArcBudget) continue;
+    const int lane = lane_id(), p = lane & 7;
+    const int64_t groups = (n + 7) / 8;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); gi < groups;
+         gi += stride) {
+        const int64_t i = gi * 8 + (lane >> 3);
+        int b = 0, e = 0;
+        if (i < n) {
+            b = row_ptr[i];
+            e = row_ptr[i + 1];
+            if (e - b > kArcBudget) e = b;  // heavy: k_agg_heavy
+        }
         Acc8 acc{};
-        for (int k = b; k < e; ++k) {
+        for (int k = b + p; k < e; k += 8) {
             const int j = col[k];
             const float a = w ? w[k] : 1.0f;
             acc8_add(acc, a, reinterpret_cast<const uint4*>(X)[j]);
         }
-        reinterpret_cast<uint4*>(M)[i] = acc8_pack(acc, invd[i]);
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
+        if (p == 0 && i < n && row_ptr[i + 1] - row_ptr[i] <= kArcBudget)
+            reinterpret_cast<uint4*>(M)[i] = acc8_pack(acc, invd[i]);
     }
 }
 
@@ -616,7 +631,7 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
     hipLaunchKernelGGL(k_inv_deg, dim3(g1d(n, bs)), dim3(bs), 0, st, n, g->opd, L.invd);
     hipLaunchKernelGGL(k_features, dim3(g1d(n, bs)), dim3(bs), 0, st, n, s, L.rs, g->opd, L.din, L.stats, L.X0);
     const TileView ta = tile_view_all(g->tiles_a);
-    hipLaunchKernelGGL(k_agg_rows8, dim3(stride_blocks(g1d(n, 64))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
+    hipLaunchKernelGGL(k_agg_rows8, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
                        g->w, L.invd, L.X0, L.M0);
     if (ta.h1 > ta.h0)
         hipLaunchKernelGGL(k_agg_heavy<kF>, dim3(ta.h1 - ta.h0), dim3(1024), 0, st, ta, g->row_ptr, g->col, g->w,

@@ -57,9 +57,10 @@ def init_params(seed: int = 0) -> np.ndarray:
     return np.concatenate([w1, np.zeros(64), w2, np.zeros(64), u, np.zeros(1)]).astype(np.float32)
 
 
-def train(num_graphs: int = 64, epochs: int = 6, lr: float = 3e-3, device: str = "cuda:0", log=print,
-          seed: int = 0):
-    """Train on solver-generated targets.  Returns (params, loss history)."""
+def train(num_graphs: int = 64, epochs: int = 60, lr: float = 3e-3, device: str = "cuda:0", log=print,
+          seed: int = 0, decay: float = 0.95):
+    """Train on solver-generated targets, the step size times `decay` after
+    every epoch.  Returns (params, loss history)."""
     data = []
     t0 = time.perf_counter()
     for i in range(num_graphs):
@@ -76,7 +77,7 @@ def train(num_graphs: int = 64, epochs: int = 6, lr: float = 3e-3, device: str =
     hist, step = [], 0
     t0 = time.perf_counter()
     for ep in range(epochs):
-        rate = lr * (0.5 ** ep)
+        rate = lr * (decay ** ep)
         for i in rng.permutation(len(data)):
             G, sd, zt = data[i]
             step += 1
