@@ -109,10 +109,14 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(wl, budget_s):
+def cpu_baseline(wl, budget_s, g_full=None, s_full=None, gpu_edge_visits=None):
     """The oracle's sequential ImprovedBLISOR (FIFO, FP64, one core) on a
     bounded sample: a graph of the same law at 1/10 of the node and edge
-    count, solved to the same eps; time scaled by the arc-count ratio."""
+    count, solved to the same eps; time scaled by the arc-count ratio.
+    Beside it, the oracle's exact solve of the full input (PCG on all host
+    threads, or sequential Gauss-Seidel when directed, to a residual of
+    1e-12) and the ratio of the GPU's edge visits to the sequential push's
+    (scaled), the work efficiency of the parallel schedule."""
     import oracle
     import synth
     frac = 10
@@ -132,10 +136,20 @@ def cpu_baseline(wl, budget_s):
         return dict(value=None, unit="s", cores=1, kind="oracle",
                     sample=f"sequential ImprovedBLISOR omega={omega} on {g.n} nodes/{g.nnz} arcs hit the "
                            f"{budget_s}s budget after {p['edge_visits']} edge visits")
-    return dict(value=dt * scale, unit="s", cores=1, kind="oracle",
-                sample=f"sequential FIFO ImprovedBLISOR (omega={omega}, eps={wl['eps']}) fully solved on a "
-                       f"{g.n}-node/{g.nnz}-arc graph of the same law in {dt:.2f}s "
-                       f"({p['edge_visits']} edge visits); scaled x{scale:.1f} by arc count")
+    out = dict(value=dt * scale, unit="s", cores=1, kind="oracle",
+               sample=f"sequential FIFO ImprovedBLISOR (omega={omega}, eps={wl['eps']}) fully solved on a "
+                      f"{g.n}-node/{g.nnz}-arc graph of the same law in {dt:.2f}s "
+                      f"({p['edge_visits']} edge visits); scaled x{scale:.1f} by arc count")
+    if gpu_edge_visits is not None:
+        out["gpu_to_oracle_edge_visits"] = round(gpu_edge_visits / (p["edge_visits"] * scale), 3)
+    if g_full is not None:
+        t0 = time.perf_counter()
+        oracle.exact(g_full, s_full)
+        out["exact_solve"] = {"value": round(time.perf_counter() - t0, 2), "unit": "s",
+                              "cores": 1 if g_full.directed else oracle.threads(),
+                              "kind": "oracle Gauss-Seidel" if g_full.directed else "oracle Jacobi-PCG",
+                              "sample": "the full input, to ||s - (I+L) z||_inf <= 1e-12"}
+    return out
 
 
 def warm_start_eval(dev):
@@ -390,7 +404,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_budget)
+        cpu = cpu_baseline(wl, args.cpu_budget, g, s, st["edge_visits"])
         log(f"cpu baseline: {cpu}")
 
     value = ms_per_step / 1000.0
@@ -411,7 +425,7 @@ def main():
                    "omega_choice": omega_mode or "fixed", "omega_search": omega_info,
                    "schedule": args.schedule, "precision": precision, "colours": info["num_colours"],
                    "sweeps_or_rounds": st["rounds"], "merged_tail_classes": st.get("merged_classes", 0),
-                   "skipped_row_visits": st.get("skipped_rows", 0),
+                   "skipped_row_visits": st.get("skipped_rows", 0), "edge_visits": st["edge_visits"],
                    "certified": st["certified"],
                    "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),
                    "metrics": {k: m[k] for k in ("P", "D", "I", "C")},
