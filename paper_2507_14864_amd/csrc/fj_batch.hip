@@ -81,11 +81,14 @@ __global__ void k_gather_i32(int64_t n, const int32_t* __restrict__ idx, const i
 
 // --------------------------------------------------------- flags per slot
 // slot = one component of the union or one multi-vector item
-__global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done, int* all_done, int* bad) {
+__global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done, int* all_done, int* bad,
+                              unsigned long long* vupd, unsigned long long* vdone) {
     for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
         upd[s] = 0;
         done[s] = 0;
         sweeps_done[s] = 0;
+        vupd[s] = 0ull;
+        vdone[s] = 0ull;
     }
     if (threadIdx.x == 0) {
         *all_done = 0;
@@ -93,8 +96,12 @@ __global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done,
     }
 }
 
+// vupd/vdone (multi-vector items): bit l set when vector l updated in this
+// sweep / had a sweep without an update.  The vectors of an item are
+// independent systems on one graph, so a vector whose sweep changed nothing
+// is converged: its lane stops gathering (bit for bit the same result).
 __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* upd, int* done, int* sweeps_done,
-                                                   int* all_done) {
+                                                   int* all_done, unsigned long long* vupd, unsigned long long* vdone) {
     __shared__ int s_open;
     if (threadIdx.x == 0) s_open = 0;
     __syncthreads();
@@ -110,6 +117,8 @@ __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* u
             }
         }
         upd[s] = 0;
+        vdone[s] |= ~vupd[s];
+        vupd[s] = 0ull;
     }
     if (open) s_open = 1;
     __syncthreads();
@@ -197,19 +206,30 @@ struct MState {
     double* zh;          // [n][k]
     double omega, thr, epsp;
     int k;
+    const unsigned long long* vdone;  // the item's converged vectors (bit per lane)
+    unsigned long long* vupd;         // the item's vectors updated in this sweep
 };
+// set the bits of m in *mask; the read first keeps the waves of a sweep from
+// all contending for the one word once its bits are set
+__device__ __forceinline__ void vmask_or(unsigned long long* mask, unsigned long long m) {
+    if (m & ~__atomic_load_n(mask, __ATOMIC_RELAXED)) atomicOr(mask, m);
+}
+// lane l sweeps vector l while it is not converged
+__device__ __forceinline__ bool mrhs_active(const MState& S, int l) {
+    return l < S.k && !((*S.vdone >> l) & 1ull);
+}
 
-// lane l < k: sum over arcs [beg, end) of a_e * zh[col_e][l]; four arcs in flight
+// active lane l: sum over arcs [beg, end) of a_e * zh[col_e][l]; four arcs in flight
 __device__ __forceinline__ double mrhs_arc_sum(int beg, int end, const int32_t* __restrict__ pcol,
                                                const float* __restrict__ pw, const double* __restrict__ zh, int k,
-                                               int l) {
+                                               int l, bool act) {
     double acc = 0.0;
     int e = beg;
     for (; e + 3 < end; e += 4) {
         int j0 = pcol[e], j1 = pcol[e + 1], j2 = pcol[e + 2], j3 = pcol[e + 3];
         double a0 = pw ? pw[e] : 1.0, a1 = pw ? pw[e + 1] : 1.0, a2 = pw ? pw[e + 2] : 1.0, a3 = pw ? pw[e + 3] : 1.0;
         double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-        if (l < k) {
+        if (act) {
             v0 = zh[static_cast<int64_t>(j0) * k + l];
             v1 = zh[static_cast<int64_t>(j1) * k + l];
             v2 = zh[static_cast<int64_t>(j2) * k + l];
@@ -223,13 +243,13 @@ __device__ __forceinline__ double mrhs_arc_sum(int beg, int end, const int32_t* 
     for (; e < end; ++e) {
         int j = pcol[e];
         double a = pw ? pw[e] : 1.0;
-        if (l < k) acc += a * zh[static_cast<int64_t>(j) * k + l];
+        if (act) acc += a * zh[static_cast<int64_t>(j) * k + l];
     }
     return acc;
 }
 
-__device__ __forceinline__ bool mrhs_row(int64_t i, int l, double sum, const MState& S, bool* nf) {
-    if (l >= S.k) return false;
+__device__ __forceinline__ bool mrhs_row(int64_t i, int l, double sum, const MState& S, bool* nf, bool act) {
+    if (!act) return false;
     const int64_t q = i * S.k + l;
     double z = S.zh[q], sp = S.sp[q];
     double r = sp - S.popd[i] * z + sum;
@@ -255,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, 
         const int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
         const int beg = tv.chunk_beg[cidx];
         const int end = min(beg + kArcBudget, prow_ptr[row + 1]);
-        double acc = mrhs_arc_sum(beg, end, pcol, pw, S.zh, S.k, lane);
+        double acc = mrhs_arc_sum(beg, end, pcol, pw, S.zh, S.k, lane, mrhs_active(S, lane));
         if (lane < S.k) partial[cidx * S.k + lane] = acc;
         return;
     }
@@ -263,10 +283,15 @@ __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, 
     if (i >= re) return;
     const int b = prow_ptr[i], e = prow_ptr[i + 1];
     if (e - b > kArcBudget) return;  // heavy: chunks + k_msor_heavy
-    double acc = mrhs_arc_sum(b, e, pcol, pw, S.zh, S.k, lane);
+    const bool act = mrhs_active(S, lane);
+    double acc = mrhs_arc_sum(b, e, pcol, pw, S.zh, S.k, lane, act);
     bool nf = false;
-    bool u = mrhs_row(i, lane, acc, S, &nf);
-    if (__ballot(u) && lane == 0) flag_set(upd);
+    bool u = mrhs_row(i, lane, acc, S, &nf, act);
+    const unsigned long long um = __ballot(u);
+    if (um && lane == 0) {
+        flag_set(upd);
+        vmask_or(S.vupd, um);
+    }
     if (__ballot(nf) && lane == 0) flag_set(bad);
 }
 
@@ -278,12 +303,17 @@ __global__ __launch_bounds__(kBlock) void k_msor_heavy(TileView tv, MState S, co
     const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
+    const bool act = mrhs_active(S, lane);
     double sum = 0.0;
-    if (lane < S.k)
+    if (act)
         for (int32_t q = c0; q < c1; ++q) sum += partial[static_cast<int64_t>(q) * S.k + lane];
     bool nf = false;
-    bool u = mrhs_row(tv.heavy_row[hh], lane, sum, S, &nf);
-    if (__ballot(u) && lane == 0) flag_set(upd);
+    bool u = mrhs_row(tv.heavy_row[hh], lane, sum, S, &nf, act);
+    const unsigned long long um = __ballot(u);
+    if (um && lane == 0) {
+        flag_set(upd);
+        vmask_or(S.vupd, um);
+    }
     if (__ballot(nf) && lane == 0) flag_set(bad);
 }
 
@@ -608,6 +638,7 @@ struct fj_batch {
     std::vector<double> slot_omega;   // relaxation factor per slot (union component or multi-vector item)
     double* d_slot_omega = nullptr;
     int* upd = nullptr; int* done = nullptr; int* sweeps_done = nullptr; int* all_done = nullptr; int* bad = nullptr;
+    unsigned long long* vupd = nullptr; unsigned long long* vdone = nullptr;
     fj_solve_stats* stats = nullptr;
     fj_metrics_out* mets = nullptr;
     int64_t* metric_slot = nullptr;
@@ -654,6 +685,8 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
     int* swd = cv.take<int>(nslots + 1);
     int* alld = cv.take<int>(1);
     int* bad = cv.take<int>(1);
+    auto* vupd = cv.take<unsigned long long>(nslots + 1);
+    auto* vdone = cv.take<unsigned long long>(nslots + 1);
     fj_solve_stats* stats = cv.take<fj_solve_stats>(num);
     fj_metrics_out* mets = cv.take<fj_metrics_out>(total_k);
     int64_t* mslot = cv.take<int64_t>(num);
@@ -661,6 +694,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
         b->nslots = nslots;
         b->d_slot_omega = somega;
         b->upd = upd; b->done = done; b->sweeps_done = swd; b->all_done = alld; b->bad = bad;
+        b->vupd = vupd; b->vdone = vdone;
         b->stats = stats; b->mets = mets; b->metric_slot = mslot; b->total_k = total_k;
     }
     if (ncomp > 0) {
@@ -725,7 +759,7 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
     int launches = 0;
     const int bs = 256;
     hipLaunchKernelGGL(k_flags_reset, dim3(1), dim3(256), 0, st, b->nslots, b->upd, b->done, b->sweeps_done,
-                       b->all_done, b->bad);
+                       b->all_done, b->bad, b->vupd, b->vdone);
     ++launches;
     UnionGroup& U = b->U;
     const double epsp = b->epsp;
@@ -764,7 +798,8 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
                 MrhsGroup& G = b->M[m];
                 if (k >= G.g.num_colours) continue;
                 const int slot = U.ncomp + static_cast<int>(m);
-                MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->slot_omega[slot], 1.0 - 1e-6, epsp, G.k};
+                MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->slot_omega[slot], 1.0 - 1e-6, epsp, G.k,
+                         b->vdone + slot, b->vupd + slot};
                 TileView tv = tile_view(G.g.tiles_p, k);
                 const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
                 hipLaunchKernelGGL(k_msor_class, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, st,
@@ -779,7 +814,7 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
             }
         }
         hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, st, b->nslots, sw, b->upd, b->done, b->sweeps_done,
-                           b->all_done);
+                           b->all_done, b->vupd, b->vdone);
         ++launches;
     }
     // results

@@ -2,7 +2,7 @@
 // reproducible): C = z^T z, I = sum (z - s)^2, P = sum (z - mean)^2 with the
 // mean-centred vector of Sec. 3.4 (two passes, because the mean subtraction
 // cancels), D = sum over edges of a_ij (z_i - z_j)^2 (undirected: each edge
-// once, i.e. half of the sum over the stored arcs; directed: each arc once).
+// once, from its arc with j > i; directed: each arc once).
 //
 // The same passes accumulate what a-posteriori bounds on the measures need.
 // If every |z_v - z*_v| <= b_v with b_v = kappa u_v, u_v = z_v + c (Lemma 7
@@ -92,17 +92,24 @@ __global__ __launch_bounds__(kBlock) void k_metrics_centred(int64_t n, const dou
 
 // edges: each lane accumulates its own arcs over a light tile or one chunk of
 // a heavy row; fixed-order block sums of a d^2, a 2|d|(u_i + u_j), a (u_i + u_j)^2
+// upper (undirected graphs): only the arcs (i, j) with j > i, so each edge
+// once; the pattern and weights are symmetric (validated at create), so this
+// is the same sum as half of the one over all stored arcs, with half the
+// gathers.
 __global__ __launch_bounds__(kBlock) void k_metrics_edges(TileView tv, const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                          const double* __restrict__ z, double c, double* part) {
+                                                          const double* __restrict__ z, double c, int upper,
+                                                          double* part) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_z[kWavesPerBlock][64];
     __shared__ double lds[kWavesPerBlock];
     const int wid = threadIdx.x >> 6, lane = lane_id();
     const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     double acc = 0.0, acc1 = 0.0, acc2 = 0.0;
-    auto arc = [&](double zi, int k) {
-        const double zj = z[col[k]];
+    auto arc = [&](double zi, int64_t i, int k) {
+        const int j = col[k];
+        if (upper && j < i) return;
+        const double zj = z[j];
         const double d = zi - zj, us = (zi + c) + (zj + c);
         const double a = w ? static_cast<double>(w[k]) : 1.0;
         acc += a * d * d;
@@ -115,14 +122,15 @@ __global__ __launch_bounds__(kBlock) void k_metrics_edges(TileView tv, const int
         const double zi = z[row];
         const int beg = tv.chunk_beg[cc];
         const int end = min(beg + kArcBudget, row_ptr[row + 1]);
-        for (int k = beg + lane; k < end; k += 64) arc(zi, k);
+        for (int k = beg + lane; k < end; k += 64) arc(zi, row, k);
     } else if (wv - tv.nchunks < tv.ntiles) {
         const int64_t tix = tv.t0 + (wv - tv.nchunks);
         if (tv.tile_heavy[tix] < 0) {
             const int32_t r0 = tv.tile_start[tix];
             const int nrows = tv.tile_start[tix + 1] - r0;
             if (lane < nrows) s_z[wid][lane] = z[r0 + lane];
-            tile_for_each_arc(row_ptr, r0, nrows, s_pre[wid], [&](int k, int slot) { arc(s_z[wid][slot], k); });
+            tile_for_each_arc(row_ptr, r0, nrows, s_pre[wid],
+                              [&](int k, int slot) { arc(s_z[wid][slot], r0 + slot, k); });
         }
     }
     acc = block_sum<kBlock>(acc, lds);
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(1024) void k_metrics_mean(const double* part, int64
 }
 
 __global__ __launch_bounds__(1024) void k_metrics_final(const double* part_p, int64_t nbp, const double* part_d,
-                                                        int64_t nbd, int directed, double* out) {
+                                                        int64_t nbd, double* out) {
     __shared__ double lds[16];
     const double p = reduce_parts(part_p, nbp, 2, 0, lds);
     const double p1 = reduce_parts(part_p, nbp, 2, 1, lds);
@@ -174,12 +182,11 @@ __global__ __launch_bounds__(1024) void k_metrics_final(const double* part_p, in
     const double d1 = reduce_parts(part_d, nbd, 3, 1, lds);
     const double d2 = reduce_parts(part_d, nbd, 3, 2, lds);
     if (threadIdx.x == 0) {
-        const double f = directed ? 1.0 : 0.5;
         out[kOutP] = p;
         out[kOutP1] = p1;
-        out[kOutD] = f * d;
-        out[kOutD1] = f * d1;
-        out[kOutD2] = f * d2;
+        out[kOutD] = d;
+        out[kOutD1] = d1;
+        out[kOutD2] = d2;
     }
 }
 
@@ -298,11 +305,11 @@ fj_status metrics_passes(const fj_graph* g, const double* s, const double* z, do
     const unsigned nbn = nblocks_nodes(n), nbt = nblocks_edges(g);
     hipLaunchKernelGGL(k_metrics_nodes, dim3(nbn), dim3(kBlock), 0, st, n, s, z, c, L.part1);
     hipLaunchKernelGGL(k_metrics_edges, dim3(nbt), dim3(kBlock), 0, st, tile_view_all(g->tiles_a), g->row_ptr,
-                       g->col, g->w, z, c, L.part_d);
+                       g->col, g->w, z, c, g->directed ? 0 : 1, L.part_d);
     hipLaunchKernelGGL(k_metrics_mean, dim3(1), dim3(1024), 0, st, L.part1, static_cast<int64_t>(nbn), n, L.out);
     hipLaunchKernelGGL(k_metrics_centred, dim3(nbn), dim3(kBlock), 0, st, n, z, c, L.out, L.part2);
     hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(1024), 0, st, L.part2, static_cast<int64_t>(nbn), L.part_d,
-                       static_cast<int64_t>(nbt), g->directed, L.out);
+                       static_cast<int64_t>(nbt), L.out);
     FJ_HIP(hipMemcpyAsync(h, L.out, sizeof(double) * kOutSlots, hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
     return FJ_OK;
