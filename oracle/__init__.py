@@ -180,9 +180,15 @@ def metrics(g, s, z) -> dict:
 
 
 def jacobi_spectral_radius(g) -> float:
-    """mu = rho((I+D)^{-1} A), the quantity Eq. (optimal-omega) takes (Sec. 5.2):
-    all eigenvalues of the dense matrix for n <= 2000, else the largest-magnitude
-    one from scipy's Arnoldi iteration."""
+    """mu = rho((I+D)^{-1} A), the quantity Eq. (optimal-omega) takes (Sec. 5.2).
+
+    n <= 2000: every eigenvalue of the dense matrix (LAPACK).  Larger graphs:
+    scipy's ARPACK for the one eigenvalue wanted.  Undirected graphs use the
+    similar symmetric matrix (I+D)^{-1/2} A (I+D)^{-1/2} and its largest
+    algebraic eigenvalue (Lanczos), which is mu by Perron-Frobenius (the
+    matrix is nonnegative); directed graphs the largest-magnitude eigenvalue
+    of (I+D)^{-1} A (Arnoldi).  Both start from the Perron vector of a
+    regular graph ((I+D)^{1/2} 1 and 1)."""
     d = degrees(g)
     if g.n == 0:
         return 0.0
@@ -195,8 +201,15 @@ def jacobi_spectral_radius(g) -> float:
     import scipy.sparse.linalg as spla
     w = np.ones(g.nnz) if g.w is None else g.w.astype(np.float64)
     A = sp.csr_matrix((w, g.col, g.row_ptr), shape=(g.n, g.n))
+    if not g.directed:
+        q = 1.0 / np.sqrt(1.0 + d)
+        S = sp.diags(q) @ A @ sp.diags(q)
+        vals = spla.eigsh(S, k=1, which="LA", v0=np.sqrt(1.0 + d), tol=1e-13, maxiter=100000,
+                          return_eigenvectors=False)
+        return float(vals[0])
     J = sp.diags(1.0 / (1.0 + d)) @ A
-    vals = spla.eigs(J, k=1, which="LM", return_eigenvectors=False, tol=1e-12, maxiter=100000)
+    vals = spla.eigs(J, k=1, which="LM", v0=np.ones(g.n), tol=1e-13, maxiter=100000,
+                     return_eigenvectors=False)
     return float(np.max(np.abs(vals)))
 
 

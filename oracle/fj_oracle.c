@@ -187,27 +187,48 @@ int oracle_gs(int64_t n, const int32_t* row_ptr, const int32_t* col, const float
     return done ? sw : -1;
 }
 
+/* FIFO of node ids with a membership flag: every node is queued at most
+ * once, so n + 1 slots of a ring suffice. */
+typedef struct { int32_t* slot; unsigned char* queued; int64_t cap, head, tail; } fifo_t;
+static void fifo_admit(fifo_t* f, int32_t v) {
+    if (f->queued[v]) return;
+    f->slot[f->tail] = v;
+    f->tail = (f->tail + 1) % f->cap;
+    f->queued[v] = 1;
+}
+static int32_t fifo_take(fifo_t* f) {
+    int32_t v = f->slot[f->head];
+    f->head = (f->head + 1) % f->cap;
+    f->queued[v] = 0;
+    return v;
+}
+
 /* ImprovedBLISOR: the shift of Alg. 2 (ImprovedBLI) wrapped around Alg. 3
  * (BoundLocalIterSOR), as the text after Lemma 7 describes.  omega = 1 gives
  * Alg. 1 (BoundLocalIter) inside Alg. 2.
  *
- *   eps' = sigma eps / (c + sigma);  s' = s + c;  h = eps' s'     (Alg. 2)
- *   zhat' = 0, r = s', FIFO queue seeded with every node in index order
- *   pop v:  zhat'_v += omega r_v / (1 + d_v)                     (Eq. (sor1))
- *           r_u += a_uv omega r_v / (1 + d_v) for every u with a_uv > 0
- *                  (Eq. (sor3)); enqueue u if |r_u| > h_u and u is not queued
- *           r_v <- (1 - omega) r_v                                 (Eq. (sor2));
- *                  re-enqueue v if |r_v| > h_v
- *   stop when the queue is empty: then |r| <= h, and by Lemma 7
- *   |zhat' - z'| <= eps' z'; return zhat = zhat' - c.
+ * Shifted system (Alg. 2): s' = s + c, eps' = sigma eps / (c + sigma), and the
+ * threshold of node v is h_v = eps' s'_v.  The estimate starts at zhat' = 0
+ * with residual r = s', and every node waits in a FIFO queue in index order.
+ * A push at v moves three things, the over-relaxed Gauss-Seidel step of
+ * Sec. 5.2 written on the residual:
+ *   Eq. (sor1)  zhat'_v grows by omega r_v / (1 + d_v);
+ *   Eq. (sor3)  each u with a_uv > 0 (u listens to v) gains a_uv times that
+ *               amount in r_u;
+ *   Eq. (sor2)  r_v keeps (1 - omega) of itself.
+ * After the push, every node whose residual it changed (the in-neighbours of
+ * v in CSR(A^T) order, then v) joins the back of the queue if its |r| exceeds
+ * its threshold and it is not already waiting.  The loop ends with an empty
+ * queue, so |r| <= h everywhere and Lemma 7 gives |zhat' - z'| <= eps' z';
+ * the result is zhat = zhat' - c.
  *
- * Readings where the paper is terse: the threshold inside the call uses the
- * shifted opinions s' (the proof of the ImprovedBLI lemma needs h = eps' s');
- * weights enter the scatter as a_uv; the test is strict (|r| > h).
+ * Readings where the paper is terse: the threshold uses the shifted opinions
+ * s' (the proof of the ImprovedBLI lemma needs h = eps' s'); weights enter
+ * Eq. (sor3) as a_uv; the threshold test is strict (|r| > h).
  *
  * Optional warm start: if z0 != NULL, zhat' = z0 + c and r = s' - (I+L) zhat'
- * (valid for any zhat' by Lemma 4); the queue is then seeded with the nodes
- * violating the threshold, in index order.
+ * (valid for any zhat' by Lemma 4); the queue then holds the nodes over
+ * their threshold, in index order.
  *
  * max_pops / max_edge_visits: 0 = unlimited; when a cap stops the loop early
  * the function returns 1 (not converged).  A residual that has become NaN or
@@ -225,49 +246,51 @@ int oracle_push(int64_t n, const int32_t* row_ptr, const int32_t* col, const flo
     int32_t* t_col = (int32_t*)malloc(sizeof(int32_t) * (nnz ? nnz : 1));
     float* t_w = (float*)malloc(sizeof(float) * (nnz ? nnz : 1));
     double* d = (double*)malloc(sizeof(double) * n);
-    double* sp = (double*)malloc(sizeof(double) * n);
     double* h = (double*)malloc(sizeof(double) * n);
     double* r = (double*)malloc(sizeof(double) * n);
     double* zh = (double*)malloc(sizeof(double) * n);
-    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
-    unsigned char* inq = (unsigned char*)calloc((size_t)n, 1);
+    fifo_t Q = {(int32_t*)malloc(sizeof(int32_t) * (n + 1)), (unsigned char*)calloc((size_t)n + 1, 1),
+                n + 1, 0, 0};
     oracle_transpose(n, row_ptr, col, w, t_row_ptr, t_col, t_w);
     oracle_degrees(n, row_ptr, w, d);
 
-    double epsp = sigma * eps / (c + sigma);
-    for (int64_t v = 0; v < n; ++v) { sp[v] = s[v] + c; h[v] = epsp * sp[v]; }
-    int64_t qcap = n + 1, head = 0, tail = 0; /* ring buffer; at most n queued */
+    /* the shifted problem of Alg. 2 */
+    const double epsp = sigma * eps / (c + sigma);
+    for (int64_t v = 0; v < n; ++v) {
+        r[v] = s[v] + c;  /* s'; the residual of zhat' = 0 */
+        h[v] = epsp * r[v];
+        zh[v] = 0.0;
+    }
     if (z0) {
         for (int64_t v = 0; v < n; ++v) zh[v] = z0[v] + c;
+        double* sp = (double*)malloc(sizeof(double) * n);
+        memcpy(sp, r, sizeof(double) * n);
         oracle_residual(n, row_ptr, col, w, sp, zh, r);
+        free(sp);
         for (int64_t v = 0; v < n; ++v)
-            if (fabs(r[v]) > h[v]) { q[tail] = (int32_t)v; tail = (tail + 1) % qcap; inq[v] = 1; }
+            if (fabs(r[v]) > h[v]) fifo_admit(&Q, (int32_t)v);
     } else {
-        for (int64_t v = 0; v < n; ++v) {
-            zh[v] = 0.0; r[v] = sp[v];
-            q[tail] = (int32_t)v; tail = (tail + 1) % qcap; inq[v] = 1;
-        }
+        for (int64_t v = 0; v < n; ++v) fifo_admit(&Q, (int32_t)v);
     }
+
     int64_t pops = 0, visits = 0;
     int capped = 0;
-    while (head != tail) {
+    while (Q.head != Q.tail) {
         if ((max_pops && pops >= max_pops) || (max_edge_visits && visits >= max_edge_visits)) {
             capped = 1;
             break;
         }
-        int32_t v = q[head]; head = (head + 1) % qcap; inq[v] = 0;
-        double x = r[v];
-        double delta = omega * x / (1.0 + d[v]);
-        zh[v] += delta;
-        for (int64_t k = t_row_ptr[v]; k < t_row_ptr[v + 1]; ++k) {
-            int32_t u = t_col[k];
-            r[u] += (double)t_w[k] * delta;
-            if (fabs(r[u]) > h[u] && !inq[u]) { q[tail] = u; tail = (tail + 1) % qcap; inq[u] = 1; }
-        }
-        r[v] = (1.0 - omega) * x;
-        if (fabs(r[v]) > h[v] && !inq[v]) { q[tail] = v; tail = (tail + 1) % qcap; inq[v] = 1; }
+        const int32_t v = fifo_take(&Q);
+        const int64_t b = t_row_ptr[v], e = t_row_ptr[v + 1];
+        const double amount = omega * r[v] / (1.0 + d[v]);
+        zh[v] += amount;                                              /* Eq. (sor1) */
+        for (int64_t k = b; k < e; ++k) r[t_col[k]] += (double)t_w[k] * amount; /* Eq. (sor3) */
+        r[v] = (1.0 - omega) * r[v];                                  /* Eq. (sor2) */
+        for (int64_t k = b; k < e; ++k)
+            if (fabs(r[t_col[k]]) > h[t_col[k]]) fifo_admit(&Q, t_col[k]);
+        if (fabs(r[v]) > h[v]) fifo_admit(&Q, v);
         ++pops;
-        visits += t_row_ptr[v + 1] - t_row_ptr[v];
+        visits += e - b;
     }
     int finite = 1;
     for (int64_t v = 0; v < n; ++v) {
@@ -276,8 +299,8 @@ int oracle_push(int64_t n, const int32_t* row_ptr, const int32_t* col, const flo
     }
     if (out_r) memcpy(out_r, r, sizeof(double) * n);
     if (stats) { stats[0] = pops; stats[1] = visits; }
-    free(t_row_ptr); free(t_col); free(t_w); free(d); free(sp); free(h); free(r); free(zh);
-    free(q); free(inq);
+    free(t_row_ptr); free(t_col); free(t_w); free(d); free(h); free(r); free(zh);
+    free(Q.slot); free(Q.queued);
     return capped ? 1 : (finite ? 0 : 2);
 }
 

@@ -331,6 +331,26 @@ def test_certificate_bounds_relative_error():
     assert oracle.certificate(g, s, bad, 1e-4) > 1.0
 
 
+@pytest.mark.parametrize("c,sigma", [(1e-5, 1e-5), (3e-5, 1e-5), (0.0, 1e-5), (1e-5, 4e-5)])
+def test_certificate_value_with_a_planted_residual(c, sigma):
+    """Plant the residual: z = z* - (I+L)^{-1} r gives s - (I+L) z = r
+    (Lemma 1).  With r_v = t eps (s_v + c) for a constant t, the ratio of
+    Alg. 3's threshold test after Alg. 2's shift is |r_v| / (eps' (s_v + c)) =
+    t (c + sigma) / sigma at every node, eps' = sigma eps / (c + sigma).  Using
+    eps for eps', s for s + c, or a residual of the unshifted estimate gives
+    another number."""
+    g = synth.chung_lu(600, 3000, 2.3, 123, directed=True, weighted=True)
+    s = synth.opinions(g.n, "uniform", 124)
+    s[::5] = 0.0  # nodes where s and s + c differ by a factor
+    if c == 0.0:
+        s = s + 0.05
+    eps, t = 1e-3, 0.75
+    r = t * eps * (s + c) * np.where(np.arange(g.n) % 2 == 0, 1.0, -1.0)
+    z = oracle.dense_solve(g, s) - oracle.dense_solve(g, r)
+    want = t * (c + sigma) / sigma
+    assert abs(oracle.certificate(g, s, z, eps, sigma=sigma, c=c) - want) <= 1e-6 * want
+
+
 def test_fj_iterate_is_equation_one():
     """One synchronous step of Eq. (1) by hand on a weighted directed path, and
     many steps converge to the equilibrium of Lemma 1."""
@@ -402,22 +422,45 @@ def test_spectral_radius_star(k):
     assert abs(oracle.jacobi_spectral_radius(graphs.star(k)) - np.sqrt(k / (2.0 * (k + 1)))) <= 1e-12
 
 
-def test_spectral_radius_sparse_path_agrees_with_dense():
+def test_spectral_radius_sparse_path_closed_forms():
+    """n > 2000 takes the sparse (Lanczos / Arnoldi) path; pin it to closed
+    forms: the even cycle C_4000 (mu = 2/3), K_2100 (mu = 2099/2100) and the
+    star with 3000 leaves (mu^2 = k / (2 (k+1)))."""
+    assert abs(oracle.jacobi_spectral_radius(graphs.cycle(4000)) - 2.0 / 3.0) <= 1e-12
+    assert abs(oracle.jacobi_spectral_radius(graphs.complete(2100)) - 2099.0 / 2100.0) <= 1e-12
+    k = 3000
+    assert abs(oracle.jacobi_spectral_radius(graphs.star(k)) - np.sqrt(k / (2.0 * (k + 1)))) <= 1e-12
+
+
+def test_spectral_radius_sparse_path_directed_secular_equation():
+    """Directed complete graph on n = 2100 nodes where node i listens to every
+    other node with its own weight w_i: (I+D)^{-1} A = diag(al) (1 1^T - I) with
+    al_i = w_i / (1 + (n-1) w_i).  lambda is an eigenvalue iff 1 1^T - diag(1 +
+    lambda / al) is singular, i.e. sum_i al_i / (al_i + lambda) = 1; the left
+    side falls from n to 0 on lambda > 0, so the Perron root is its one
+    positive root, found here by bisection."""
+    n = 2100
+    rng = np.random.default_rng(5)
+    wr = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    arcs = [(i, j) for i in range(n) for j in range(n) if i != j]
+    g = graphs.from_arcs(n, arcs, [wr[i] for i, _ in arcs], directed=True)
+    wf = wr.astype(np.float64)
+    al = wf / (1.0 + (n - 1) * wf)
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if np.sum(al / (al + mid)) > 1.0:
+            lo = mid
+        else:
+            hi = mid
+    assert abs(oracle.jacobi_spectral_radius(g) - lo) <= 1e-12
+
+
+def test_spectral_radius_sparse_path_inside_row_sum_bound():
     g = synth.chung_lu(2500, 12000, 2.2, 85, directed=True, weighted=True)
-    mu_sparse = oracle.jacobi_spectral_radius(g)
-    sub = synth.chung_lu(1500, 7000, 2.2, 85, directed=True, weighted=True)
-    mu_dense = oracle.jacobi_spectral_radius(sub)
-    # both paths must land inside (0, max_i d_i/(1+d_i)] (row sums bound rho)
-    for gg, mu in ((g, mu_sparse), (sub, mu_dense)):
-        d = oracle.degrees(gg)
-        assert 0.0 < mu <= np.max(d / (1.0 + d)) + 1e-12
-    # and the sparse path reproduces the dense one on the same graph
-    import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
-    d = oracle.degrees(sub)
-    A = sp.csr_matrix((sub.w.astype(np.float64), sub.col, sub.row_ptr), shape=(sub.n, sub.n))
-    vals = spla.eigs(sp.diags(1.0 / (1.0 + d)) @ A, k=1, which="LM", return_eigenvectors=False, tol=1e-12)
-    assert abs(np.max(np.abs(vals)) - mu_dense) <= 1e-9
+    mu = oracle.jacobi_spectral_radius(g)
+    d = oracle.degrees(g)
+    assert 0.0 < mu <= np.max(d / (1.0 + d)) + 1e-12
 
 
 @pytest.mark.parametrize("mu", [0.0, 0.3, 2.0 / 3.0, 0.9, 0.99])
