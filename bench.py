@@ -109,47 +109,54 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(wl, budget_s, g_full=None, s_full=None, gpu_edge_visits=None):
-    """The oracle's sequential ImprovedBLISOR (FIFO, FP64, one core) on a
-    bounded sample: a graph of the same law at 1/10 of the node and edge
-    count, solved to the same eps; time scaled by the arc-count ratio.
-    Beside it, the oracle's exact solve of the full input (PCG on all host
-    threads, or sequential Gauss-Seidel when directed, to a residual of
-    1e-12) and the ratio of the GPU's edge visits to the sequential push's
-    (scaled), the work efficiency of the parallel schedule."""
+def host_cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, g, s, gpu_edge_visits=None):
+    """The oracle's sequential ImprovedBLISOR (FIFO, FP64, one core) on the
+    same input the GPU solves, to the same eps with the same omega (omega 1
+    on directed graphs).  Beside it, the oracle's exact solve of that input
+    (PCG on all host threads, or sequential Gauss-Seidel when directed, to a
+    residual of 1e-12), whose z is returned for the error report, and the
+    ratio of the GPU's edge visits to the sequential push's (the work
+    efficiency of the parallel schedule)."""
     import oracle
-    import synth
-    frac = 10
-    n, m = wl["n"] // frac, wl["m"] // frac
-    if wl["gamma"] == 0.0:
-        return None
-    g = synth.chung_lu(n, m, wl["gamma"], wl["seed"], directed=wl["directed"], weighted=wl["weighted"])
-    s = synth.opinions(g.n, wl["s_kind"], wl["seed"])
     omega = wl["omega"] if not wl["directed"] else 1.0
     t0 = time.perf_counter()
-    p = oracle.push(g, s, wl["eps"], omega=omega, max_edge_visits=int(budget_s * 8e7))
+    p = oracle.push(g, s, wl["eps"], omega=omega)
     dt = time.perf_counter() - t0
-    full_nnz_estimate = g.nnz * frac
-    scale = full_nnz_estimate / g.nnz
-    if p["capped"]:
-        # still running when the budget ran out: extrapolate from the visit rate
-        return dict(value=None, unit="s", cores=1, kind="oracle",
-                    sample=f"sequential ImprovedBLISOR omega={omega} on {g.n} nodes/{g.nnz} arcs hit the "
-                           f"{budget_s}s budget after {p['edge_visits']} edge visits")
-    out = dict(value=dt * scale, unit="s", cores=1, kind="oracle",
-               sample=f"sequential FIFO ImprovedBLISOR (omega={omega}, eps={wl['eps']}) fully solved on a "
-                      f"{g.n}-node/{g.nnz}-arc graph of the same law in {dt:.2f}s "
-                      f"({p['edge_visits']} edge visits); scaled x{scale:.1f} by arc count")
+    out = dict(value=round(dt, 3), unit="s", cores=1, kind="oracle",
+               sample=f"sequential FIFO ImprovedBLISOR (omega={omega}, eps={wl['eps']}, FP64) fully solved on the "
+                      f"benchmark's own input ({g.n} nodes, {g.nnz} arcs; {p['edge_visits']} edge visits)",
+               host_cpu=host_cpu_model(), host_threads=os.cpu_count())
     if gpu_edge_visits is not None:
-        out["gpu_to_oracle_edge_visits"] = round(gpu_edge_visits / (p["edge_visits"] * scale), 3)
-    if g_full is not None:
-        t0 = time.perf_counter()
-        oracle.exact(g_full, s_full)
-        out["exact_solve"] = {"value": round(time.perf_counter() - t0, 2), "unit": "s",
-                              "cores": 1 if g_full.directed else oracle.threads(),
-                              "kind": "oracle Gauss-Seidel" if g_full.directed else "oracle Jacobi-PCG",
-                              "sample": "the full input, to ||s - (I+L) z||_inf <= 1e-12"}
-    return out
+        out["gpu_to_oracle_edge_visits"] = round(gpu_edge_visits / max(p["edge_visits"], 1), 3)
+    t0 = time.perf_counter()
+    zt = oracle.exact(g, s)
+    out["exact_solve"] = {"value": round(time.perf_counter() - t0, 2), "unit": "s",
+                          "cores": 1 if g.directed else oracle.threads(),
+                          "kind": "oracle Gauss-Seidel" if g.directed else "oracle Jacobi-PCG",
+                          "sample": "the full input, to ||s - (I+L) z||_inf <= 1e-12"}
+    return out, zt, p["z"]
+
+
+def errors_vs_exact(g, s, z, zt, eps):
+    """Measured errors of a solve against the oracle's exact z: the largest
+    relative error of z where z_exact >= sigma = 1e-5 (the ImprovedBLI
+    guarantee), and the relative error of each Table 1 measure."""
+    import oracle
+    m, mt = oracle.metrics(g, s, z), oracle.metrics(g, s, zt)
+    return {"z_max_rel": float(f"{oracle.max_rel_error(z, zt, floor=1e-5):.3e}"),
+            **{k: float(f"{abs(m[k] - mt[k]) / abs(mt[k]):.3e}") for k in "PDIC"}, "eps": eps}
 
 
 def warm_start_eval(dev):
@@ -206,10 +213,12 @@ def batch_inputs():
     return big, S, smalls, ss
 
 
-def bench_batch(args):
+def batch_eval(dev, steps, warmup):
+    """The batched solve (64 vectors on the 2M-node graph plus 256 graphs of
+    1k-200k nodes): ingest, tune, then `steps` replays of the recorded
+    sequence timed between device synchronizations."""
     import torch
     import paper_2507_14864_amd as fj
-    dev = "cuda:0"
     t0 = time.perf_counter()
     big, S, smalls, ss = batch_inputs()
     log(f"batch inputs generated in {time.perf_counter() - t0:.1f}s: big n={big.n} nnz={big.nnz}, "
@@ -230,30 +239,40 @@ def bench_batch(args):
     t0 = time.perf_counter()
     info = B.tune([1.2, 1.4, 1.5, 1.6, 1.7])
     tune_s = time.perf_counter() - t0
-    log(f"ingest {ingest:.2f}s, tune {tune_s:.2f}s: {info}")
-    for _ in range(args.warmup):
+    log(f"batch ingest {ingest:.2f}s, tune {tune_s:.2f}s: {info}")
+    for _ in range(warmup):
         B.solve_async()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         B.solve_async()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    dt = (time.perf_counter() - t0) / max(steps, 1)
     stats, mets = B.results()
     cert = sum(s["certified"] for s in stats)
-    out = {
+    out = {"workload": "64 vectors (U[0,1], Beta(2,2), bimodal) on an undirected Chung-Lu graph with 2M nodes / "
+                       "20M edge samples, plus 256 graphs of 1k-200k nodes (average degree 8, half directed)",
+           "s_per_batch": round(dt, 5), "vector_solves_per_s": round(320 / dt, 1), "eps": 1e-4,
+           "omega_multi": info["omega_multi"], "omega_undirected": info["omega_undirected"],
+           "omega_directed": info["omega_directed"], "sweep_budget": info["sweep_budget"],
+           "graph_nodes": info["graph_nodes"], "certified_items": cert, "items": len(stats),
+           "max_sweeps_used": max(s["rounds"] for s in stats), "ingest_s": round(ingest, 2),
+           "tune_s": round(tune_s, 2), "steps": steps}
+    del B
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(args):
+    out = batch_eval("cuda:0", args.steps, args.warmup)
+    dt = out["s_per_batch"]
+    line = {
         "metric": "batched FJ solve time (64 vectors on a 2M-node graph + 256 graphs of 1k-200k nodes, eps 1e-4)",
-        "value": round(dt, 5), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(dt * 1000, 3), "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "batch", "vectors": 64 + len(smalls), "vector_solves_per_s": round(320 / dt, 1),
-                   "omega_multi": info["omega_multi"], "omega_undirected": info["omega_undirected"],
-                   "omega_directed": info["omega_directed"], "sweep_budget": info["sweep_budget"],
-                   "graph_nodes": info["graph_nodes"], "certified_items": cert, "items": len(stats),
-                   "max_sweeps_used": max(s["rounds"] for s in stats), "ingest_s": round(ingest, 2),
-                   "tune_ms": [round(x, 1) for x in info["tune_ms"][:5]]},
+        "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1000, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": {"workload": "batch", **out},
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -271,10 +290,11 @@ def main():
                          "the estimate or the tuning runs before the timed steps")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the learned warm start evaluation on the held-out 5M-node directed graph")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched solve (64 vectors on a 2M-node graph + 256 small graphs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--gather-bits", type=int, default=0, choices=[0, 32, 64],
@@ -385,7 +405,7 @@ def main():
                         traffic=measured_traffic() if args.schedule == "sor" and args.workload == "cl10m" else None,
                         kernel=("k_sor_class" if args.schedule == "sor" or not args.push_scatter
                                 else "k_push_light+k_push_heavy"),
-                        bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
+                        algorithmic_bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
                         launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))
         log(f"profiled step: {stp}")
 
@@ -402,10 +422,18 @@ def main():
         warm = warm_start_eval(dev)
         log(f"warm start: {warm}")
 
-    cpu = None
+    batch = None
+    if not args.no_batch and args.workload == "cl10m":
+        batch = batch_eval(dev, steps=3, warmup=1)
+        log(f"batch: {batch}")
+
+    cpu, errors = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_budget, g, s, st["edge_visits"])
+        cpu, zt, z_fifo = cpu_baseline(wl, g, s, st["edge_visits"])
         log(f"cpu baseline: {cpu}")
+        errors = {"gpu": errors_vs_exact(g, s, z.cpu().numpy(), zt, wl["eps"]),
+                  "oracle_push": errors_vs_exact(g, s, z_fifo, zt, wl["eps"])}
+        log(f"errors against the exact z: {errors}")
 
     value = ms_per_step / 1000.0
     out = {
@@ -432,7 +460,9 @@ def main():
                    "metric_bounds": {"tau": tau, **{k: bounds[k] for k in ("P", "D", "I", "C")}}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "errors_vs_exact": errors,
         "warm_start": warm,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

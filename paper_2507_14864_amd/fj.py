@@ -5,6 +5,7 @@ device memory (workspaces are torch uint8 tensors) and the current stream.
 There is no CPU fallback: without the built library or a GPU every call raises.
 """
 import ctypes
+import sys
 import os
 from typing import Optional
 
@@ -499,11 +500,20 @@ class Batch:
         self.solve_async()
         return self.results()
 
-    def __del__(self):
+    def close(self):
+        """Release the batch (its recorded hipGraph included) now."""
         h = getattr(self, "_h", None)
         if h is not None and _LIB is not None:
             _LIB.fj_batch_destroy(h)
             self._h = None
+
+    def __del__(self):
+        # fj_batch_destroy calls into the HIP runtime (it frees the recorded
+        # graph); at interpreter shutdown that runtime may already be gone, so
+        # the handle is left to the process's end there
+        if sys.is_finalizing():
+            return
+        self.close()
 
 
 # ------------------------------------------------------------ learned warm start

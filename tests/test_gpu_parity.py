@@ -550,3 +550,21 @@ def test_bound_skipping_is_bit_exact(directed, weighted, precision, gather_bits)
         # arcs gathered plus arcs of skipped rows cover every sweep
         assert st1["edge_visits"] + st1["skipped_arcs"] == st1["rounds"] * g.nnz
         assert 0 <= st1["mirror_edge_visits"] <= st1["mirror_rounds"] * g.nnz
+
+
+def test_refinement_reseeds_from_the_fp64_residual():
+    """FP32 push rounds (scatter form) at eps = 1e-7: the threshold
+    eps' (s + c) lies below the FP32 rounding of the residual itself, so the
+    rounds go quiet on an FP32 residual whose FP64 recomputation fails the
+    certificate of Lemma 7.  The solve then re-seeds r from the FP64 residual
+    and resumes until the certificate holds; the result meets Lemma 7's
+    bound against the exact z."""
+    fj = fjmod()
+    g = synth.chung_lu(50000, 400000, 2.3, 961)
+    s = synth.opinions(g.n, "uniform", 962)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV)
+    z, st = fj.solve(G, to_dev(s), eps=1e-7, omega=1.0, precision="fp32", schedule="push", push_scatter=True)
+    print(f"refinement: {st}", flush=True)
+    assert st["refinements"] >= 1 and st["certified"] == 1 and st["max_ratio"] <= 1.0
+    check_solution(g, s, z, zt, 1e-7)

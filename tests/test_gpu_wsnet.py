@@ -59,23 +59,41 @@ def test_forward_matches_reference_large():
     assert np.corrcoef(z, z_ref)[0, 1] >= 0.999
 
 
-def test_gradient_matches_reference():
-    fj, g, s, G = _setup(n=4000, m=24000, seed=911)
-    p = mpnn.init_params(4)
+GRAD_BLOCKS = {"W1": (0, 1024), "b1": (1024, 1088), "W2": (1088, 9280), "b2": (9280, 9344), "u": (9344, 9408),
+               "c0": (9408, 9409)}
+
+
+def _check_gradient(fj, g, s, G, seed, tol):
+    p = mpnn.init_params(seed)
     zt = oracle.exact(g, s)
     loss_ref, grad_ref = mpnn.loss_and_grad(g, s, p, zt)
     loss, grad = fj.wsnet_grad(G, torch.from_numpy(s).to(DEV), torch.from_numpy(zt).to(DEV),
                                torch.from_numpy(p.astype(np.float32)).to(DEV))
     assert abs(float(loss.item()) - loss_ref) <= 2e-2 * loss_ref
     grad = grad.cpu().numpy().astype(np.float64)
-    offs = {"W1": (0, 1024), "b1": (1024, 1088), "W2": (1088, 9280), "b2": (9280, 9344), "u": (9344, 9408),
-            "c0": (9408, 9409)}
-    for name, (a, b) in offs.items():
+    for name, (a, b) in GRAD_BLOCKS.items():
         ref = grad_ref[a:b]
         scale = max(np.max(np.abs(ref)), 1e-12)
-        assert np.max(np.abs(grad[a:b] - ref)) <= 5e-2 * scale, name
+        err = np.max(np.abs(grad[a:b] - ref)) / scale
+        print(f"gradient {name}: max error {err:.2e} of the block's largest entry", flush=True)
+        assert err <= tol, name
         if b - a > 1:
             assert np.corrcoef(grad[a:b], ref)[0, 1] >= 0.99, name
+
+
+def test_gradient_matches_reference():
+    fj, g, s, G = _setup(n=4000, m=24000, seed=911)
+    _check_gradient(fj, g, s, G, 4, 5e-2)
+
+
+def test_gradient_matches_reference_heavy_rows():
+    """Rows of A and of A^T above the light-row arc budget (256): the forward
+    aggregation's heavy path and the backward's transposed heavy path
+    (k_aggT_heavy) both run, against the FP64 reference."""
+    fj, g, s, G = _setup(n=60000, m=600000, seed=941)
+    trp, _, _ = oracle.transpose(g)
+    assert np.diff(g.row_ptr).max() > 256 and np.diff(trp).max() > 256
+    _check_gradient(fj, g, s, G, 6, 5e-2)
 
 
 def test_training_reduces_loss_and_start_is_certified():

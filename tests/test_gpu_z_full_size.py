@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,6 +45,17 @@ def _check(g, s, z, zt, eps, c=1e-5, sigma=1e-5):
     assert oracle.certificate(g, s, z, eps, sigma=sigma, c=c) <= 1.0 + 1e-9
 
 
+MEASURE_TOL = 1e-4  # the stated tolerance of the FP32 path on P, D, I, C
+
+
+def _check_measures(m, mt, tol=MEASURE_TOL, what=""):
+    """Table 1 measures of the GPU's z against those of the exact z."""
+    errs = {k: abs(m[k] - mt[k]) / abs(mt[k]) for k in "PDIC"}
+    print(f"measure errors {what}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    for k in "PDIC":
+        assert errs[k] <= tol, (what, k, m[k], mt[k], errs[k])
+
+
 def test_cl10m_as_benchmarked():
     """10M nodes, ~200M stored arcs, omega 1.6, FP32 sweeps with the
     fixed-point copy, merged tail and bound skipping: the benchmark's step."""
@@ -71,11 +83,13 @@ def test_cl10m_as_benchmarked():
     mo = oracle.metrics(g, s, zc)
     for k in "PDIC":
         assert abs(m[k] - mo[k]) <= 1e-10 * abs(mo[k]), (k, m[k], mo[k])
-    # the a-posteriori bounds hold the exact measures
+    # the a-posteriori bounds hold the exact measures, and the measures meet
+    # the FP32 path's tolerance against those of the exact z
     mb, b, _ = fj.metrics_bounds(G, sd, z)
     mt = oracle.metrics(g, s, zt)
     for k in "PDIC":
         assert abs(mb[k] - mt[k]) <= b[k] + 1e-12 * abs(mt[k]), k
+    _check_measures(m, mt, what="cl10m")
     del G, z, z2
     torch.cuda.empty_cache()
 
@@ -89,6 +103,7 @@ def test_cl1m_directed_as_benchmarked(omega):
     wl = bench.WORKLOADS["cl1m_directed"]
     g, s = bench.make_input(wl)
     zt, _ = oracle.gs(g, s, TOL)
+    mt = oracle.metrics(g, s, zt)
     G = fj.Graph.from_host(g, DEV, colour=True)
     sd = torch.from_numpy(s).to(DEV)
     schedules = ("sor", "push") if omega == 1.0 else ("sor",)
@@ -101,6 +116,7 @@ def test_cl1m_directed_as_benchmarked(omega):
         mo = oracle.metrics(g, s, zc)
         for k in "PDIC":
             assert abs(m[k] - mo[k]) <= 1e-10 * abs(mo[k]), (sched, k)
+        _check_measures(m, mt, what=f"cl1m_directed {sched} omega={omega}")
     del G
     torch.cuda.empty_cache()
 
@@ -115,9 +131,11 @@ def test_heldout_5m_cold_and_network_start():
     zt, _ = oracle.gs(g, s, TOL)
     G = fj.Graph.from_host(g, DEV, colour=True)
     sd = torch.from_numpy(s).to(DEV)
+    mt = oracle.metrics(g, s, zt)
     z, st = fj.solve(G, sd, eps=1e-4, omega=1.1, schedule="sor")
     assert st["certified"] == 1
     _check(g, s, z.cpu().numpy(), zt, 1e-4)
+    _check_measures(fj.metrics(G, sd, z), mt, what="held-out cold")
     params = warmstart.load_params(DEV)
     assert params is not None, "stored network weights are missing"
     z0 = fj.wsnet_forward(G, sd, params)
@@ -126,6 +144,7 @@ def test_heldout_5m_cold_and_network_start():
     zw, stw = fj.solve(G, sd, eps=1e-4, omega=1.1, schedule="sor", z0=z0)
     assert stw["certified"] == 1 and stw["rounds"] < st["rounds"]
     _check(g, s, zw.cpu().numpy(), zt, 1e-4)
+    _check_measures(fj.metrics(G, sd, zw), mt, what="held-out from the network")
     del G
     torch.cuda.empty_cache()
 
@@ -159,9 +178,52 @@ def test_batch_as_benchmarked():
         mo = oracle.metrics(big, S[:, q], Z[:, q])
         for k in "PDIC":
             assert abs(mets[0][q][k] - mo[k]) <= 1e-10 * abs(mo[k]), (q, k)
+        _check_measures(mets[0][q], oracle.metrics(big, S[:, q], zt), what=f"batch vector {q}")
     for i in range(0, 256, 15):
         g = smalls[i]
         zt = oracle.exact(g, ss[i], TOL)
         _check(g, ss[i], B.output(i + 1).cpu().numpy(), zt, 1e-4)
+        _check_measures(mets[i + 1][0], oracle.metrics(g, ss[i], zt), what=f"batch graph {i}")
     del B
     torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def cl10m_graph():
+    import bench
+    import paper_2507_14864_amd as fj
+    wl = bench.WORKLOADS["cl10m"]
+    g, _ = bench.make_input(wl)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    yield wl, g, G
+    del G
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("law", ["uniform", "exp", "pareto"])
+def test_cl10m_paper_opinion_laws(cl10m_graph, law):
+    """The three opinion laws of Sec. 6 (U[0,1]; 1 + Exp(1) and Pareto with
+    alpha = 2.5, each divided by its maximum) on the full 10M-node graph, in
+    the benchmark's configuration: z against PCG's exact solution under
+    Lemma 7's bound, the certificate recomputed by the oracle, and the
+    measures against those of the exact z.  Pareto puts most opinions near
+    2e-5, a few times the shift c, so its thresholds eps' (s + c) are the
+    smallest."""
+    import paper_2507_14864_amd as fj
+    wl, g, G = cl10m_graph
+    s = synth.opinions(g.n, law, wl["seed"])
+    print(f"cl10m {law}: s in [{s.min():.3g}, {s.max():.3g}], median {np.median(s):.3g}", flush=True)
+    zt, _ = oracle.cg(g, s, TOL)
+    sd = torch.from_numpy(s).to(DEV)
+    z, st = fj.solve(G, sd, eps=wl["eps"], omega=wl["omega"], precision="fp32", schedule="sor")
+    print(f"cl10m {law}: sweeps {st['rounds']} max ratio {st['max_ratio']:.4f} refinements {st['refinements']}",
+          flush=True)
+    assert st["certified"] == 1
+    zc = z.cpu().numpy()
+    _check(g, s, zc, zt, wl["eps"])
+    m = fj.metrics(G, sd, z)
+    mt = oracle.metrics(g, s, zt)
+    mb, b, _ = fj.metrics_bounds(G, sd, z)
+    for k in "PDIC":
+        assert abs(m[k] - mt[k]) <= b[k] + 1e-12 * abs(mt[k]), (law, k)
+    _check_measures(m, mt, what=f"cl10m {law}")
