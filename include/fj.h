@@ -13,9 +13,10 @@
  *  - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
  *    tensor's data_ptr) unless the comment says [host].
  *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
- *  - The library never allocates device memory.  Callers query the workspace
- *    size of each call and pass a buffer of at least that many bytes, aligned
- *    to 256 bytes.  A graph workspace must stay alive and untouched while the
+ *  - The library never allocates device memory at run time (its only device
+ *    memory of its own is the static 8 MiB array of fj_metrics_noalloc, part
+ *    of its code object).  Callers query the workspace size of each call and
+ *    pass a buffer of at least that many bytes, aligned to 256 bytes.  A graph workspace must stay alive and untouched while the
  *    graph handle exists.  A solve/metrics workspace may be reused between
  *    calls but not by two concurrent calls.
  *  - Graph: CSR of the adjacency matrix A.  Row i lists the nodes j with
@@ -242,6 +243,27 @@ size_t fj_metrics_workspace_bytes(const fj_graph* g);
  * s, z: device [n].  out: [host].  Synchronizes `stream`. */
 fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* fj_metrics without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and the same fixed-order reductions as
+ * fj_metrics (results bitwise equal), with their partial sums in a static
+ * device array of fj_metrics_noalloc_max_bytes() = 8 MiB that the library
+ * holds on every GPU it runs on until the process ends.  A graph needs
+ * fj_metrics_noalloc_bytes(g) of it: 24 bytes per 4 wave tiles (a tile is at
+ * most 64 rows or 256 arcs of a row) plus 72 bytes per 2048 nodes, about
+ * 0.13 bytes per node plus 0.025 per arc (a 10M-node graph of 200M arcs
+ * needs about 6 MB); a larger graph gets FJ_ERR_WORKSPACE_TOO_SMALL.  Calls nothing that allocates.  The array of the
+ * current device is used, and `stream` (NULL: the null stream) must belong to
+ * that device (else FJ_ERR_INVALID_ARGUMENT).  Every call on one GPU shares
+ * its array: calls that overlap on one GPU (from several host threads or
+ * streams) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero.  s, z: device [n]; out: [host].  Synchronizes
+ * `stream`. */
+size_t fj_metrics_noalloc_max_bytes(void);
+size_t fj_metrics_noalloc_bytes(const fj_graph* g);
+fj_status fj_metrics_noalloc(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out,
+                             void* stream);
 
 /* A-posteriori bounds on the error of the measures of z against those of the
  * exact z* = (I+L)^{-1} s.  With the residual level

@@ -16,6 +16,7 @@
 // to zero, so the mean's move drops out of the first-order term and can only
 // lower the second-order one.  The sums are formed once, before kappa is known.
 #include <cmath>
+#include <mutex>
 
 #include "fj_device.h"
 #include "fj_internal.h"
@@ -315,6 +316,42 @@ fj_status metrics_passes(const fj_graph* g, const double* s, const double* z, do
     return FJ_OK;
 }
 
+// ------------------------------------------------- allocation-free measures
+// For callers that cannot allocate (code under graph capture, serving loops):
+// the partial sums of the measures live in this file-scope device array, one
+// copy per GPU, instead of a caller workspace.  Host code must never pass the
+// array's name to a kernel or copy: it is a host-side stand-in, not a device
+// address.  The device address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once.
+fj_status current_scratch(int dev, void** out) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        FJ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("fj_metrics_noalloc: hipGetSymbolAddress returned a null address");
+            return FJ_ERR_HIP;
+        }
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return FJ_OK;
+}
+
+size_t metrics_scratch_bytes(const fj_graph* g) {
+    Carver cv(nullptr);
+    carve_metrics(cv, g);
+    return cv.bytes();
+}
+
 }  // namespace
 }  // namespace fj
 
@@ -434,5 +471,55 @@ extern "C" fj_status fj_stress(const fj_graph* g, const double* s, const double*
         FJ_HIP(hipStreamSynchronize(st));
     }
     *total = h;
+    return FJ_OK;
+}
+
+extern "C" size_t fj_metrics_noalloc_max_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" size_t fj_metrics_noalloc_bytes(const fj_graph* g) { return g ? metrics_scratch_bytes(g) : 0; }
+
+extern "C" fj_status fj_metrics_noalloc(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out,
+                                        void* stream) {
+    if (!g || !out || ((!s || !z) && g->n > 0)) {
+        set_error("fj_metrics_noalloc: null argument");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const size_t need = metrics_scratch_bytes(g);
+    if (need > kStaticScratchBytes) {
+        set_error("fj_metrics_noalloc: the graph's partial sums need " + std::to_string(need) +
+                  " bytes, more than the " + std::to_string(kStaticScratchBytes) +
+                  "-byte static scratch; use fj_metrics with a workspace");
+        return FJ_ERR_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    FJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        set_error("fj_metrics_noalloc: device ordinal out of range");
+        return FJ_ERR_UNSUPPORTED;
+    }
+    if (st) {
+        int sdev = -1;
+        FJ_HIP(hipStreamGetDevice(st, &sdev));
+        if (sdev != dev) {
+            set_error("fj_metrics_noalloc: the stream belongs to another device than the current one");
+            return FJ_ERR_INVALID_ARGUMENT;
+        }
+    }
+    void* base = nullptr;
+    {
+        const fj_status rc = current_scratch(dev, &base);
+        if (rc != FJ_OK) return rc;
+    }
+    Carver cv(base);
+    const MetricsLayout L = carve_metrics(cv, g);
+    double h[kOutSlots];
+    const fj_status rc = metrics_passes(g, s, z, 0.0, L, st, h);
+    if (rc != FJ_OK) return rc;
+    out->P = h[kOutP];
+    out->D = h[kOutD];
+    out->I = h[kOutI];
+    out->C = h[kOutC];
+    out->mean = h[kOutMean];
     return FJ_OK;
 }

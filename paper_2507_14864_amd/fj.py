@@ -111,6 +111,12 @@ def lib():
         L.fj_metrics_workspace_bytes.restype = sz
         L.fj_metrics.argtypes = [vp, vp, vp, P(MetricsOut), vp, sz, vp]
         L.fj_metrics.restype = i32
+        L.fj_metrics_noalloc_max_bytes.argtypes = []
+        L.fj_metrics_noalloc_max_bytes.restype = sz
+        L.fj_metrics_noalloc_bytes.argtypes = [vp]
+        L.fj_metrics_noalloc_bytes.restype = sz
+        L.fj_metrics_noalloc.argtypes = [vp, vp, vp, P(MetricsOut), vp]
+        L.fj_metrics_noalloc.restype = i32
         L.fj_metrics_bounds.argtypes = [vp, vp, vp, ctypes.c_double, P(MetricsOut), P(MetricsOut),
                                         P(ctypes.c_double), vp, sz, vp]
         L.fj_metrics_bounds.restype = i32
@@ -285,6 +291,23 @@ def metrics(graph: Graph, s: torch.Tensor, z: torch.Tensor) -> dict:
     _check(lib().fj_metrics(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
                             ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def metrics_noalloc(graph: Graph, s: torch.Tensor, z: torch.Tensor) -> dict:
+    """fj_metrics_noalloc: the measures with the partial sums in the library's
+    static device array (no workspace; graphs up to its size)."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(z, torch.float64, n, "z")
+    out = MetricsOut()
+    _check(lib().fj_metrics_noalloc(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                    ctypes.byref(out), _stream()))
+    return {k: getattr(out, k) for k, _ in out._fields_}
+
+
+def metrics_noalloc_bytes(graph: Graph) -> tuple:
+    """(bytes of the static array this graph needs, the array's size)."""
+    return int(lib().fj_metrics_noalloc_bytes(graph.handle)), int(lib().fj_metrics_noalloc_max_bytes())
 
 
 def metrics_bounds(graph: Graph, s: torch.Tensor, z: torch.Tensor, c: float = 1e-5) -> tuple:

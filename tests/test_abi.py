@@ -77,3 +77,19 @@ def test_optimal_omega_is_host_arithmetic(lib):
     for mu in (0.0, 0.25, 2.0 / 3.0, 0.95, 0.999):
         assert abs(f(mu) - oracle.optimal_omega(mu)) <= 1e-15
     assert f(-1.0) == 1.0 and f(1.0) == 2.0 and f(float("nan")) == 1.0
+
+
+def test_noalloc_metrics_host_checks(lib):
+    """The allocation-free measures state their static size and reject a null
+    graph before any device call."""
+    from paper_2507_14864_amd.fj import MetricsOut
+    lib.fj_metrics_noalloc_max_bytes.restype = ctypes.c_size_t
+    assert lib.fj_metrics_noalloc_max_bytes() == 8 << 20
+    lib.fj_metrics_noalloc_bytes.argtypes = [ctypes.c_void_p]
+    lib.fj_metrics_noalloc_bytes.restype = ctypes.c_size_t
+    assert lib.fj_metrics_noalloc_bytes(None) == 0
+    f = lib.fj_metrics_noalloc
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(MetricsOut), ctypes.c_void_p]
+    f.restype = ctypes.c_int32
+    out = MetricsOut()
+    assert f(None, None, None, ctypes.byref(out), None) == 1
