@@ -258,6 +258,7 @@ def batch_eval(dev, steps, warmup):
            "graph_nodes": info["graph_nodes"], "certified_items": cert, "items": len(stats),
            "max_sweeps_used": max(s["rounds"] for s in stats), "ingest_s": round(ingest, 2),
            "tune_s": round(tune_s, 2), "steps": steps}
+    B.close()  # release the recorded hipGraph while the runtime is up
     del B
     torch.cuda.empty_cache()
     return out
