@@ -409,6 +409,18 @@ def main():
                         algorithmic_bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
                         launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))
         log(f"profiled step: {stp}")
+        if args.schedule == "sor":
+            # the ceiling of the sweep's memory pattern: the same index stream
+            # gathering 4-byte (fixed-point copy) or 8-byte (FP64) values and
+            # nothing else; the sweep's arc rate against it
+            probe4 = fj.gather_probe(G, 4, 20)
+            probe8 = fj.gather_probe(G, 8, 20)
+            sweep_rate = stp["edge_visits"] / (stp["kernel_ms"] * 1e-3)
+            roofline["gather_ceiling"] = {
+                "kernel": "k_gather_probe", "arcs_per_s_4B": round(probe4), "arcs_per_s_8B": round(probe8),
+                "sweep_arcs_per_s": round(sweep_rate), "frac": round(sweep_rate / probe4, 4)}
+            roofline["gather_frac"] = roofline["gather_ceiling"]["frac"]
+            log(f"gather ceiling: {roofline['gather_ceiling']}")
 
     if args.calib_copy:
         # one elementwise kernel that reads 1 GiB and writes 1 GiB (4x the 256 MB Infinity Cache)

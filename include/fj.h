@@ -304,6 +304,22 @@ fj_status fj_stress(const fj_graph* g, const double* s, const double* z, double*
 fj_status fj_certify(const fj_graph* g, const double* s, const double* z, double eps, double c,
                      double sigma, double* out_max_ratio, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------- diagnostics */
+
+/* The random-gather ceiling of the sweep's access pattern on this graph: one
+ * launch over every arc of the colour-major CSR (the original CSR when the
+ * graph has no colouring) that streams the column index and gathers the value
+ * at it, value_bytes = 4 (the fixed-point copy the early sweeps read) or 8
+ * (the FP64 estimate), four loads in flight per lane, and nothing else.  A
+ * sweep of Eq. (sor1) in pull form does this plus its per-row arithmetic, so
+ * its arc rate divided by this one is the fraction of the gather ceiling it
+ * reaches.  One untimed launch, then `reps` (1..1000) launches timed with HIP
+ * events on `stream`.  arcs_per_s: [host] out, arcs per second.
+ * Synchronizes `stream`. */
+size_t fj_gather_probe_workspace_bytes(const fj_graph* g);
+fj_status fj_gather_probe(const fj_graph* g, int32_t value_bytes, int32_t reps, double* arcs_per_s, void* ws,
+                          size_t ws_bytes, void* stream);
+
 /* ----------------------------------------------------------- batched solve
  * Many opinion vectors and many graphs solved by one enqueued sequence that
  * never synchronizes the host (capture-safe), so a whole batch can run as one

@@ -117,6 +117,10 @@ def lib():
         L.fj_metrics_noalloc_bytes.restype = sz
         L.fj_metrics_noalloc.argtypes = [vp, vp, vp, P(MetricsOut), vp]
         L.fj_metrics_noalloc.restype = i32
+        L.fj_gather_probe_workspace_bytes.argtypes = [vp]
+        L.fj_gather_probe_workspace_bytes.restype = sz
+        L.fj_gather_probe.argtypes = [vp, i32, i32, P(dbl), vp, sz, vp]
+        L.fj_gather_probe.restype = i32
         L.fj_metrics_bounds.argtypes = [vp, vp, vp, ctypes.c_double, P(MetricsOut), P(MetricsOut),
                                         P(ctypes.c_double), vp, sz, vp]
         L.fj_metrics_bounds.restype = i32
@@ -323,6 +327,15 @@ def metrics_bounds(graph: Graph, s: torch.Tensor, z: torch.Tensor, c: float = 1e
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return ({k: getattr(out, k) for k, _ in out._fields_}, {k: getattr(bound, k) for k, _ in bound._fields_},
             tau.value)
+
+
+def gather_probe(graph: Graph, value_bytes: int = 4, reps: int = 10) -> float:
+    """Arcs per second of the sweep's gather pattern alone (fj_gather_probe)."""
+    ws = _workspace(lib().fj_gather_probe_workspace_bytes(graph.handle), graph.device)
+    rate = ctypes.c_double()
+    _check(lib().fj_gather_probe(graph.handle, int(value_bytes), int(reps), ctypes.byref(rate),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return rate.value
 
 
 def optimal_omega(mu: float) -> float:

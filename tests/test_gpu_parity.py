@@ -568,3 +568,18 @@ def test_refinement_reseeds_from_the_fp64_residual():
     print(f"refinement: {st}", flush=True)
     assert st["refinements"] >= 1 and st["certified"] == 1 and st["max_ratio"] <= 1.0
     check_solution(g, s, z, zt, 1e-7)
+
+
+def test_gather_probe_reports_a_rate():
+    """fj_gather_probe times the sweep's index stream alone; bad sizes are rejected."""
+    fj = fjmod()
+    g = synth.chung_lu(50_000, 400_000, 2.3, 7)
+    for colour in (True, False):
+        G = fj.Graph.from_host(g, DEV, colour=colour)
+        r4 = fj.gather_probe(G, 4, 3)
+        r8 = fj.gather_probe(G, 8, 3)
+        assert r4 > 0 and r8 > 0
+        with pytest.raises(fj.FJError):
+            fj.gather_probe(G, 2, 1)
+        with pytest.raises(fj.FJError):
+            fj.gather_probe(G, 4, 0)
