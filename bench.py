@@ -255,7 +255,8 @@ def batch_eval(dev, steps, warmup):
            "s_per_batch": round(dt, 5), "vector_solves_per_s": round(320 / dt, 1), "eps": 1e-4,
            "omega_multi": info["omega_multi"], "omega_undirected": info["omega_undirected"],
            "omega_directed": info["omega_directed"], "sweep_budget": info["sweep_budget"],
-           "graph_nodes": info["graph_nodes"], "certified_items": cert, "items": len(stats),
+           "graph_nodes": info["graph_nodes"], "union_chunks_in_flight": info["union_chunks_in_flight"],
+           "multi_arcs_in_flight": info["multi_arcs_in_flight"], "certified_items": cert, "items": len(stats),
            "max_sweeps_used": max(s["rounds"] for s in stats), "ingest_s": round(ingest, 2),
            "tune_s": round(tune_s, 2), "steps": steps}
     B.close()  # release the recorded hipGraph while the runtime is up

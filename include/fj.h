@@ -353,12 +353,48 @@ fj_status fj_batch_destroy(fj_batch* b);
  * before fj_solve_batched; z is valid after it. [host] out. */
 fj_status fj_batch_io(const fj_batch* b, int32_t item, double** s, double** z);
 
-/* Autotuner (synchronizes): with the inputs currently in place, times the
- * batched solve for each omega in omegas[0..n_omegas) (host-driven, with
- * convergence feedback), keeps the fastest, sets the sweep budget to the
- * sweeps it needed plus a margin, and records the launch sequence into a
- * hipGraph that fj_solve_batched then replays.  [host] omegas. */
+/* Autotuner (synchronizes): with the inputs currently in place, solves the
+ * batch once for each omega in omegas[0..n_omegas) and keeps, per item group
+ * (undirected single-vector items, directed single-vector items, each
+ * multi-vector item), the one that needed the fewest sweeps; then times the
+ * launch parameters at those omegas, one at a time: 64-arc chunks in flight
+ * per light tile of the single-vector union (2, 4 or 8) and arcs in flight
+ * per lane of the multi-vector rows (2, 4 or 8), which leave the sums and the
+ * result unchanged.  The choice is kept for the life of the process under the
+ * batch's shape (eps, c, sigma; per group the item count and the base-2
+ * magnitude of nodes and arcs; per multi-vector item k, nodes, arcs and
+ * direction): a later batch of the same shape takes it without timing (one
+ * solve still measures the sweeps its inputs need).  The sweep budget is the
+ * sweeps needed plus max(4, 25%), and the launch sequence is recorded into a
+ * hipGraph that fj_solve_batched replays.  [host] omegas.
+ * FJ_ERR_NOT_CONVERGED if an item needs more than 512 sweeps for every
+ * candidate. */
 fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_omegas, void* stream);
+
+/* Forget every shape kept by fj_batch_tune in this process. */
+void fj_batch_tune_cache_clear(void);
+
+/* Caller-owned inputs and outputs: s[i] and z[i] ([host] arrays of num_items
+ * device pointers) hold item i's opinions and receive its equilibrium, n_i x k_i
+ * doubles node-major, in place of the workspace buffers of fj_batch_io.  Every
+ * later solve copies s[i] in at its start and writes z[i] at its end, inside
+ * the same enqueued sequence (a recorded hipGraph is recorded again with the
+ * copies).  The buffers must stay valid while bound.  s = z = NULL unbinds.
+ * Synchronizes `stream`. */
+fj_status fj_batch_bind(fj_batch* b, const double* const* s, double* const* z, void* stream);
+
+/* After fj_solve_batched (synchronizes): counts the items whose FP64
+ * certificate failed, normally because their inputs need more sweeps than
+ * the budget recorded by fj_batch_tune.  With extra_sweeps > 0 those items
+ * sweep on from their current estimates (Lemma 4: any estimate is a valid
+ * start) for up to extra_sweeps more sweeps, the results of every item are
+ * recomputed (and copied to the bound outputs), and they are counted again.
+ * uncertified: [host] out.  stats_dev, metrics_dev: device, as for
+ * fj_solve_batched, or NULL; they receive the items' stats and measures after
+ * the check (and its continuation).  FJ_OK when every item is certified,
+ * else FJ_ERR_NOT_CONVERGED. */
+fj_status fj_batch_check(fj_batch* b, int32_t extra_sweeps, int32_t* uncertified, fj_solve_stats* stats_dev,
+                         fj_metrics_out* metrics_dev, void* stream);
 
 typedef struct {
     double omega;         /* relaxation factor of the last item group */
@@ -368,7 +404,11 @@ typedef struct {
     int32_t sweep_budget; /* sweeps recorded per solve */
     int32_t graph_nodes;  /* kernel launches in the recorded hipGraph (0 if none) */
     int32_t num_colours;  /* most colour classes over the items */
-    double tune_ms[16];   /* measured time per candidate omega */
+    double tune_ms[16];   /* measured time per candidate omega (0 when the shape was known) */
+    int32_t union_chunks_in_flight; /* launch parameter chosen for the single-vector union */
+    int32_t multi_arcs_in_flight;   /* launch parameter chosen for the multi-vector items */
+    int32_t cache_hit;    /* 1: the last fj_batch_tune took a shape kept from an earlier batch */
+    int32_t bound;        /* 1: inputs and outputs are caller-bound (fj_batch_bind) */
 } fj_batch_info;
 fj_status fj_batch_get_info(const fj_batch* b, fj_batch_info* out);
 

@@ -413,7 +413,14 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("omega_undirected", ctypes.c_double),
                 ("omega_directed", ctypes.c_double), ("omega_multi", ctypes.c_double),
                 ("sweep_budget", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
-                ("num_colours", ctypes.c_int32), ("tune_ms", ctypes.c_double * 16)]
+                ("num_colours", ctypes.c_int32), ("tune_ms", ctypes.c_double * 16),
+                ("union_chunks_in_flight", ctypes.c_int32), ("multi_arcs_in_flight", ctypes.c_int32),
+                ("cache_hit", ctypes.c_int32), ("bound", ctypes.c_int32)]
+
+
+def batch_tune_cache_clear():
+    """Forget the batch shapes fj_batch_tune has kept in this process."""
+    _batch_lib().fj_batch_tune_cache_clear()
 
 
 def _batch_lib():
@@ -436,6 +443,12 @@ def _batch_lib():
         L.fj_batch_set_omegas.restype = i32
         L.fj_solve_batched.argtypes = [vp, vp, vp, vp]
         L.fj_solve_batched.restype = i32
+        L.fj_batch_tune_cache_clear.argtypes = []
+        L.fj_batch_tune_cache_clear.restype = None
+        L.fj_batch_bind.argtypes = [vp, vp, vp, vp]
+        L.fj_batch_bind.restype = i32
+        L.fj_batch_check.argtypes = [vp, i32, P(i32), vp, vp, vp]
+        L.fj_batch_check.restype = i32
         L._batch_ready = True
     return L
 
@@ -448,6 +461,7 @@ class Batch:
     def __init__(self, graphs, ks, eps=1e-4, omega=1.5, c=1e-5, sigma=1e-5):
         L = _batch_lib()
         self._keep = []
+        self._bound = None
         self.ns, self.ks = [], [int(k) for k in ks]
         descs = (BatchItemDesc * len(graphs))()
         for i, (rp, col, w, directed) in enumerate(graphs):
@@ -535,6 +549,38 @@ class Batch:
     def solve(self):
         self.solve_async()
         return self.results()
+
+    def bind(self, s_list=None, z_list=None):
+        """Caller-owned inputs and outputs (fj_batch_bind): item i reads
+        s_list[i] and writes z_list[i] (contiguous float64 CUDA tensors of
+        n_i * k_i elements, node-major).  No arguments: unbind."""
+        if s_list is None:
+            self._bound = None
+            _check(_batch_lib().fj_batch_bind(self._h, None, None, _stream()))
+            return
+        if len(s_list) != self.num_items or len(z_list) != self.num_items:
+            raise ValueError("need one s and one z tensor per item")
+        for i, (si, zi) in enumerate(zip(s_list, z_list)):
+            cnt = self.ns[i] * self.ks[i]
+            for t, nm in ((si, "s"), (zi, "z")):
+                if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != cnt:
+                    raise ValueError(f"item {i}: {nm} must be a contiguous float64 CUDA tensor of {cnt} elements")
+        sp = (ctypes.c_void_p * self.num_items)(*[t.data_ptr() for t in s_list])
+        zp = (ctypes.c_void_p * self.num_items)(*[t.data_ptr() for t in z_list])
+        self._bound = (list(s_list), list(z_list))  # keep the buffers alive while bound
+        _check(_batch_lib().fj_batch_bind(self._h, sp, zp, _stream()))
+
+    def check(self, extra_sweeps: int = 256) -> int:
+        """fj_batch_check after a solve: items whose certificate failed sweep
+        on for up to extra_sweeps more sweeps; refreshes results().  Returns
+        the number of items still not certified (0 on success)."""
+        cnt = ctypes.c_int32()
+        rc = _batch_lib().fj_batch_check(self._h, int(extra_sweeps), ctypes.byref(cnt),
+                                         ctypes.c_void_p(self._stats.data_ptr()),
+                                         ctypes.c_void_p(self._mets.data_ptr()), _stream())
+        if rc not in (FJ_OK, FJ_ERR_NOT_CONVERGED):
+            _check(rc)
+        return int(cnt.value)
 
     def close(self):
         """Release the batch (its recorded hipGraph included) now."""

@@ -145,3 +145,110 @@ def test_batch_rejects_bad_items():
         fj.Batch([_dev(g), _dev(bad)], [1, 1])
     with pytest.raises((fj.FJError, ValueError)):
         fj.Batch([_dev(g)], [65])
+
+
+def _all_certified_against_oracle(B, single, multi, ss, sm, k):
+    stats, mets = B.results()
+    for i, g in enumerate(single):
+        assert stats[i]["certified"] == 1, (i, stats[i])
+        _check(g, ss[i], B.output(i).cpu().numpy(), oracle.exact(g, ss[i]))
+    assert stats[-1]["certified"] == 1, stats[-1]
+    zm = B.output(len(single)).cpu().numpy()
+    for q in range(k):
+        _check(multi, sm[:, q], zm[:, q], oracle.exact(multi, sm[:, q]))
+    return stats
+
+
+def test_check_continues_items_beyond_the_recorded_budget():
+    """After tuning, a slower relaxation factor leaves every item short of its
+    certificate within the recorded budget; fj_batch_check sweeps them on from
+    their estimates (Lemma 4) to the certificate."""
+    import paper_2507_14864_amd as fj
+    single, multi = _items()
+    k = 3
+    B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+    ss, sm = _fill(B, single, multi, k)
+    info = B.tune([1.2, 1.5])
+    B.set_omegas(0.4, 0.4, 0.4)  # keeps the tuned budget, drops the recording
+    stats, _ = B.solve()
+    short = sum(1 for st in stats if not st["certified"])
+    print(f"budget {info['sweep_budget']}: {short} of {len(stats)} items short of the certificate", flush=True)
+    assert short > 0
+    assert B.check(extra_sweeps=4000) == 0
+    stats = _all_certified_against_oracle(B, single, multi, ss, sm, k)
+    assert max(st["rounds"] for st in stats) > info["sweep_budget"]
+
+
+def test_opinions_swapped_after_tuning_are_certified():
+    """Tuned on one set of opinions, solved on the paper's Pareto law (Sec. 6):
+    every item ends certified, with fj_batch_check finishing any item the
+    recorded budget did not."""
+    import paper_2507_14864_amd as fj
+    single, multi = _items()
+    k = 3
+    B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+    _fill(B, single, multi, k)
+    B.tune([1.2, 1.5])
+    ss = []
+    for i, g in enumerate(single):
+        s = synth.opinions(g.n, "pareto", 950 + i)
+        B.input(i).copy_(torch.from_numpy(s))
+        ss.append(s)
+    sm = np.stack([synth.opinions(multi.n, "pareto", 960 + q) for q in range(k)], axis=1)
+    B.input(len(single)).copy_(torch.from_numpy(np.ascontiguousarray(sm)))
+    stats, _ = B.solve()
+    short = sum(1 for st in stats if not st["certified"])
+    print(f"Pareto opinions: {short} item(s) short after the recorded budget", flush=True)
+    assert B.check(extra_sweeps=1000) == 0
+    _all_certified_against_oracle(B, single, multi, ss, sm, k)
+
+
+def test_bound_caller_buffers_match_workspace_io():
+    import paper_2507_14864_amd as fj
+    single, multi = _items()
+    k = 3
+    B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+    ss, sm = _fill(B, single, multi, k)
+    info = B.tune([1.2, 1.5])
+    B.solve()
+    z_io = [B.output(i).clone() for i in range(len(single) + 1)]
+    s_user = [torch.from_numpy(s).to(DEV) for s in ss] + [torch.from_numpy(np.ascontiguousarray(sm)).to(DEV).view(-1)]
+    z_user = [torch.full_like(t, -1.0) for t in s_user]
+    B.bind(s_user, z_user)
+    info_b = B.info()
+    assert info_b["bound"] == 1 and info_b["graph_nodes"] == info["graph_nodes"] + 2
+    for i in range(len(single) + 1):
+        B.input(i).fill_(0.25)  # the bound inputs are copied over these at the solve's start
+    for rep in range(2):
+        stats, _ = B.solve()
+        assert all(st["certified"] == 1 for st in stats)
+        for i in range(len(single) + 1):
+            assert torch.equal(z_user[i], z_io[i].reshape(-1)), (rep, i)
+    B.bind()
+    assert B.info()["bound"] == 0
+    with pytest.raises(ValueError):
+        B.bind(s_user[:-1], z_user[:-1])
+
+
+def test_tuned_shape_is_reused_by_a_batch_of_the_same_shape():
+    import paper_2507_14864_amd as fj
+    fj.batch_tune_cache_clear()
+    single, multi = _items()
+    k = 3
+    outs = []
+    for trial in range(2):
+        B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+        _fill(B, single, multi, k)
+        info = B.tune([1.2, 1.5])
+        assert info["cache_hit"] == trial, info
+        assert info["union_chunks_in_flight"] in (2, 4, 8) and info["multi_arcs_in_flight"] in (2, 4, 8)
+        stats, _ = B.solve()
+        assert all(st["certified"] == 1 for st in stats)
+        outs.append((info, [B.output(i).cpu().numpy().copy() for i in range(len(single) + 1)]))
+        B.close()
+    (i0, z0), (i1, z1) = outs
+    for key in ("omega_undirected", "omega_directed", "omega_multi", "union_chunks_in_flight",
+                "multi_arcs_in_flight", "sweep_budget"):
+        assert i0[key] == i1[key], key
+    for a, b in zip(z0, z1):
+        assert np.array_equal(a, b)
