@@ -5,30 +5,44 @@ proposes a starting estimate.  By Lemma 4 any starting estimate is valid and
 by Lemma 7 the residual certificate decides the result, so the network never
 changes what is computed, only how long the push runs.  This module is the
 plain definition the GPU kernels are checked against; its gradients are pinned
-by central finite differences (tests/test_oracle_mpnn.py).  Parity with the
-paper: unpinned (the paper has no such network).
+by central finite differences and its forward by a loop form
+(tests/test_oracle_mpnn.py).  Parity with the paper: unpinned (the paper has
+no such network).
 
 Definition (all arrays FP64, n nodes, CSR of A with weights a_ij):
-  d_v   = sum_j a_vj,  din_v = sum_u a_uv
-  X0_v  = [s_v, nbr_v(s), log1p d_v, log1p din_v, 1/(1+d_v), mean(s), 1, 0]
-          with nbr_v(x) = sum_j a_vj x_j / d_v (0 when d_v = 0)
-  A1 = [X0 | nbr(X0)]           (n x 16)
-  H1 = relu(A1 W1 + b1)         (n x 64)
-  A2 = [H1 | nbr(H1)]           (n x 128)
-  H2 = relu(A2 W2 + b2)         (n x 64)
+  d_v   = sum_j a_vj
+  nbr_v(x) = sum_j a_vj x_j / d_v   (0 when d_v = 0)
+  ns    = nbr(s)
+  z1_v  = (s_v + d_v ns_v) / (1 + d_v)      one step of Eq. (1) from s
+  X0_v  = [s_v, ns_v, z1_v, log1p d_v, 1/(1+d_v), mean(s), 1, 0]      (n x 8)
+  H1 = relu(X0 W1 + b1)                      (n x 64)   layer 1
+  P  = H1 Wp                                 (n x 16)   message of layer 2
+  M  = nbr(P)                                (n x 16)
+  H2 = relu([H1 | M] W2 + b2)                (n x 64)   layer 2
   o  = H2 u + c0
-  z0 = min(s) + (max(s) - min(s)) sigmoid(o)       (inside [min s, max s],
-       where the equilibrium lies: (I+L)^{-1} is row-stochastic, Sec. 3.3)
+  z0 = min(s) + (max(s) - min(s)) sigmoid(o)   (inside [min s, max s], where
+       the equilibrium lies: (I+L)^{-1} is row-stochastic, Sec. 3.3)
   loss = mean_v (z0_v - z_v)^2
-Parameters are one flat FP32/FP64 vector: W1 (16x64 row-major), b1 (64),
-W2 (128x64), b2 (64), u (64), c0 (1).
+Layer 1's message is the opinion itself (ns), layer 2's a learned 16-wide
+projection of the hidden state.  Parameters are one flat FP32/FP64 vector:
+W1 (8x64 row-major), b1 (64), Wp (64x16), W2 (80x64), b2 (64), u (64), c0 (1).
 """
 import numpy as np
 
-F_IN, HID = 8, 64
-SIZES = [("W1", (2 * F_IN, HID)), ("b1", (HID,)), ("W2", (2 * HID, HID)), ("b2", (HID,)),
+F_IN, HID, MSG = 8, 64, 16
+SIZES = [("W1", (F_IN, HID)), ("b1", (HID,)), ("Wp", (HID, MSG)), ("W2", (HID + MSG, HID)), ("b2", (HID,)),
          ("u", (HID,)), ("c0", (1,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SIZES)
+
+
+def offsets():
+    """name -> (first, one past last) in the flat parameter vector."""
+    out, off = {}, 0
+    for name, shape in SIZES:
+        k = int(np.prod(shape))
+        out[name] = (off, off + k)
+        off += k
+    return out
 
 
 def unpack(p):
@@ -46,36 +60,37 @@ def pack(d):
 
 def init_params(seed=0):
     rng = np.random.default_rng(seed)
-    d = {"W1": rng.normal(0, np.sqrt(2.0 / (2 * F_IN)), (2 * F_IN, HID)), "b1": np.zeros(HID),
-         "W2": rng.normal(0, np.sqrt(2.0 / (2 * HID)), (2 * HID, HID)), "b2": np.zeros(HID),
+    d = {"W1": rng.normal(0, np.sqrt(2.0 / F_IN), (F_IN, HID)), "b1": np.zeros(HID),
+         "Wp": rng.normal(0, np.sqrt(1.0 / HID), (HID, MSG)),
+         "W2": rng.normal(0, np.sqrt(2.0 / (HID + MSG)), (HID + MSG, HID)), "b2": np.zeros(HID),
          "u": rng.normal(0, np.sqrt(1.0 / HID), HID), "c0": np.zeros(1)}
     return pack(d)
 
 
-def _dense_a(g):
+def _adjacency(g):
     import scipy.sparse as sp
     w = np.ones(g.nnz) if g.w is None else g.w.astype(np.float64)
     return sp.csr_matrix((w, g.col, g.row_ptr), shape=(g.n, g.n))
 
 
 def neighbour_mean_matrix(g):
-    """Sparse operator P with (P x)_v = sum_j a_vj x_j / d_v (0 if d_v = 0)."""
+    """Sparse operator N with (N x)_v = sum_j a_vj x_j / d_v (0 if d_v = 0), and d."""
     import scipy.sparse as sp
-    A = _dense_a(g)
+    A = _adjacency(g)
     d = np.asarray(A.sum(axis=1)).ravel()
     inv = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
-    return sp.diags(inv) @ A, A, d
+    return sp.diags(inv) @ A, d
 
 
 def features(g, s):
-    P, A, d = neighbour_mean_matrix(g)
-    din = np.asarray(A.sum(axis=0)).ravel()
+    N, d = neighbour_mean_matrix(g)
     s = np.asarray(s, dtype=np.float64)
+    ns = N @ s
     X = np.zeros((g.n, F_IN))
     X[:, 0] = s
-    X[:, 1] = P @ s
-    X[:, 2] = np.log1p(d)
-    X[:, 3] = np.log1p(din)
+    X[:, 1] = ns
+    X[:, 2] = (s + d * ns) / (1.0 + d)
+    X[:, 3] = np.log1p(d)
     X[:, 4] = 1.0 / (1.0 + d)
     X[:, 5] = s.mean()
     X[:, 6] = 1.0
@@ -84,23 +99,25 @@ def features(g, s):
 
 def forward(g, s, p):
     prm = unpack(p)
-    P, _, _ = neighbour_mean_matrix(g)
+    N, _ = neighbour_mean_matrix(g)
     X0 = features(g, s)
-    A1 = np.hstack([X0, P @ X0])
-    Y1 = A1 @ prm["W1"] + prm["b1"]
+    Y1 = X0 @ prm["W1"] + prm["b1"]
     H1 = np.maximum(Y1, 0.0)
-    A2 = np.hstack([H1, P @ H1])
+    P = H1 @ prm["Wp"]
+    M = N @ P
+    A2 = np.hstack([H1, M])
     Y2 = A2 @ prm["W2"] + prm["b2"]
     H2 = np.maximum(Y2, 0.0)
     o = H2 @ prm["u"] + prm["c0"][0]
     lo, hi = float(np.min(s)), float(np.max(s))
     sg = 1.0 / (1.0 + np.exp(-o))
     z0 = lo + (hi - lo) * sg
-    return dict(P=P, X0=X0, A1=A1, Y1=Y1, H1=H1, A2=A2, Y2=Y2, H2=H2, o=o, sg=sg, z0=z0, lo=lo, hi=hi)
+    return dict(N=N, X0=X0, Y1=Y1, H1=H1, P=P, M=M, A2=A2, Y2=Y2, H2=H2, o=o, sg=sg, z0=z0, lo=lo, hi=hi)
 
 
 def loss_and_grad(g, s, p, z_target):
-    """Mean squared error of z0 against z_target and its gradient (flat)."""
+    """Mean squared error of z0 against z_target and its gradient (flat),
+    by the chain rule through the definition above."""
     prm = unpack(p)
     f = forward(g, s, p)
     n = g.n
@@ -113,8 +130,11 @@ def loss_and_grad(g, s, p, z_target):
     grads["W2"] = f["A2"].T @ dY2
     grads["b2"] = dY2.sum(axis=0)
     dA2 = dY2 @ prm["W2"].T
-    dH1 = dA2[:, :HID] + f["P"].T @ dA2[:, HID:]
+    dM = dA2[:, HID:]
+    dP = f["N"].T @ dM
+    grads["Wp"] = f["H1"].T @ dP
+    dH1 = dA2[:, :HID] + dP @ prm["Wp"].T
     dY1 = dH1 * (f["Y1"] > 0)
-    grads["W1"] = f["A1"].T @ dY1
+    grads["W1"] = f["X0"].T @ dY1
     grads["b1"] = dY1.sum(axis=0)
     return loss, pack(grads)

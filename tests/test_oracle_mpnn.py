@@ -12,15 +12,14 @@ from tests import graphs
 
 
 def _loop_forward(g, s, p):
+    """The network written out with explicit loops over rows, arcs and units."""
     prm = mpnn.unpack(p)
     n = g.n
     w = lambda k: 1.0 if g.w is None else float(g.w[k])
     d = np.zeros(n)
-    din = np.zeros(n)
     for i in range(n):
         for k in range(g.row_ptr[i], g.row_ptr[i + 1]):
             d[i] += w(k)
-            din[g.col[k]] += w(k)
 
     def nbr(x):
         out = np.zeros_like(x)
@@ -31,18 +30,33 @@ def _loop_forward(g, s, p):
                 out[i] /= d[i]
         return out
 
+    ns = nbr(np.asarray(s, float))
+    mean = sum(s) / n
     X = np.zeros((n, 8))
     for i in range(n):
-        X[i] = [s[i], 0, np.log1p(d[i]), np.log1p(din[i]), 1 / (1 + d[i]), np.mean(s), 1, 0]
-    X[:, 1] = nbr(np.asarray(s, float))
-    H1 = np.maximum(np.hstack([X, nbr(X)]) @ prm["W1"] + prm["b1"], 0)
-    H2 = np.maximum(np.hstack([H1, nbr(H1)]) @ prm["W2"] + prm["b2"], 0)
-    o = H2 @ prm["u"] + prm["c0"][0]
-    return min(s) + (max(s) - min(s)) / (1 + np.exp(-o))
+        X[i] = [s[i], ns[i], (s[i] + d[i] * ns[i]) / (1 + d[i]), np.log1p(d[i]), 1 / (1 + d[i]), mean, 1, 0]
+    H1 = np.zeros((n, 64))
+    for i in range(n):
+        for c in range(64):
+            H1[i, c] = max(0.0, sum(X[i, f] * prm["W1"][f, c] for f in range(8)) + prm["b1"][c])
+    P = np.zeros((n, 16))
+    for i in range(n):
+        for j in range(16):
+            P[i, j] = sum(H1[i, c] * prm["Wp"][c, j] for c in range(64))
+    M = nbr(P)
+    z0 = np.zeros(n)
+    for i in range(n):
+        o = prm["c0"][0]
+        for c in range(64):
+            y = prm["b2"][c] + sum(H1[i, m] * prm["W2"][m, c] for m in range(64)) + \
+                sum(M[i, j] * prm["W2"][64 + j, c] for j in range(16))
+            o += max(0.0, y) * prm["u"][c]
+        z0[i] = min(s) + (max(s) - min(s)) / (1 + np.exp(-o))
+    return z0
 
 
 def test_forward_matches_loop_definition():
-    g = graphs.random_graph(25, 0.2, 3, directed=True, weighted=True)
+    g = graphs.random_graph(12, 0.3, 3, directed=True, weighted=True)
     s = synth.opinions(g.n, "uniform", 4)
     p = mpnn.init_params(5)
     assert np.allclose(mpnn.forward(g, s, p)["z0"], _loop_forward(g, s, p), atol=1e-12)
@@ -64,7 +78,8 @@ def test_gradient_matches_finite_differences():
     p[mpnn.N_PARAMS - 1] = 0.3  # c0 away from a symmetric point
     loss, grad = mpnn.loss_and_grad(g, s, p, zt)
     rng = np.random.default_rng(12)
-    idx = np.concatenate([rng.choice(mpnn.N_PARAMS, 60, replace=False), [mpnn.N_PARAMS - 1]])
+    # entries of every block, c0 included
+    idx = np.concatenate([rng.integers(a, b, 12) for a, b in mpnn.offsets().values()] + [[mpnn.N_PARAMS - 1]])
     h = 1e-6
     for i in idx:
         e = np.zeros_like(p)
