@@ -429,28 +429,33 @@ fj_status fj_solve_batched(fj_batch* b, fj_solve_stats* stats_dev, fj_metrics_ou
  * proposes a starting estimate z0; by Lemma 4 any start is valid and by
  * Lemma 7 the same residual certificate decides the result, so passing z0 as
  * fj_solve_opts.z0 only changes how long the sweeps run.  Network (hidden
- * width 64, BF16 activations and weights on MFMA, FP32 accumulation):
- *   X0 = [s, nbr(s), log1p d, log1p din, 1/(1+d), mean s, 1, 0]
- *   H1 = relu([X0 | nbr(X0)] W1 + b1),  H2 = relu([H1 | nbr(H1)] W2 + b2)
+ * width 64, BF16 operands on MFMA, FP32 accumulation):
+ *   ns = nbr(s), z1 = (s + d ns) / (1 + d)  (one step of Eq. (1) from s)
+ *   X0 = [s, ns, z1, log1p d, 1/(1+d), mean s, 1, 0]
+ *   H1 = relu(X0 W1 + b1),  P = H1 Wp,  M = nbr(P)
+ *   H2 = relu([H1 | M] W2 + b2)
  *   z0 = min s + (max s - min s) sigmoid(H2 u + c0),  nbr(x)_v = sum_j a_vj x_j / d_v
- * params: device FP32 [fj_wsnet_param_count()] = W1 (16x64 row-major), b1 (64),
- * W2 (128x64), b2 (64), u (64), c0 (1).  The graph must come from
- * fj_graph_create (any flags).  Training uses the mean squared error
- * against a target z (normally a tighter solve of the same problem). */
+ * Layer 1's message is the opinion, layer 2's the 16-wide P.
+ * params: device FP32 [fj_wsnet_param_count()] = W1 (8x64 row-major), b1 (64),
+ * Wp (64x16), W2 (80x64), b2 (64), u (64), c0 (1).  The graph must come from
+ * fj_graph_create (any flags).  Training minimises the mean over nodes of
+ * w_v (z0_v - z_v)^2 against a target z (normally a tighter solve of the same
+ * problem), w_v = 1 / (z_v + rel_floor)^2 when rel_floor > 0 (the
+ * certificate is relative), else 1. */
 int32_t fj_wsnet_param_count(void);
 /* training != 0: room for the backward pass as well. */
 size_t fj_wsnet_workspace_bytes(const fj_graph* g, int32_t training);
 /* z0: device [n] out.  s: device [n]. */
 fj_status fj_wsnet_forward(const fj_graph* g, const double* s, const float* params, double* z0, void* ws,
                            size_t ws_bytes, void* stream);
-/* grad: device [param_count] out; loss: device scalar out (mean squared error). */
+/* grad: device [param_count] out; loss: device scalar out (the weighted mean squared error). */
 fj_status fj_wsnet_grad(const fj_graph* g, const double* s, const double* z_target, const float* params,
-                        float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
+                        double rel_floor, float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on params; adam_m/adam_v:
  * device [param_count] moment buffers (zero before step 1); step >= 1. */
 fj_status fj_wsnet_train_step(const fj_graph* g, const double* s, const double* z_target, float* params,
-                              float* adam_m, float* adam_v, int32_t step, float lr, float* loss, void* ws,
-                              size_t ws_bytes, void* stream);
+                              float* adam_m, float* adam_v, int32_t step, float lr, double rel_floor, float* loss,
+                              void* ws, size_t ws_bytes, void* stream);
 
 /* `steps` synchronous applications of the FJ update of Eq. (1),
  * z_i <- (s_i + sum_j a_ij z_j) / (1 + d_i), in place on z (device [n]).

@@ -22,7 +22,9 @@ Definition (all arrays FP64, n nodes, CSR of A with weights a_ij):
   o  = H2 u + c0
   z0 = min(s) + (max(s) - min(s)) sigmoid(o)   (inside [min s, max s], where
        the equilibrium lies: (I+L)^{-1} is row-stochastic, Sec. 3.3)
-  loss = mean_v (z0_v - z_v)^2
+  loss = mean_v w_v (z0_v - z_v)^2,  w_v = 1 (rel_floor <= 0) or
+         1 / (z_v + rel_floor)^2 (relative error with a floor; the
+         certificate is relative, so nodes with a small z weigh more)
 Layer 1's message is the opinion itself (ns), layer 2's a learned 16-wide
 projection of the hidden state.  Parameters are one flat FP32/FP64 vector:
 W1 (8x64 row-major), b1 (64), Wp (64x16), W2 (80x64), b2 (64), u (64), c0 (1).
@@ -115,15 +117,21 @@ def forward(g, s, p):
     return dict(N=N, X0=X0, Y1=Y1, H1=H1, P=P, M=M, A2=A2, Y2=Y2, H2=H2, o=o, sg=sg, z0=z0, lo=lo, hi=hi)
 
 
-def loss_and_grad(g, s, p, z_target):
-    """Mean squared error of z0 against z_target and its gradient (flat),
-    by the chain rule through the definition above."""
+def loss_weights(z_target, rel_floor=0.0):
+    z = np.asarray(z_target, dtype=np.float64)
+    return np.ones_like(z) if rel_floor <= 0.0 else 1.0 / (z + rel_floor) ** 2
+
+
+def loss_and_grad(g, s, p, z_target, rel_floor=0.0):
+    """The (weighted) mean squared error of z0 against z_target and its
+    gradient (flat), by the chain rule through the definition above."""
     prm = unpack(p)
     f = forward(g, s, p)
     n = g.n
     r = f["z0"] - np.asarray(z_target, dtype=np.float64)
-    loss = float(np.mean(r * r))
-    dz0 = 2.0 * r / n
+    wv = loss_weights(z_target, rel_floor)
+    loss = float(np.mean(wv * r * r))
+    dz0 = 2.0 * wv * r / n
     do = dz0 * (f["hi"] - f["lo"]) * f["sg"] * (1.0 - f["sg"])
     grads = {"u": f["H2"].T @ do, "c0": np.array([do.sum()])}
     dY2 = np.outer(do, prm["u"]) * (f["Y2"] > 0)

@@ -5,12 +5,24 @@
 // sweeps run.  fj_jacobi_steps implements the FJ update of Eq. (1) itself and
 // serves as the untrained control.
 //
-// Network (hidden width 64, BF16 storage, FP32 accumulation on MFMA):
-//   X0 = [s, nbr(s), log1p d, log1p din, 1/(1+d), mean s, 1, 0]
-//   H1 = relu([X0 | nbr(X0)] W1 + b1),  H2 = relu([H1 | nbr(H1)] W2 + b2)
+// Network (hidden width 64, BF16 operands on MFMA, FP32 accumulation):
+//   ns = nbr(s),  z1 = (s + d ns) / (1 + d)      (one step of Eq. (1) from s)
+//   X0 = [s, ns, z1, log1p d, 1/(1+d), mean s, 1, 0]
+//   H1 = relu(X0 W1 + b1)                        layer 1 (its message: s)
+//   P  = H1 Wp,  M = nbr(P)                      layer 2's 16-wide message
+//   H2 = relu([H1 | M] W2 + b2)                  layer 2
 //   z0 = min s + (max s - min s) sigmoid(H2 u + c0)
 // with nbr(x)_v = sum_j a_vj x_j / d_v.  Parameters are one flat FP32 vector:
-// W1 (16x64), b1 (64), W2 (128x64), b2 (64), u (64), c0 (1).
+// W1 (8x64), b1 (64), Wp (64x16), W2 (80x64), b2 (64), u (64), c0 (1).
+//
+// Every dense product runs on v_mfma_f32_16x16x16_bf16 over 16-row tiles, one
+// tile per wave step: the per-node layers (X0 -> H1 -> P and [H1|M] -> H2 ->
+// z0) and, in training, the weight gradients (X0^T dY1, H1^T dP, [H1|M]^T dY2)
+// and the products with transposed weights.  The gathers are the only
+// passes over the arcs: the neighbour sum of s, the 16-wide message over
+// CSR(A) forward and its transpose over CSR(A^T) backward.  The network never
+// stores H1, H2 or dY2: each tile kernel recomputes layer 1 from X0.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -23,121 +35,44 @@ namespace {
 
 constexpr int kF = 8;     // input features
 constexpr int kH = 64;    // hidden width
-constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 9280, kOffU = 9344, kOffC0 = 9408;
-constexpr int kNParams = 9409;
+constexpr int kMsg = 16;  // width of layer 2's message
+constexpr int kK2 = kH + kMsg;  // inputs of layer 2
+constexpr int kOffW1 = 0, kOffB1 = 512, kOffWp = 576, kOffW2 = 1600, kOffB2 = 6720, kOffU = 6784, kOffC0 = 6848;
+constexpr int kNParams = 6849;
+static_assert(kOffB1 == kF * kH && kOffWp == kOffB1 + kH && kOffW2 == kOffWp + kH * kMsg &&
+                  kOffB2 == kOffW2 + kK2 * kH && kOffU == kOffB2 + kH && kOffC0 == kOffU + kH && kNParams == kOffC0 + 1,
+              "parameter layout");
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);  // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
-}
+// round to nearest even (gfx950 converts in hardware: v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+__device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
 
 inline unsigned g1d(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
-// -------------------------------------------------------------- scalars
-// [0] sum s, [1] min s, [2] max s over n, per block then one block
-__global__ __launch_bounds__(256) void k_s_stats(int64_t n, const double* __restrict__ s, double* part) {
-    __shared__ double a[4], b[4], c[4];
-    double sm = 0.0, mn = INFINITY, mx = -INFINITY;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * 256) {
-        double v = s[i];
-        sm += v; mn = fmin(mn, v); mx = fmax(mx, v);
-    }
-    sm = wave_sum(sm);
-    for (int o = 32; o > 0; o >>= 1) { mn = fmin(mn, __shfl_xor(mn, o, 64)); mx = fmax(mx, __shfl_xor(mx, o, 64)); }
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 0) { a[w] = sm; b[w] = mn; c[w] = mx; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0, m1 = INFINITY, m2 = -INFINITY;
-        for (int k = 0; k < 4; ++k) { t += a[k]; m1 = fmin(m1, b[k]); m2 = fmax(m2, c[k]); }
-        part[3 * blockIdx.x + 0] = t; part[3 * blockIdx.x + 1] = m1; part[3 * blockIdx.x + 2] = m2;
-    }
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
-__global__ void k_s_stats_final(int nb, int64_t n, const double* __restrict__ part, double* out) {
-    if (threadIdx.x != 0) return;
-    double t = 0, m1 = INFINITY, m2 = -INFINITY;
-    for (int k = 0; k < nb; ++k) { t += part[3 * k]; m1 = fmin(m1, part[3 * k + 1]); m2 = fmax(m2, part[3 * k + 2]); }
-    out[0] = n ? t / static_cast<double>(n) : 0.0;  // mean
-    out[1] = m1;
-    out[2] = m2;
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
+    bf16x4 v;
+    v[0] = static_cast<short>(f2bf(a));
+    v[1] = static_cast<short>(f2bf(b));
+    v[2] = static_cast<short>(f2bf(c));
+    v[3] = static_cast<short>(f2bf(d));
+    return v;
 }
+__device__ __forceinline__ bf16x4 lds4(const uint16_t* p) {  // 8-byte aligned LDS read
+    return *reinterpret_cast<const bf16x4*>(p);
+}
+constexpr f32x4 kZero4 = {0.f, 0.f, 0.f, 0.f};
 
-// ----------------------------------------------------------- row sums
-// out[i] = sum over CSR row i of f(k); light tiles here, heavy rows by chunk
-// partials + k_rowsum_heavy (fixed order).
-template <int MODE>  // 0: sum a_ij s_j (CSR(A)); 1: sum of weights (in-degree over CSR(A^T))
-__global__ __launch_bounds__(kBlock) void k_rowsum_tiles(TileView tv, const int32_t* __restrict__ row_ptr,
-                                                         const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                         const double* __restrict__ x, double* partial, double* out) {
-    __shared__ int s_pre[kWavesPerBlock][65];
-    __shared__ double s_acc[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    auto f = [&](int k) {
-        double a = w ? static_cast<double>(w[k]) : 1.0;
-        if constexpr (MODE == 0) return a * x[col[k]];
-        return a;
-    };
-    if (wv < tv.nchunks) {
-        const int64_t c = tv.c0 + wv;
-        const int32_t row = tv.heavy_row[tv.chunk_heavy[c]];
-        const int beg = tv.chunk_beg[c];
-        double sum = chunk_sum(beg, min(beg + kArcBudget, row_ptr[row + 1]), f);
-        if (lane == 0) partial[c] = sum;
-        return;
-    }
-    wv -= tv.nchunks;
-    if (wv >= tv.ntiles) return;
-    const int64_t tix = tv.t0 + wv;
-    if (tv.tile_heavy[tix] >= 0) return;
-    const int32_t r0 = tv.tile_start[tix];
-    const int nrows = tv.tile_start[tix + 1] - r0;
-    double sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], f);
-    if (lane < nrows) out[r0 + lane] = sum;
-}
 
-__global__ __launch_bounds__(kBlock) void k_rowsum_heavy(TileView tv, const double* __restrict__ partial, double* out) {
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    if (hh >= tv.h1) return;
-    double sum = 0.0;
-    for (int32_t q = tv.heavy_chunk0[hh] + lane; q < tv.heavy_chunk0[hh + 1]; q += 64) sum += partial[q];
-    sum = wave_sum(sum);
-    if (lane == 0) out[tv.heavy_row[hh]] = sum;
-}
-
-// --------------------------------------------------------------- features
-__global__ void k_features(int64_t n, const double* __restrict__ s, const double* __restrict__ ws_sum,
-                           const double* __restrict__ opd, const double* __restrict__ din,
-                           const double* __restrict__ stats, uint16_t* X0) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double d = opd[i] - 1.0;
-    const double nb = d > 0.0 ? ws_sum[i] / d : 0.0;
-    float f[kF] = {static_cast<float>(s[i]), static_cast<float>(nb), static_cast<float>(log1p(d)),
-                   static_cast<float>(log1p(din[i])), static_cast<float>(1.0 / (1.0 + d)),
-                   static_cast<float>(stats[0]), 1.0f, 0.0f};
-    for (int q = 0; q < kF; ++q) X0[i * kF + q] = f2bf(f[q]);
-}
-
-__global__ void k_inv_deg(int64_t n, const double* __restrict__ opd, float* invd) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double d = opd[i] - 1.0;
-    invd[i] = d > 0.0 ? static_cast<float>(1.0 / d) : 0.0f;
-}
 
 // ------------------------------------------------------------ aggregation
-// M_v = sum_j a_vj X_j / d_v over CSR(A) rows, X bf16 [n][D] -> M bf16 [n][D].
-// Every lane loads 16 bytes (8 features) of a gathered row, so one arc takes
-// D/8 lanes.  Rows longer than kArcBudget are done by k_agg_heavy (one
-// 1024-thread block per row); the light kernels skip them.
+// BF16 rows of 8 features, accumulated in FP32: 16 bytes per lane and arc.
 struct Acc8 {
     float v[8];
 };
@@ -157,37 +92,73 @@ __device__ __forceinline__ uint4 acc8_pack(const Acc8& acc, float sc) {
     return uint4{q[0], q[1], q[2], q[3]};
 }
 
-// lanes of one wave in groups of D/8; group g takes arcs b + start + g, + stride, ...
-template <int D>
-__device__ __forceinline__ void agg_accum(int b, int e, int lane, const int32_t* __restrict__ col,
-                                          const float* __restrict__ w, const uint16_t* __restrict__ X, int start,
-                                          int stride, Acc8& acc) {
-    constexpr int L = D / 8;  // lanes per arc
-    const int sub = lane / L, part = lane % L;
-    for (int k = b + start + sub; k < e; k += stride) {
-        const int j = col[k];
-        const float a = w ? w[k] : 1.0f;
-        acc8_add(acc, a, reinterpret_cast<const uint4*>(X + static_cast<int64_t>(j) * D)[part]);
+// grid for the grid-stride kernels: enough waves to fill every CU, no more
+// than the work needs
+inline unsigned stride_blocks(int64_t waves, int per_cu = 16) {
+    const int64_t cap = 256 * static_cast<int64_t>(per_cu);  // blocks of 4 waves per CU
+    const int64_t need = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min(need, cap)));
+}
+
+
+// ------------------------------------------------- per-call node passes
+// One pass over the nodes: per-block sum, min and max of s, the FP32 copy of
+// s the neighbour sums gather, and 1/d (0 where d = 0) for the means.
+__global__ __launch_bounds__(256) void k_s_prep(int64_t n, const double* __restrict__ s,
+                                                const double* __restrict__ opd, double* part, float* s32,
+                                                float* invd) {
+    __shared__ double a[4], b[4], c[4];
+    double sm = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256) {
+        const double v = s[i], d = opd[i] - 1.0;
+        sm += v;
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+        s32[i] = static_cast<float>(v);
+        invd[i] = d > 0.0 ? static_cast<float>(1.0 / d) : 0.0f;
+    }
+    sm = wave_sum(sm);
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) { a[w] = sm; b[w] = mn; c[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0, m1 = INFINITY, m2 = -INFINITY;
+        for (int k = 0; k < 4; ++k) { t += a[k]; m1 = fmin(m1, b[k]); m2 = fmax(m2, c[k]); }
+        part[3 * blockIdx.x + 0] = t; part[3 * blockIdx.x + 1] = m1; part[3 * blockIdx.x + 2] = m2;
+    }
+}
+// mean, min, max from the block partials: one wave, fixed order
+__global__ void k_s_final(int nb, int64_t n, const double* __restrict__ part, double* out) {
+    const int lane = lane_id();
+    double t = 0, m1 = INFINITY, m2 = -INFINITY;
+    for (int k = lane; k < nb; k += 64) {
+        t += part[3 * k];
+        m1 = fmin(m1, part[3 * k + 1]);
+        m2 = fmax(m2, part[3 * k + 2]);
+    }
+    t = wave_sum(t);
+    for (int o = 32; o > 0; o >>= 1) {
+        m1 = fmin(m1, __shfl_xor(m1, o, 64));
+        m2 = fmax(m2, __shfl_xor(m2, o, 64));
+    }
+    if (lane == 0) {
+        out[0] = n ? t / static_cast<double>(n) : 0.0;
+        out[1] = m1;
+        out[2] = m2;
     }
 }
 
-// fold the 64 / (D/8) arc groups of a wave, fixed order; lanes < D/8 hold the row
-template <int D>
-__device__ __forceinline__ void agg_fold(Acc8& acc) {
-#pragma unroll
-    for (int o = D / 8; o < 64; o <<= 1)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
-}
-
-// D = 8: eight lanes per row (16 bytes per arc, lane p of a row takes its
-// arcs p, p + 8, ...), eight consecutive rows per wave, grid-stride over the
-// groups of eight rows.  The eight partial sums of a row are folded in a
-// fixed order.
-__global__ __launch_bounds__(kBlock) void k_agg_rows8(int64_t n, const int32_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                     const float* __restrict__ invd, const uint16_t* __restrict__ X,
-                                                     uint16_t* M) {
+// rs_i = sum_j a_ij s_j over CSR(A) from the FP32 copy: eight lanes per row
+// (lane p takes arcs p, p + 8, ...), eight rows per wave, a fixed-order fold;
+// rows longer than kArcBudget are left to k_nbr_heavy
+__global__ __launch_bounds__(kBlock) void k_nbr_rows(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                    const float* __restrict__ s32, float* rs) {
     const int lane = lane_id(), p = lane & 7;
     const int64_t groups = (n + 7) / 8;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
@@ -198,315 +169,636 @@ __global__ __launch_bounds__(kBlock) void k_agg_rows8(int64_t n, const int32_t* 
         if (i < n) {
             b = row_ptr[i];
             e = row_ptr[i + 1];
-            if (e - b > kArcBudget) e = b;  // heavy: k_agg_heavy
+            if (e - b > kArcBudget) e = b;
         }
-        Acc8 acc{};
-        for (int k = b + p; k < e; k += 8) {
-            const int j = col[k];
-            const float a = w ? w[k] : 1.0f;
-            acc8_add(acc, a, reinterpret_cast<const uint4*>(X)[j]);
-        }
+        float acc = 0.f;
+        for (int k = b + p; k < e; k += 8) acc += (w ? w[k] : 1.0f) * s32[col[k]];
 #pragma unroll
-        for (int o = 1; o < 8; o <<= 1)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
-        if (p == 0 && i < n && row_ptr[i + 1] - row_ptr[i] <= kArcBudget)
-            reinterpret_cast<uint4*>(M)[i] = acc8_pack(acc, invd[i]);
+        for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        if (p == 0 && i < n && row_ptr[i + 1] - row_ptr[i] <= kArcBudget) rs[i] = acc;
     }
 }
+// Heavy rows of CSR(A) (more than kArcBudget arcs) in 256-arc chunks, a wave
+// per chunk: partial sums per chunk, then k_nbr_combine adds a row's chunks in
+// chunk order
+__global__ __launch_bounds__(kBlock) void k_nbr_chunks(TileView tv, const int32_t* __restrict__ col,
+                                                      const float* __restrict__ w, const float* __restrict__ s32,
+                                                      float* partial) {
+    const int lane = lane_id();
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (c >= tv.nchunks) return;
+    const int64_t cidx = tv.c0 + c;
+    const int beg = tv.chunk_beg[cidx], end = tv.chunk_end[cidx];
+    float acc = 0.f;
+    for (int k = beg + lane; k < end; k += 64) acc += (w ? w[k] : 1.0f) * s32[col[k]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) partial[cidx] = acc;
+}
+__global__ __launch_bounds__(kBlock) void k_nbr_combine(TileView tv, const float* __restrict__ partial, float* rs) {
+    const int lane = lane_id();
+    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (hh >= tv.h1) return;
+    float t = 0.f;
+    for (int32_t q = tv.heavy_chunk0[hh] + lane; q < tv.heavy_chunk0[hh + 1]; q += 64) t += partial[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) rs[tv.heavy_row[hh]] = t;
+}
 
-// D = 64: a wave per row, 8 lanes per arc (one 128-byte line), 8 arcs per step;
-// grid-stride over rows.
-__global__ __launch_bounds__(kBlock) void k_agg_rows64(int64_t n, const int32_t* __restrict__ row_ptr,
+// ------------------------------------------------------ message aggregation
+// M_v = sum_j a_vj P_j / d_v for the 16-wide BF16 message P over CSR(A): 32
+// bytes per arc, two lanes per arc (16 bytes each), eight lanes per row (four
+// arcs in flight), eight rows per wave, grid-stride over groups of eight
+// rows.  The four arc groups of a row are folded in a fixed order.  Rows
+// longer than kArcBudget are left to k_agg16_chunks.
+__global__ __launch_bounds__(kBlock) void k_agg_rows16(int64_t n, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col, const float* __restrict__ w,
                                                       const float* __restrict__ invd, const uint16_t* __restrict__ X,
                                                       uint16_t* M) {
-    const int lane = lane_id();
+    const int lane = lane_id(), p = lane & 7, sub = p >> 1, half = p & 1;
+    const int64_t groups = (n + 7) / 8;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); i < n; i += stride) {
-        const int b = row_ptr[i], e = row_ptr[i + 1];
-        if (e - b > kArcBudget) continue;  // uniform across the wave
+    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); gi < groups;
+         gi += stride) {
+        const int64_t i = gi * 8 + (lane >> 3);
+        int b = 0, e = 0;
+        if (i < n) {
+            b = row_ptr[i];
+            e = row_ptr[i + 1];
+            if (e - b > kArcBudget) e = b;  // heavy: k_agg16_chunks
+        }
         Acc8 acc{};
-        agg_accum<kH>(b, e, lane, col, w, X, 0, 8, acc);
-        agg_fold<kH>(acc);
-        if (lane < 8) reinterpret_cast<uint4*>(M + i * kH)[lane] = acc8_pack(acc, invd[i]);
-    }
-}
-
-template <int D>
-__global__ __launch_bounds__(1024) void k_agg_heavy(TileView tv, const int32_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                    const float* __restrict__ invd, const uint16_t* __restrict__ X,
-                                                    uint16_t* M) {
-    constexpr int L = D / 8, G = 64 / L;  // lanes per arc, arcs per wave step
-    __shared__ Acc8 part[16][L];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int32_t i = tv.heavy_row[tv.h0 + blockIdx.x];
-    const int b = row_ptr[i], e = row_ptr[i + 1];
-    Acc8 acc{};
-    agg_accum<D>(b, e, lane, col, w, X, wid * G, 16 * G, acc);
-    agg_fold<D>(acc);
-    if (lane < L) part[wid][lane] = acc;
-    __syncthreads();
-    if (wid == 0 && lane < L) {
-        Acc8 t{};
-        for (int v = 0; v < 16; ++v)
+        for (int k = b + sub; k < e; k += 4) {
+            const int j = col[k];
+            const float a = w ? w[k] : 1.0f;
+            acc8_add(acc, a, reinterpret_cast<const uint4*>(X)[2 * static_cast<int64_t>(j) + half]);
+        }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) t.v[q] += part[v][lane].v[q];
-        reinterpret_cast<uint4*>(M + static_cast<int64_t>(i) * D)[lane] = acc8_pack(t, invd[i]);
+        for (int o = 2; o < 8; o <<= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
+        if (sub == 0 && i < n && row_ptr[i + 1] - row_ptr[i] <= kArcBudget)
+            reinterpret_cast<uint4*>(M)[2 * i + half] = acc8_pack(acc, invd[i]);
     }
 }
 
-// grid for the grid-stride kernels: enough waves to fill every CU, no more
-// than the work needs
-inline unsigned stride_blocks(int64_t waves, int per_cu = 16) {
-    const int64_t cap = 256 * static_cast<int64_t>(per_cu);  // blocks of 4 waves per CU
-    const int64_t need = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    return static_cast<unsigned>(std::max<int64_t>(1, std::min(need, cap)));
+// Heavy rows of the 16-wide aggregation in 256-arc chunks: a wave per chunk
+// (two lanes per arc, 32 arcs per step) writes 16 FP32 partial sums; then
+// k_agg16_combine adds a row's chunks in chunk order and scales by 1/d.
+__global__ __launch_bounds__(kBlock) void k_agg16_chunks(TileView tv, const int32_t* __restrict__ col,
+                                                        const float* __restrict__ w, const uint16_t* __restrict__ X,
+                                                        float* partial) {
+    const int lane = lane_id(), half = lane & 1, sub = lane >> 1;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (c >= tv.nchunks) return;
+    const int64_t cidx = tv.c0 + c;
+    const int beg = tv.chunk_beg[cidx], end = tv.chunk_end[cidx];
+    Acc8 acc{};
+    for (int k = beg + sub; k < end; k += 32) {
+        const int j = col[k];
+        acc8_add(acc, w ? w[k] : 1.0f, reinterpret_cast<const uint4*>(X)[2 * static_cast<int64_t>(j) + half]);
+    }
+#pragma unroll
+    for (int o = 2; o < 64; o <<= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc.v[q] += __shfl_xor(acc.v[q], o, 64);
+    if (sub == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) partial[cidx * kMsg + 8 * half + q] = acc.v[q];
+}
+__global__ __launch_bounds__(kBlock) void k_agg16_combine(TileView tv, const float* __restrict__ partial,
+                                                         const float* __restrict__ invd, uint16_t* M) {
+    const int lane = lane_id();
+    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (hh >= tv.h1 || lane >= kMsg) return;
+    float t = 0.f;
+    for (int32_t q = tv.heavy_chunk0[hh]; q < tv.heavy_chunk0[hh + 1]; ++q) t += partial[static_cast<int64_t>(q) * kMsg + lane];
+    const int32_t i = tv.heavy_row[hh];
+    M[static_cast<int64_t>(i) * kMsg + lane] = f2bf(t * invd[i]);
 }
 
-// Backward of the aggregation: out_j = sum over u with a_uj > 0 of
-// (a_uj / d_u) G_u, i.e. a gather over row j of CSR(A^T).  G is the right half
-// (columns 64..127) of dA2 (FP32, row stride 128).  Fused with the rest of
-// layer 1's backward: dY1_j = (dA2_j[0:64] + out_j) * [H1_j > 0].
-__global__ __launch_bounds__(kBlock) void k_aggT_light(int64_t n, const int32_t* __restrict__ t_row_ptr,
-                                                       const int32_t* __restrict__ t_col, const float* __restrict__ t_w,
-                                                       const float* __restrict__ invd, const float* __restrict__ dA2,
-                                                       const uint16_t* __restrict__ H1, float* dY1) {
-    const int lane = lane_id();
-    const int64_t j = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+// Backward of the aggregation: dP_j = sum over v with a_vj > 0 of
+// (a_vj / d_v) dM_v, a gather over row j of CSR(A^T) of 16-wide FP32 rows.
+// Sixteen lanes per row (one feature each), four rows per wave; rows longer
+// than kArcBudget are left to k_aggT16_heavy.
+__global__ __launch_bounds__(kBlock) void k_aggT16_light(int64_t n, const int32_t* __restrict__ t_row_ptr,
+                                                        const int32_t* __restrict__ t_col,
+                                                        const float* __restrict__ t_w, const float* __restrict__ invd,
+                                                        const float* __restrict__ dM, float* dP) {
+    const int lane = lane_id(), f = lane & 15;
+    const int64_t j = ((static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 4);
     if (j >= n) return;
     const int b = t_row_ptr[j], e = t_row_ptr[j + 1];
     if (e - b > kArcBudget) return;
     float acc = 0.f;
     for (int k = b; k < e; ++k) {
-        const int u = t_col[k];
-        const float a = (t_w ? t_w[k] : 1.0f) * invd[u];
-        acc += a * dA2[static_cast<int64_t>(u) * 128 + 64 + lane];
+        const int v = t_col[k];
+        acc += (t_w ? t_w[k] : 1.0f) * invd[v] * dM[static_cast<int64_t>(v) * kMsg + f];
     }
-    const float g = dA2[j * 128 + lane] + acc;
-    dY1[j * kH + lane] = bf2f(H1[j * kH + lane]) > 0.f ? g : 0.f;
+    dP[j * kMsg + f] = acc;
 }
 
-__global__ __launch_bounds__(1024) void k_aggT_heavy(TileView tv, const int32_t* __restrict__ t_row_ptr,
-                                                     const int32_t* __restrict__ t_col, const float* __restrict__ t_w,
-                                                     const float* __restrict__ invd, const float* __restrict__ dA2,
-                                                     const uint16_t* __restrict__ H1, float* dY1) {
-    __shared__ float sacc[16][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+// one 1024-thread block per heavy row of CSR(A^T): 64 groups of 16 lanes
+// stride over its arcs, then the groups are added in a fixed order
+__global__ __launch_bounds__(1024) void k_aggT16_heavy(TileView tv, const int32_t* __restrict__ t_row_ptr,
+                                                      const int32_t* __restrict__ t_col, const float* __restrict__ t_w,
+                                                      const float* __restrict__ invd, const float* __restrict__ dM,
+                                                      float* dP) {
+    __shared__ float sacc[64][kMsg];
+    const int grp = threadIdx.x >> 4, f = threadIdx.x & 15;
     const int32_t j = tv.heavy_row[tv.h0 + blockIdx.x];
     const int b = t_row_ptr[j], e = t_row_ptr[j + 1];
     float acc = 0.f;
-    for (int k = b + wid; k < e; k += 16) {
-        const int u = t_col[k];
-        const float a = (t_w ? t_w[k] : 1.0f) * invd[u];
-        acc += a * dA2[static_cast<int64_t>(u) * 128 + 64 + lane];
+    for (int k = b + grp; k < e; k += 64) {
+        const int v = t_col[k];
+        acc += (t_w ? t_w[k] : 1.0f) * invd[v] * dM[static_cast<int64_t>(v) * kMsg + f];
     }
-    sacc[wid][lane] = acc;
+    sacc[grp][f] = acc;
     __syncthreads();
-    if (wid == 0) {
+    if (threadIdx.x < kMsg) {
         float t = 0.f;
-        for (int v = 0; v < 16; ++v) t += sacc[v][lane];
-        const float g = dA2[static_cast<int64_t>(j) * 128 + lane] + t;
-        dY1[static_cast<int64_t>(j) * kH + lane] = bf2f(H1[static_cast<int64_t>(j) * kH + lane]) > 0.f ? g : 0.f;
+        for (int g = 0; g < 64; ++g) t += sacc[g][f];
+        dP[static_cast<int64_t>(j) * kMsg + f] = t;
     }
 }
 
-// ------------------------------------------------------------------ GEMM
-// Y[16 rows x N] per wave on v_mfma_f32_16x16x16_bf16: A = [A_left | A_right]
-// (bf16, widths KL and KR, row-major), W (bf16) read from LDS as Wt[j][k].
-// Lane l supplies A[row l%16][k 4(l/16)..+3] and Wt[col l%16][k 4(l/16)..+3];
-// it receives D[rows 4(l/16)+q][col l%16].
-// MODE 0: H = relu(Y + b) stored bf16 [n][N]
-// MODE 1: H2 = relu(Y + b) stored bf16; o = H2 u + c0; z0 = lo + (hi-lo) sigmoid(o)
-// MODE 2: as 1 without storing H2 (inference)
-// MODE 3: Y stored FP32 [n][N] (backward: dA = dY W^T; W given as [N][K])
-template <int KL, int KR, int N, int MODE>
-__global__ __launch_bounds__(kBlock) void k_gemm(int64_t n, const uint16_t* __restrict__ Al,
-                                                 const uint16_t* __restrict__ Ar, const uint16_t* __restrict__ W,
-                                                 const float* __restrict__ bias, const float* __restrict__ u,
-                                                 const float* __restrict__ c0, const double* __restrict__ stats,
-                                                 uint16_t* Hout, float* Yout, float* o_out, double* z0) {
-    constexpr int K = KL + KR;
-    static_assert(K % 16 == 0 && N % 16 == 0 && KL % 4 == 0, "tile shapes");
-    __shared__ uint16_t Wt[N][K + 4];
-    for (int idx = threadIdx.x; idx < N * K; idx += kBlock) {  // coalesced reads of W
-        if constexpr (MODE == 3) Wt[idx / K][idx % K] = W[idx];
-        else Wt[idx % N][idx / N] = W[idx];
+// ------------------------------------------------------------ tile kernels
+// A wave takes 16 consecutive rows at a time.  v_mfma_f32_16x16x16_bf16:
+// lane l (li = l % 16, kq = l / 16) supplies A[row li][k 4kq..4kq+3] and
+// B[k 4kq..4kq+3][col li] and receives D[rows 4kq..4kq+3][col li].  D's
+// layout is also the A operand of the transposed product (A^T with rows of
+// the tile as k), so the weight gradients take layer outputs straight from
+// registers.  Weights live in LDS as BF16, transposed where they are B.
+constexpr int kW1S = 16 + 4;  // padded row strides (multiples of 4: 8-byte reads)
+constexpr int kHS = kH + 4;
+constexpr int kW2S = kK2 + 4;
+constexpr int kMS = kMsg + 4;
+
+struct NetW {  // forward weights of one block
+    uint16_t w1t[kH][kW1S];    // w1t[n][k] = W1[k][n], k < 8 (k 8..15 zero)
+    uint16_t wpt[kMsg][kHS];   // wpt[j][m] = Wp[m][j]
+    uint16_t w2t[kH][kW2S];    // w2t[n][k] = W2[k][n]
+};
+struct NetWB {  // extra weights of the backward (row-major)
+    uint16_t w2r[kK2][kHS];    // W2[k][n]
+    uint16_t wpr[kH][kMS];     // Wp[m][j]
+};
+
+__device__ void load_weights(const float* __restrict__ p, NetW& W) {
+    for (int i = threadIdx.x; i < kH * 16; i += blockDim.x) {
+        const int nn = i / 16, k = i % 16;
+        W.w1t[nn][k] = k < kF ? f2bf(p[kOffW1 + k * kH + nn]) : 0;
     }
+    for (int i = threadIdx.x; i < kMsg * kH; i += blockDim.x) {
+        const int j = i / kH, m = i % kH;
+        W.wpt[j][m] = f2bf(p[kOffWp + m * kMsg + j]);
+    }
+    for (int i = threadIdx.x; i < kH * kK2; i += blockDim.x) {
+        const int nn = i / kK2, k = i % kK2;
+        W.w2t[nn][k] = f2bf(p[kOffW2 + k * kH + nn]);
+    }
+}
+__device__ void load_weights_bwd(const float* __restrict__ p, NetWB& B) {
+    for (int i = threadIdx.x; i < kK2 * kH; i += blockDim.x) B.w2r[i / kH][i % kH] = f2bf(p[kOffW2 + i]);
+    for (int i = threadIdx.x; i < kH * kMsg; i += blockDim.x) B.wpr[i / kMsg][i % kMsg] = f2bf(p[kOffWp + i]);
+}
+
+struct NetIn {
+    int64_t n;
+    const double* s;
+    const float* rs;      // sum_j a_ij s_j
+    const double* opd;    // 1 + d
+    const double* stats;  // mean, min, max of s
+    const float* p;       // parameters (FP32)
+    double rel_floor;     // loss weights 1 / (z + rel_floor)^2 when > 0, else 1
+};
+
+// X0 of row r: [s, ns, z1, log1p d, 1/(1+d), mean s, 1, 0], in FP32 (the
+// MFMA takes them in BF16)
+__device__ __forceinline__ void features8(const NetIn& I, int64_t r, float* f) {
+    const float sv = static_cast<float>(I.s[r]), o = static_cast<float>(I.opd[r]), d = o - 1.0f, rsv = I.rs[r];
+    const float inv = 1.0f / o;
+    f[0] = sv;
+    f[1] = d > 0.0f ? rsv / d : 0.0f;
+    f[2] = (sv + rsv) * inv;
+    f[3] = log1pf(d);
+    f[4] = inv;
+    f[5] = static_cast<float>(I.stats[0]);
+    f[6] = 1.0f;
+    f[7] = 0.0f;
+}
+
+// Layer 1 of the tile at row0: y (D layout) = X0 W1 + b1, h = BF16 relu(y)
+// (D layout), and h into the wave's LDS tile Hs[row][unit].
+__device__ __forceinline__ void tile_layer1(const NetIn& I, const NetW& W, int64_t row0, int li, int kq, f32x4 y[4],
+                                            float h[4][4], uint16_t (*Hs)[kHS]) {
+    const int64_t r = min(row0 + li, I.n - 1);
+    float f[8];
+    features8(I, r, f);
+    const bf16x4 a = kq == 0 ? pack4(f[0], f[1], f[2], f[3]) : kq == 1 ? pack4(f[4], f[5], f[6], f[7])
+                                                                       : pack4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        y[t] = mfma16(a, lds4(&W.w1t[16 * t + li][4 * kq]), kZero4);
+        const float bj = I.p[kOffB1 + 16 * t + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            y[t][q] += bj;
+            const uint16_t hb = f2bf(fmaxf(y[t][q], 0.f));
+            h[t][q] = bf2f(hb);
+            Hs[4 * kq + q][16 * t + li] = hb;
+        }
+    }
+}
+
+// Layer 2 of the tile: y2 (D layout) = [H1 | M] W2 + b2, H1 from Hs
+__device__ __forceinline__ void tile_layer2(const NetIn& I, const NetW& W, const uint16_t* __restrict__ M,
+                                            int64_t row0, int li, int kq, const uint16_t (*Hs)[kHS], f32x4 y2[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) y2[t] = kZero4;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const bf16x4 a = lds4(&Hs[li][16 * ks + 4 * kq]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) y2[t] = mfma16(a, lds4(&W.w2t[16 * t + li][16 * ks + 4 * kq]), y2[t]);
+    }
+    const int64_t r = min(row0 + li, I.n - 1);
+    const bf16x4 am = *reinterpret_cast<const bf16x4*>(M + r * kMsg + 4 * kq);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        y2[t] = mfma16(am, lds4(&W.w2t[16 * t + li][kH + 4 * kq]), y2[t]);
+        const float bj = I.p[kOffB2 + 16 * t + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y2[t][q] += bj;
+    }
+}
+
+// o for rows 4kq..4kq+3 of the tile (in all 16 lanes of the kq group), from
+// H2 = relu(y2) rounded to BF16 (h2, D layout)
+__device__ __forceinline__ void tile_readout(const NetIn& I, const f32x4 y2[4], int li, float o[4], float h2[4][4]) {
+    float pq[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float uj = I.p[kOffU + 16 * t + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            h2[t][q] = bfround(fmaxf(y2[t][q], 0.f));
+            pq[q] += h2[t][q] * uj;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) pq[q] += __shfl_xor(pq[q], off, 64);
+    const float c0 = I.p[kOffC0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = pq[q] + c0;
+}
+
+inline unsigned fwd_blocks(int64_t n) {
+    const int64_t tiles = (n + 15) / 16;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(1024, (tiles + kWavesPerBlock - 1) / kWavesPerBlock)));
+}
+inline unsigned bwd_blocks(int64_t n) {
+    const int64_t tiles = (n + 15) / 16;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(256, (tiles + kWavesPerBlock - 1) / kWavesPerBlock)));
+}
+
+// The forward in transposed form: H^T = W^T X^T puts the tile's rows on the
+// MFMA's n axis, so lane (li, kq) receives row li's units 16t + 4kq .. +3 --
+// exactly the B operand (row li, four consecutive k) of the next product.
+// Activations never leave registers.
+// Layer 1 of the tile at row0 in this form: h[t][q] = H1[row li][16t + 4kq + q]
+// (BF16-rounded); y1 before the relu.
+__device__ __forceinline__ void tile_layer1_t(const NetIn& I, const NetW& W, int64_t row0, int li, int kq,
+                                              float y1[4][4], float h[4][4]) {
+    const int64_t r = min(row0 + li, I.n - 1);
+    float f[8];
+    features8(I, r, f);
+    const bf16x4 b = kq == 0 ? pack4(f[0], f[1], f[2], f[3]) : kq == 1 ? pack4(f[4], f[5], f[6], f[7])
+                                                                       : pack4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 y = mfma16(lds4(&W.w1t[16 * t + li][4 * kq]), b, kZero4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            y1[t][q] = y[q] + I.p[kOffB1 + 16 * t + 4 * kq + q];
+            h[t][q] = bfround(fmaxf(y1[t][q], 0.f));
+        }
+    }
+}
+
+// P = H1 Wp (BF16 [n][16]); in transposed form lane (li, kq) gets row li's
+// message entries 4kq .. 4kq+3 and stores them as one 8-byte word
+__global__ __launch_bounds__(kBlock) void k_net_l1(NetIn I, uint16_t* __restrict__ P) {
+    __shared__ NetW W;
+    load_weights(I.p, W);
     __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int li = lane & 15, lk = (lane >> 4) * 4;
-    // grid-stride over 16-row tiles, so every block loads W once
-    const int64_t tile_stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock * 16;
-    for (int64_t row0 = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 16; row0 < n;
-         row0 += tile_stride) {
-        const int64_t ar = min(row0 + li, n - 1);
-        f32x4 acc[N / 16];
+    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int64_t tiles = (I.n + 15) / 16;
+    for (int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; tt < tiles;
+         tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+        const int64_t row0 = tt * 16;
+        float y1[4][4], h[4][4];
+        tile_layer1_t(I, W, row0, li, kq, y1, h);
+        f32x4 pt = kZero4;
 #pragma unroll
-        for (int t = 0; t < N / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < 4; ++ks)
+            pt = mfma16(lds4(&W.wpt[li][16 * ks + 4 * kq]), pack4(h[ks][0], h[ks][1], h[ks][2], h[ks][3]), pt);
+        const int64_t r = row0 + li;
+        if (r < I.n) *reinterpret_cast<bf16x4*>(P + r * kMsg + 4 * kq) = pack4(pt[0], pt[1], pt[2], pt[3]);
+    }
+}
+
+// z0 = lo + (hi - lo) sigmoid(o), o = H2 u + c0, H2 = relu([H1 | M] W2 + b2)
+__global__ __launch_bounds__(kBlock) void k_net_l2(NetIn I, const uint16_t* __restrict__ M, double* __restrict__ z0) {
+    __shared__ NetW W;
+    load_weights(I.p, W);
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const double lo = I.stats[1], hi = I.stats[2];
+    const float c0 = I.p[kOffC0];
+    const int64_t tiles = (I.n + 15) / 16;
+    for (int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; tt < tiles;
+         tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+        const int64_t row0 = tt * 16;
+        float y1[4][4], h[4][4];
+        tile_layer1_t(I, W, row0, li, kq, y1, h);
+        bf16x4 bh[4];
 #pragma unroll
-        for (int ks = 0; ks < K / 16; ++ks) {
-            const int k = ks * 16 + lk;
-            bf16x4 a;
-            if (k < KL) a = *reinterpret_cast<const bf16x4*>(Al + ar * KL + k);
-            else a = *reinterpret_cast<const bf16x4*>(Ar + ar * KR + (k - KL));
+        for (int ks = 0; ks < 4; ++ks) bh[ks] = pack4(h[ks][0], h[ks][1], h[ks][2], h[ks][3]);
+        const int64_t r = min(row0 + li, I.n - 1);
+        const bf16x4 bm = *reinterpret_cast<const bf16x4*>(M + r * kMsg + 4 * kq);
+        float o = 0.f;
 #pragma unroll
-            for (int t = 0; t < N / 16; ++t) {
-                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Wt[t * 16 + li][k]);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[t], 0, 0, 0);
-            }
-        }
-        if constexpr (MODE == 3) {
+        for (int t = 0; t < 4; ++t) {
+            f32x4 y2 = kZero4;
 #pragma unroll
-            for (int t = 0; t < N / 16; ++t)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t r = row0 + lk + q;
-                    if (r < n) Yout[r * N + t * 16 + li] = acc[t][q];
-                }
-            continue;
-        }
-        float p[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < N / 16; ++t) {
-            const int j = t * 16 + li;
-            const float bj = bias[j];
+            for (int ks = 0; ks < 4; ++ks) y2 = mfma16(lds4(&W.w2t[16 * t + li][16 * ks + 4 * kq]), bh[ks], y2);
+            y2 = mfma16(lds4(&W.w2t[16 * t + li][kH + 4 * kq]), bm, y2);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t r = row0 + lk + q;
-                const float h = fmaxf(acc[t][q] + bj, 0.f);
-                const uint16_t hb = f2bf(h);
-                if constexpr (MODE == 0 || MODE == 1)
-                    if (r < n) Hout[r * N + j] = hb;
-                if constexpr (MODE == 1 || MODE == 2) p[q] += bf2f(hb) * u[j];
+                const int unit = 16 * t + 4 * kq + q;
+                o += bfround(fmaxf(y2[q] + I.p[kOffB2 + unit], 0.f)) * I.p[kOffU + unit];
             }
         }
-        if constexpr (MODE == 1 || MODE == 2) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) p[q] += __shfl_xor(p[q], o, 64);
-            if (li == 0) {
-                const double lo = stats[1], hi = stats[2];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t r = row0 + lk + q;
-                    if (r < n) {
-                        const float o = p[q] + c0[0];
-                        if (o_out) o_out[r] = o;
-                        const double sg = 1.0 / (1.0 + exp(-static_cast<double>(o)));
-                        z0[r] = lo + (hi - lo) * sg;
-                    }
-                }
-            }
-        }
-    }  // row tiles
-}
-
-// -------------------------------------------------- readout backward + loss
-// do = (2/n)(z0 - z*) (hi-lo) sg(1-sg);  dY2 = do u * [H2 > 0] (FP32 and bf16);
-// per-block partial of sum (z0 - z*)^2.
-__global__ __launch_bounds__(kBlock) void k_readout_bwd(int64_t n, const double* __restrict__ z0,
-                                                        const double* __restrict__ zt, const float* __restrict__ o,
-                                                        const double* __restrict__ stats, const float* __restrict__ u,
-                                                        const uint16_t* __restrict__ H2, float* dout, float* dY2,
-                                                        uint16_t* dY2b, double* loss_part) {
-    __shared__ double lds[kWavesPerBlock];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;  // a wave per row
-    double l2 = 0.0;
-    if (r < n) {
-        const double diff = z0[r] - zt[r];
-        const double sg = 1.0 / (1.0 + exp(-static_cast<double>(o[r])));
-        const float dor = static_cast<float>(2.0 * diff / static_cast<double>(n) * (stats[2] - stats[1]) * sg * (1.0 - sg));
-        if (lane == 0) { dout[r] = dor; l2 = diff * diff; }
-        const float g = bf2f(H2[r * kH + lane]) > 0.f ? dor * u[lane] : 0.f;
-        dY2[r * kH + lane] = g;
-        dY2b[r * kH + lane] = f2bf(g);
+        o += __shfl_xor(o, 16, 64);
+        o += __shfl_xor(o, 32, 64);
+        if (kq == 0 && row0 + li < I.n)
+            z0[row0 + li] = lo + (hi - lo) / (1.0 + exp(-static_cast<double>(o + c0)));
     }
-    l2 = block_sum<kBlock>(l2, lds);
-    if (threadIdx.x == 0) loss_part[blockIdx.x] = l2;
 }
 
-// ---------------------------------------------------- A^T B reductions
-// out[k][j] = sum_rows A'[row][k] B[row][j] with A' = [A_left | A_right | 1]
-// (bf16 inputs; the trailing ones column yields the bias gradient), B FP32
-// [n][N].  Blocks own row ranges; each thread owns fixed (k, j) outputs; the
-// per-block partials are summed in block order by k_atb_final.
-constexpr int kAtbRows = 64;
-constexpr int kAtbBlocks = 256;
+// Per-wave partial gradients: [W2 | b2 | u | c0] (5249 floats, the parameter
+// layout from W2 on) and [W1 | b1 | Wp] (1600 floats, the layout up to W2).
+constexpr int kPart2 = kK2 * kH + kH + kH + 1;
+constexpr int kPart1 = kF * kH + kH + kH * kMsg;
+static_assert(kPart1 == kOffW2 && kOffW2 + kPart2 == kNParams, "partial layouts");
 
-template <int KL, int KR, int N>
-__global__ __launch_bounds__(256) void k_atb(int64_t n, const uint16_t* __restrict__ Al,
-                                             const uint16_t* __restrict__ Ar, const float* __restrict__ B, float* part) {
-    constexpr int K1 = KL + KR + 1;
-    constexpr int OUT = K1 * N;
-    constexpr int PER = (OUT + 255) / 256;
-    __shared__ float sa[kAtbRows][K1];
-    __shared__ float sb[kAtbRows][N];
-    float acc[PER];
+// The layer-2 part of one tile for the backward: recomputes the forward,
+// returns dO (per row 4kq+q, 0 beyond n), dY2 (D layout) and writes dY2 as
+// BF16 into Ds[row][unit]; also the squared error of rows in this lane (li 0).
+__device__ __forceinline__ void tile_bwd_top(const NetIn& I, const NetW& W, const uint16_t* __restrict__ M,
+                                             const double* __restrict__ zt, int64_t row0, int li, int kq,
+                                             uint16_t (*Hs)[kHS], uint16_t (*Ds)[kHS], f32x4 y[4], float h[4][4],
+                                             float h2[4][4], float dO[4], float dy[4][4], double* sq) {
+    f32x4 y2[4];
+    float o[4];
+    tile_layer1(I, W, row0, li, kq, y, h, Hs);
+    wave_sync_lds();
+    tile_layer2(I, W, M, row0, li, kq, Hs, y2);
+    tile_readout(I, y2, li, o, h2);
+    const double lo = I.stats[1], hi = I.stats[2];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] = 0.f;
-    const int64_t per_block = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * per_block;
-    const int64_t r_end = min(n, r_begin + per_block);
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += kAtbRows) {
-        const int rows = static_cast<int>(min<int64_t>(kAtbRows, r_end - r0));
-        for (int idx = threadIdx.x; idx < kAtbRows * K1; idx += 256) {
-            const int rr = idx / K1, k = idx % K1;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + 4 * kq + q;
+        dO[q] = 0.f;
+        if (r < I.n) {
+            const double sg = 1.0 / (1.0 + exp(-static_cast<double>(o[q])));
+            const double diff = lo + (hi - lo) * sg - zt[r];
+            const double wv = I.rel_floor > 0.0 ? 1.0 / ((zt[r] + I.rel_floor) * (zt[r] + I.rel_floor)) : 1.0;
+            dO[q] = static_cast<float>(2.0 / static_cast<double>(I.n) * wv * diff * (hi - lo) * sg * (1.0 - sg));
+            if (li == 0) *sq += wv * diff * diff;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float uj = I.p[kOffU + 16 * t + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dy[t][q] = y2[t][q] > 0.f ? dO[q] * uj : 0.f;
+            Ds[4 * kq + q][16 * t + li] = f2bf(dy[t][q]);
+        }
+    }
+    wave_sync_lds();
+}
+
+// Layer 2's gradients ([H1 | M]^T dY2, sums of dY2, H2^T dO, sum dO, the
+// loss) and dM = dY2 W2[64:80]^T (FP32 [n][16]).
+__global__ __launch_bounds__(kBlock) void k_net_bwd2(NetIn I, const uint16_t* __restrict__ M,
+                                                     const double* __restrict__ zt, float* __restrict__ dM,
+                                                     float* __restrict__ part, double* __restrict__ loss_part) {
+    __shared__ NetW W;
+    __shared__ NetWB WB;
+    __shared__ uint16_t Hs[kWavesPerBlock][16][kHS];
+    __shared__ uint16_t Ds[kWavesPerBlock][16][kHS];
+    load_weights(I.p, W);
+    load_weights_bwd(I.p, WB);
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    f32x4 gW2[5][4];
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) gW2[m][t] = kZero4;
+    float gb2[4] = {0.f, 0.f, 0.f, 0.f}, gu[4] = {0.f, 0.f, 0.f, 0.f}, gc0 = 0.f;
+    double sq = 0.0;
+    const int64_t tiles = (I.n + 15) / 16;
+    for (int64_t tt = wave; tt < tiles; tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+        const int64_t row0 = tt * 16;
+        f32x4 y[4];
+        float h[4][4], h2[4][4], dO[4], dy[4][4];
+        tile_bwd_top(I, W, M, zt, row0, li, kq, Hs[wid], Ds[wid], y, h, h2, dO, dy, &sq);
+        bf16x4 bdy[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            bdy[t] = pack4(dy[t][0], dy[t][1], dy[t][2], dy[t][3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                gb2[t] += dy[t][q];
+                gu[t] += dO[q] * h2[t][q];
+            }
+        }
+        if (li == 0) gc0 += dO[0] + dO[1] + dO[2] + dO[3];
+        // [H1 | M]^T dY2: A = H1^T per 16-unit block (D layout of layer 1), then M^T
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const bf16x4 a = pack4(h[m][0], h[m][1], h[m][2], h[m][3]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) gW2[m][t] = mfma16(a, bdy[t], gW2[m][t]);
+        }
+        bf16x4 am;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) am[q] = static_cast<short>(M[min(row0 + 4 * kq + q, I.n - 1) * kMsg + li]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) gW2[4][t] = mfma16(am, bdy[t], gW2[4][t]);
+        // dM = dY2 W2[64:80]^T: A = dY2 from Ds, B[k = unit][n = j] = W2[64 + j][unit]
+        f32x4 dm = kZero4;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            dm = mfma16(lds4(&Ds[wid][li][16 * ks + 4 * kq]), lds4(&WB.w2r[kH + li][16 * ks + 4 * kq]), dm);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = row0 + 4 * kq + q;
+            if (r < I.n) dM[r * kMsg + li] = dm[q];
+        }
+        wave_sync_lds();
+    }
+    float* pw = part + wave * kPart2;
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pw[(16 * m + 4 * kq + q) * kH + 16 * t + li] = gW2[m][t][q];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        gb2[t] += __shfl_xor(gb2[t], 16, 64);
+        gb2[t] += __shfl_xor(gb2[t], 32, 64);
+        gu[t] += __shfl_xor(gu[t], 16, 64);
+        gu[t] += __shfl_xor(gu[t], 32, 64);
+        if (kq == 0) {
+            pw[kK2 * kH + 16 * t + li] = gb2[t];
+            pw[kK2 * kH + kH + 16 * t + li] = gu[t];
+        }
+    }
+    gc0 += __shfl_xor(gc0, 16, 64);
+    gc0 += __shfl_xor(gc0, 32, 64);
+    sq += __shfl_xor(sq, 16, 64);
+    sq += __shfl_xor(sq, 32, 64);
+    if (lane == 0) {
+        pw[kK2 * kH + 2 * kH] = gc0;
+        loss_part[wave] = sq;
+    }
+}
+
+// Layer 1's gradients: dH1 = dY2 W2[0:64]^T + dP Wp^T, dY1 = dH1 [y > 0];
+// X0^T dY1, sums of dY1, H1^T dP.
+__global__ __launch_bounds__(kBlock) void k_net_bwd1(NetIn I, const uint16_t* __restrict__ M,
+                                                     const double* __restrict__ zt, const float* __restrict__ dP,
+                                                     float* __restrict__ part) {
+    __shared__ NetW W;
+    __shared__ NetWB WB;
+    __shared__ uint16_t Hs[kWavesPerBlock][16][kHS];
+    __shared__ uint16_t Ds[kWavesPerBlock][16][kHS];
+    load_weights(I.p, W);
+    load_weights_bwd(I.p, WB);
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    f32x4 gW1[4], gWp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) gW1[t] = gWp[t] = kZero4;
+    float gb1[4] = {0.f, 0.f, 0.f, 0.f};
+    double sq = 0.0;
+    const int64_t tiles = (I.n + 15) / 16;
+    for (int64_t tt = wave; tt < tiles; tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+        const int64_t row0 = tt * 16;
+        f32x4 y[4];
+        float h[4][4], h2[4][4], dO[4], dy[4][4];
+        tile_bwd_top(I, W, M, zt, row0, li, kq, Hs[wid], Ds[wid], y, h, h2, dO, dy, &sq);
+        // dH1: A = dY2 (Ds) with B[k = c][n = m] = W2[m][c]; then A = dP with B[k = j][n = m] = Wp[m][j]
+        f32x4 dh[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dh[t] = kZero4;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x4 a = lds4(&Ds[wid][li][16 * ks + 4 * kq]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dh[t] = mfma16(a, lds4(&WB.w2r[16 * t + li][16 * ks + 4 * kq]), dh[t]);
+        }
+        const int64_t r = min(row0 + li, I.n - 1);
+        const float* pr = dP + r * kMsg + 4 * kq;
+        const bf16x4 adp = pack4(pr[0], pr[1], pr[2], pr[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dh[t] = mfma16(adp, lds4(&WB.wpr[16 * t + li][4 * kq]), dh[t]);
+        // dY1 (D layout), zero beyond n
+        float dy1[4][4];
+        bool live[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) live[q] = row0 + 4 * kq + q < I.n;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dy1[t][q] = live[q] && y[t][q] > 0.f ? dh[t][q] : 0.f;
+                gb1[t] += dy1[t][q];
+            }
+        // X0^T dY1: A[m = feature li][k = row 4kq+q] (features 8..15 are zero)
+        float xf[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float f[8];
+            features8(I, min(row0 + 4 * kq + q, I.n - 1), f);
             float v = 0.f;
-            if (rr < rows) {
-                const int64_t r = r0 + rr;
-                if (k < KL) v = bf2f(Al[r * KL + k]);
-                else if (k < KL + KR) v = bf2f(Ar[r * KR + (k - KL)]);
-                else v = 1.0f;
-            }
-            sa[rr][k] = v;
-        }
-        for (int idx = threadIdx.x; idx < kAtbRows * N; idx += 256) {
-            const int rr = idx / N, j = idx % N;
-            sb[rr][j] = rr < rows ? B[(r0 + rr) * N + j] : 0.f;
-        }
-        __syncthreads();
-        for (int rr = 0; rr < rows; ++rr) {
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int o = threadIdx.x + q * 256;
-                if (o < OUT) acc[q] += sa[rr][o / N] * sb[rr][o % N];
-            }
+            for (int c = 0; c < 8; ++c) v = li == c ? f[c] : v;
+            xf[q] = v;
         }
-        __syncthreads();
+        const bf16x4 ax = pack4(xf[0], xf[1], xf[2], xf[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) gW1[t] = mfma16(ax, pack4(dy1[t][0], dy1[t][1], dy1[t][2], dy1[t][3]), gW1[t]);
+        // H1^T dP: B[k = row 4kq+q][n = j = li]
+        float dpq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dpq[q] = live[q] ? dP[(row0 + 4 * kq + q) * kMsg + li] : 0.f;
+        const bf16x4 bdp = pack4(dpq[0], dpq[1], dpq[2], dpq[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gWp[m] = mfma16(pack4(h[m][0], h[m][1], h[m][2], h[m][3]), bdp, gWp[m]);
+        wave_sync_lds();
+    }
+    float* pw = part + wave * kPart1;
+    if (kq < 2)  // rows 4kq+q < 8 of X0^T dY1 are the parameters of W1
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pw[(4 * kq + q) * kH + 16 * t + li] = gW1[t][q];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        gb1[t] += __shfl_xor(gb1[t], 16, 64);
+        gb1[t] += __shfl_xor(gb1[t], 32, 64);
+        if (kq == 0) pw[kF * kH + 16 * t + li] = gb1[t];
     }
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int o = threadIdx.x + q * 256;
-        if (o < OUT) part[static_cast<int64_t>(blockIdx.x) * OUT + o] = acc[q];
-    }
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pw[kF * kH + kH + (16 * m + 4 * kq + q) * kMsg + li] = gWp[m][q];
 }
 
-__global__ void k_atb_final(int nb, int out_count, const float* __restrict__ part, float* grad) {
+// grad[o] = sum over waves, in wave order, of the partials; loss = sum of
+// squared errors / n
+__global__ void k_net_grad_final(int waves, int64_t n, const float* __restrict__ part1,
+                                 const float* __restrict__ part2, const double* __restrict__ loss_part, float* grad,
+                                 float* loss) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= out_count) return;
-    float t = 0.f;
-    for (int b = 0; b < nb; ++b) t += part[static_cast<int64_t>(b) * out_count + o];
-    grad[o] = t;
-}
-
-__global__ void k_loss_final(int nb, int64_t n, const double* __restrict__ part, float* loss) {
-    if (threadIdx.x != 0) return;
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part[b];
-    *loss = static_cast<float>(t / static_cast<double>(n));
+    if (o < kNParams) {
+        float t = 0.f;
+        if (o < kOffW2)
+            for (int w = 0; w < waves; ++w) t += part1[static_cast<int64_t>(w) * kPart1 + o];
+        else
+            for (int w = 0; w < waves; ++w) t += part2[static_cast<int64_t>(w) * kPart2 + (o - kOffW2)];
+        grad[o] = t;
+    }
+    if (o == 0 && loss) {
+        double t = 0.0;
+        for (int w = 0; w < waves; ++w) t += loss_part[w];
+        *loss = static_cast<float>(t / static_cast<double>(n));
+    }
 }
 
 // ------------------------------------------------------- weights and Adam
-__global__ void k_weights_bf16(const float* __restrict__ p, uint16_t* w1, uint16_t* w2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 16 * kH) w1[i] = f2bf(p[kOffW1 + i]);
-    if (i < 128 * kH) w2[i] = f2bf(p[kOffW2 + i]);
-}
-
 __global__ void k_adam(int count, float* p, const float* __restrict__ g, float* m, float* v, float lr, float b1,
                        float b2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -563,12 +855,12 @@ __global__ __launch_bounds__(kBlock) void k_fj_step_heavy(TileView tv, const dou
     }
 }
 
+
 // ---------------------------------------------------------------- layout
 struct NetLayout {
-    double* stats_part; double* stats; double* rs; double* din; double* partial; float* invd;
-    uint16_t* X0; uint16_t* M0; uint16_t* H1; uint16_t* M1; uint16_t* H2;
-    float* o; double* z0; float* dout; float* dY2; uint16_t* dY2b; float* dA2; float* dY1;
-    float* atb_part; double* loss_part; float* grad; uint16_t* w1b; uint16_t* w2b;
+    double* stats_part; double* stats; float* rs; float* s32; float* invd; float* cpart;
+    uint16_t* P; uint16_t* M;
+    float* dM; float* dP; float* part1; float* part2; double* loss_part; float* grad;
 };
 
 constexpr int kStatBlocks = 256;
@@ -578,121 +870,76 @@ NetLayout carve_net(Carver& cv, const fj_graph* g, bool training) {
     const int64_t n = g->n;
     L.stats_part = cv.take<double>(3 * kStatBlocks);
     L.stats = cv.take<double>(4);
-    L.rs = cv.take<double>(n);
-    L.din = cv.take<double>(n);
-    L.partial = cv.take<double>(std::max(g->tiles_a.nchunks, g->tiles_t.nchunks) + 1);
+    L.rs = cv.take<float>(n);
+    L.s32 = cv.take<float>(n);
     L.invd = cv.take<float>(n);
-    L.X0 = cv.take<uint16_t>(n * kF);
-    L.M0 = cv.take<uint16_t>(n * kF);
-    L.H1 = cv.take<uint16_t>(n * kH);
-    L.M1 = cv.take<uint16_t>(n * kH);
-    L.w1b = cv.take<uint16_t>(16 * kH);
-    L.w2b = cv.take<uint16_t>(128 * kH);
-    L.o = cv.take<float>(n);
+    L.cpart = cv.take<float>((g->tiles_a.nchunks + 1) * kMsg);
+    L.P = cv.take<uint16_t>(n * kMsg);
+    L.M = cv.take<uint16_t>(n * kMsg);
     if (training) {
-        L.H2 = cv.take<uint16_t>(n * kH);
-        L.z0 = cv.take<double>(n);
-        L.dout = cv.take<float>(n);
-        L.dY2 = cv.take<float>(n * kH);
-        L.dY2b = cv.take<uint16_t>(n * kH);
-        L.dA2 = cv.take<float>(n * 128);
-        L.dY1 = cv.take<float>(n * kH);
-        L.atb_part = cv.take<float>(static_cast<int64_t>(kAtbBlocks) * 129 * kH);
-        L.loss_part = cv.take<double>(waves_to_blocks(n) + 1);
+        const int64_t waves = static_cast<int64_t>(bwd_blocks(n)) * kWavesPerBlock;
+        L.dM = cv.take<float>(n * kMsg);
+        L.dP = cv.take<float>(n * kMsg);
+        L.part1 = cv.take<float>(waves * kPart1);
+        L.part2 = cv.take<float>(waves * kPart2);
+        L.loss_part = cv.take<double>(waves);
         L.grad = cv.take<float>(kNParams + 3);
     }
     return L;
 }
 
-// forward up to (and including) layer 2; training keeps H2 and o
+// the forward up to the message M = nbr(P); then z0 unless training
 fj_status net_forward(const fj_graph* g, const double* s, const float* params, double* z0, const NetLayout& L,
                       bool training, hipStream_t st) {
     const int64_t n = g->n;
     const int bs = 256;
-    hipLaunchKernelGGL(k_weights_bf16, dim3(g1d(128 * kH, 256)), dim3(256), 0, st, params, L.w1b, L.w2b);
-    hipLaunchKernelGGL(k_s_stats, dim3(kStatBlocks), dim3(256), 0, st, n, s, L.stats_part);
-    hipLaunchKernelGGL(k_s_stats_final, dim3(1), dim3(64), 0, st, kStatBlocks, n, L.stats_part, L.stats);
-    {   // neighbour sum of s over CSR(A)
-        TileView tv = tile_view_all(g->tiles_a);
-        hipLaunchKernelGGL(k_rowsum_tiles<0>, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0, st, tv,
-                           g->row_ptr, g->col, g->w, s, L.partial, L.rs);
-        if (tv.h1 > tv.h0)
-            hipLaunchKernelGGL(k_rowsum_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv,
-                               L.partial, L.rs);
-    }
-    {   // in-degree: row sums of CSR(A^T)
-        TileView tv = tile_view_all(g->tiles_t);
-        hipLaunchKernelGGL(k_rowsum_tiles<1>, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0, st, tv,
-                           g->t_row_ptr, g->t_col, g->t_w, static_cast<const double*>(nullptr), L.partial, L.din);
-        if (tv.h1 > tv.h0)
-            hipLaunchKernelGGL(k_rowsum_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv,
-                               L.partial, L.din);
-    }
-    hipLaunchKernelGGL(k_inv_deg, dim3(g1d(n, bs)), dim3(bs), 0, st, n, g->opd, L.invd);
-    hipLaunchKernelGGL(k_features, dim3(g1d(n, bs)), dim3(bs), 0, st, n, s, L.rs, g->opd, L.din, L.stats, L.X0);
+    hipLaunchKernelGGL(k_s_prep, dim3(kStatBlocks), dim3(256), 0, st, n, s, g->opd, L.stats_part, L.s32, L.invd);
+    hipLaunchKernelGGL(k_s_final, dim3(1), dim3(64), 0, st, kStatBlocks, n, L.stats_part, L.stats);
     const TileView ta = tile_view_all(g->tiles_a);
-    hipLaunchKernelGGL(k_agg_rows8, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
-                       g->w, L.invd, L.X0, L.M0);
-    if (ta.h1 > ta.h0)
-        hipLaunchKernelGGL(k_agg_heavy<kF>, dim3(ta.h1 - ta.h0), dim3(1024), 0, st, ta, g->row_ptr, g->col, g->w,
-                           L.invd, L.X0, L.M0);
-    const unsigned nb_gemm = stride_blocks(g1d(n, 16), 8);
-    hipLaunchKernelGGL((k_gemm<kF, kF, kH, 0>), dim3(nb_gemm), dim3(kBlock), 0, st, n, L.X0, L.M0, L.w1b,
-                       params + kOffB1, params + kOffU, params + kOffC0, L.stats, L.H1, static_cast<float*>(nullptr),
-                       static_cast<float*>(nullptr), static_cast<double*>(nullptr));
-    hipLaunchKernelGGL(k_agg_rows64, dim3(stride_blocks(n)), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w,
-                       L.invd, L.H1, L.M1);
-    if (ta.h1 > ta.h0)
-        hipLaunchKernelGGL(k_agg_heavy<kH>, dim3(ta.h1 - ta.h0), dim3(1024), 0, st, ta, g->row_ptr, g->col, g->w,
-                           L.invd, L.H1, L.M1);
-    if (training)
-        hipLaunchKernelGGL((k_gemm<kH, kH, kH, 1>), dim3(nb_gemm), dim3(kBlock), 0, st, n, L.H1, L.M1, L.w2b,
-                           params + kOffB2, params + kOffU, params + kOffC0, L.stats, L.H2,
-                           static_cast<float*>(nullptr), L.o, z0);
-    else
-        hipLaunchKernelGGL((k_gemm<kH, kH, kH, 2>), dim3(nb_gemm), dim3(kBlock), 0, st, n, L.H1, L.M1, L.w2b,
-                           params + kOffB2, params + kOffU, params + kOffC0, L.stats,
-                           static_cast<uint16_t*>(nullptr), static_cast<float*>(nullptr), L.o, z0);
+    // layer 1's message: the neighbour sum of s over CSR(A)
+    hipLaunchKernelGGL(k_nbr_rows, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w,
+                       L.s32, L.rs);
+    if (ta.h1 > ta.h0) {
+        hipLaunchKernelGGL(k_nbr_chunks, dim3(waves_to_blocks(ta.nchunks)), dim3(kBlock), 0, st, ta, g->col, g->w,
+                           L.s32, L.cpart);
+        hipLaunchKernelGGL(k_nbr_combine, dim3(waves_to_blocks(ta.h1 - ta.h0)), dim3(kBlock), 0, st, ta, L.cpart,
+                           L.rs);
+    }
+    const NetIn I{n, s, L.rs, g->opd, L.stats, params, 0.0};
+    hipLaunchKernelGGL(k_net_l1, dim3(fwd_blocks(n)), dim3(kBlock), 0, st, I, L.P);
+    // layer 2's message
+    hipLaunchKernelGGL(k_agg_rows16, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
+                       g->w, L.invd, L.P, L.M);
+    if (ta.h1 > ta.h0) {
+        hipLaunchKernelGGL(k_agg16_chunks, dim3(waves_to_blocks(ta.nchunks)), dim3(kBlock), 0, st, ta, g->col, g->w,
+                           L.P, L.cpart);
+        hipLaunchKernelGGL(k_agg16_combine, dim3(waves_to_blocks(ta.h1 - ta.h0)), dim3(kBlock), 0, st, ta, L.cpart,
+                           L.invd, L.M);
+    }
+    if (!training) hipLaunchKernelGGL(k_net_l2, dim3(fwd_blocks(n)), dim3(kBlock), 0, st, I, L.M, z0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "warm-start forward");
     return FJ_OK;
 }
 
-fj_status net_grad(const fj_graph* g, const double* s, const double* zt, const float* params, const NetLayout& L,
-                   float* grad, float* loss, hipStream_t st) {
+fj_status net_grad(const fj_graph* g, const double* s, const double* zt, const float* params, double rel_floor,
+                   const NetLayout& L, float* grad, float* loss, hipStream_t st) {
     const int64_t n = g->n;
-    fj_status rc = net_forward(g, s, params, L.z0, L, true, st);
+    fj_status rc = net_forward(g, s, params, nullptr, L, true, st);
     if (rc) return rc;
-    const unsigned nbw = waves_to_blocks(n);
-    hipLaunchKernelGGL(k_readout_bwd, dim3(nbw), dim3(kBlock), 0, st, n, L.z0, zt, L.o, L.stats, params + kOffU,
-                       L.H2, L.dout, L.dY2, L.dY2b, L.loss_part);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, static_cast<int>(nbw), n, L.loss_part, loss);
-    // du, dc0 = [H2 | 1]^T do
-    hipLaunchKernelGGL((k_atb<kH, 0, 1>), dim3(kAtbBlocks), dim3(256), 0, st, n, L.H2,
-                       static_cast<const uint16_t*>(nullptr), L.dout, L.atb_part);
-    hipLaunchKernelGGL(k_atb_final, dim3(1), dim3(128), 0, st, kAtbBlocks, kH + 1, L.atb_part, grad + kOffU);
-    // dW2, db2 = [H1 | M1 | 1]^T dY2
-    hipLaunchKernelGGL((k_atb<kH, kH, kH>), dim3(kAtbBlocks), dim3(256), 0, st, n, L.H1, L.M1, L.dY2, L.atb_part);
-    hipLaunchKernelGGL(k_atb_final, dim3(g1d(129 * kH, 256)), dim3(256), 0, st, kAtbBlocks, 129 * kH, L.atb_part,
-                       grad + kOffW2);
-    // dA2 = dY2 W2^T (MFMA; W2 read as [N=128][K=64])
-    const unsigned nb_gemm = stride_blocks(g1d(n, 16), 8);
-    hipLaunchKernelGGL((k_gemm<kH, 0, 128, 3>), dim3(nb_gemm), dim3(kBlock), 0, st, n, L.dY2b,
-                       static_cast<const uint16_t*>(nullptr), L.w2b, static_cast<const float*>(nullptr),
-                       static_cast<const float*>(nullptr), static_cast<const float*>(nullptr),
-                       static_cast<const double*>(nullptr), static_cast<uint16_t*>(nullptr), L.dA2,
-                       static_cast<float*>(nullptr), static_cast<double*>(nullptr));
-    // dY1 = (dA2[:, :64] + nbr^T(dA2[:, 64:])) * [H1 > 0]
-    hipLaunchKernelGGL(k_aggT_light, dim3(g1d(n * 64, kBlock)), dim3(kBlock), 0, st, n, g->t_row_ptr, g->t_col,
-                       g->t_w, L.invd, L.dA2, L.H1, L.dY1);
+    const NetIn I{n, s, L.rs, g->opd, L.stats, params, rel_floor};
+    const unsigned nb = bwd_blocks(n);
+    hipLaunchKernelGGL(k_net_bwd2, dim3(nb), dim3(kBlock), 0, st, I, L.M, zt, L.dM, L.part2, L.loss_part);
+    // dP = nbr^T(dM) over CSR(A^T)
+    hipLaunchKernelGGL(k_aggT16_light, dim3(g1d(n * kMsg, kBlock)), dim3(kBlock), 0, st, n, g->t_row_ptr, g->t_col,
+                       g->t_w, L.invd, L.dM, L.dP);
     const TileView tt = tile_view_all(g->tiles_t);
     if (tt.h1 > tt.h0)
-        hipLaunchKernelGGL(k_aggT_heavy, dim3(tt.h1 - tt.h0), dim3(1024), 0, st, tt, g->t_row_ptr, g->t_col, g->t_w,
-                           L.invd, L.dA2, L.H1, L.dY1);
-    // dW1, db1 = [X0 | M0 | 1]^T dY1
-    hipLaunchKernelGGL((k_atb<kF, kF, kH>), dim3(kAtbBlocks), dim3(256), 0, st, n, L.X0, L.M0, L.dY1, L.atb_part);
-    hipLaunchKernelGGL(k_atb_final, dim3(g1d(17 * kH, 256)), dim3(256), 0, st, kAtbBlocks, 17 * kH, L.atb_part,
-                       grad + kOffW1);
+        hipLaunchKernelGGL(k_aggT16_heavy, dim3(tt.h1 - tt.h0), dim3(1024), 0, st, tt, g->t_row_ptr, g->t_col,
+                           g->t_w, L.invd, L.dM, L.dP);
+    hipLaunchKernelGGL(k_net_bwd1, dim3(nb), dim3(kBlock), 0, st, I, L.M, zt, L.dP, L.part1);
+    hipLaunchKernelGGL(k_net_grad_final, dim3(g1d(kNParams, 256)), dim3(256), 0, st,
+                       static_cast<int>(nb * kWavesPerBlock), n, L.part1, L.part2, L.loss_part, grad, loss);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "warm-start backward");
     return FJ_OK;
@@ -738,31 +985,32 @@ extern "C" fj_status fj_wsnet_forward(const fj_graph* g, const double* s, const 
 }
 
 extern "C" fj_status fj_wsnet_grad(const fj_graph* g, const double* s, const double* z_target, const float* params,
-                                   float* grad, float* loss, void* ws, size_t ws_bytes, void* stream) {
+                                   double rel_floor, float* grad, float* loss, void* ws, size_t ws_bytes,
+                                   void* stream) {
     fj_status rc = net_args_ok(g, s, params, ws, ws_bytes, true);
     if (rc) return rc;
-    if (!z_target || !grad || !loss) {
-        set_error("fj_wsnet_grad: null argument");
+    if (!z_target || !grad || !loss || !std::isfinite(rel_floor)) {
+        set_error("fj_wsnet_grad: null argument or non-finite rel_floor");
         return FJ_ERR_INVALID_ARGUMENT;
     }
     Carver cv(ws);
     NetLayout L = carve_net(cv, g, true);
-    return net_grad(g, s, z_target, params, L, grad, loss, static_cast<hipStream_t>(stream));
+    return net_grad(g, s, z_target, params, rel_floor, L, grad, loss, static_cast<hipStream_t>(stream));
 }
 
 extern "C" fj_status fj_wsnet_train_step(const fj_graph* g, const double* s, const double* z_target, float* params,
-                                         float* adam_m, float* adam_v, int32_t step, float lr, float* loss, void* ws,
-                                         size_t ws_bytes, void* stream) {
+                                         float* adam_m, float* adam_v, int32_t step, float lr, double rel_floor,
+                                         float* loss, void* ws, size_t ws_bytes, void* stream) {
     fj_status rc = net_args_ok(g, s, params, ws, ws_bytes, true);
     if (rc) return rc;
-    if (!z_target || !adam_m || !adam_v || !loss || step < 1 || !(lr > 0.f)) {
+    if (!z_target || !adam_m || !adam_v || !loss || step < 1 || !(lr > 0.f) || !std::isfinite(rel_floor)) {
         set_error("fj_wsnet_train_step: bad argument");
         return FJ_ERR_INVALID_ARGUMENT;
     }
     Carver cv(ws);
     NetLayout L = carve_net(cv, g, true);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    rc = net_grad(g, s, z_target, params, L, L.grad, loss, st);
+    rc = net_grad(g, s, z_target, params, rel_floor, L, L.grad, loss, st);
     if (rc) return rc;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - powf(b1, static_cast<float>(step)), c2 = 1.f - powf(b2, static_cast<float>(step));
@@ -808,3 +1056,4 @@ extern "C" fj_status fj_jacobi_steps(const fj_graph* g, const double* s, double*
     if (e != hipSuccess) return hip_fail(e, "jacobi");
     return FJ_OK;
 }
+

@@ -608,9 +608,9 @@ def _net_lib():
         L.fj_wsnet_workspace_bytes.restype = sz
         L.fj_wsnet_forward.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.fj_wsnet_forward.restype = i32
-        L.fj_wsnet_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.fj_wsnet_grad.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, sz, vp]
         L.fj_wsnet_grad.restype = i32
-        L.fj_wsnet_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, fl, vp, vp, sz, vp]
+        L.fj_wsnet_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, fl, ctypes.c_double, vp, vp, sz, vp]
         L.fj_wsnet_train_step.restype = i32
         L.fj_jacobi_workspace_bytes.argtypes = [vp]
         L.fj_jacobi_workspace_bytes.restype = sz
@@ -647,22 +647,23 @@ def wsnet_forward(graph: Graph, s: torch.Tensor, params: torch.Tensor, out: Opti
     return z0
 
 
-def wsnet_grad(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, params: torch.Tensor):
-    """(loss, grad) of the mean squared error of z0 against z_target."""
+def wsnet_grad(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, params: torch.Tensor, rel_floor: float = 0.0):
+    """(loss, grad) of the mean over nodes of w (z0 - z_target)^2, with
+    w = 1 / (z_target + rel_floor)^2 when rel_floor > 0, else 1."""
     n = graph.n
     _dev_ptr(z_target, torch.float64, n, "z_target")
     grad = torch.empty(wsnet_param_count(), dtype=torch.float32, device=graph.device)
     loss = torch.empty(1, dtype=torch.float32, device=graph.device)
     ws = _net_ws(graph, True)
     _check(_net_lib().fj_wsnet_grad(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(z_target.data_ptr()),
-                                    ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                    ctypes.c_void_p(params.data_ptr()), float(rel_floor), ctypes.c_void_p(grad.data_ptr()),
                                     ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                     _stream()))
     return loss, grad
 
 
 def wsnet_train_step(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, params: torch.Tensor,
-                     m: torch.Tensor, v: torch.Tensor, step: int, lr: float) -> torch.Tensor:
+                     m: torch.Tensor, v: torch.Tensor, step: int, lr: float, rel_floor: float = 0.0) -> torch.Tensor:
     """One Adam step in place on params (m, v: moment buffers).  Returns the
     loss (device scalar) of the forward pass before the step."""
     loss = torch.empty(1, dtype=torch.float32, device=graph.device)
@@ -670,7 +671,7 @@ def wsnet_train_step(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, para
     _check(_net_lib().fj_wsnet_train_step(graph.handle, ctypes.c_void_p(s.data_ptr()),
                                           ctypes.c_void_p(z_target.data_ptr()), ctypes.c_void_p(params.data_ptr()),
                                           ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(step),
-                                          float(lr), ctypes.c_void_p(loss.data_ptr()),
+                                          float(lr), float(rel_floor), ctypes.c_void_p(loss.data_ptr()),
                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return loss
 

@@ -76,7 +76,12 @@ def test_gradient_matches_finite_differences():
     zt = synth.opinions(g.n, "uniform", 10)
     p = mpnn.init_params(11)
     p[mpnn.N_PARAMS - 1] = 0.3  # c0 away from a symmetric point
-    loss, grad = mpnn.loss_and_grad(g, s, p, zt)
+    check_fd(g, s, p, zt, 0.0)
+    check_fd(g, s, p, zt, 0.05)
+
+
+def check_fd(g, s, p, zt, rel_floor):
+    loss, grad = mpnn.loss_and_grad(g, s, p, zt, rel_floor)
     rng = np.random.default_rng(12)
     # entries of every block, c0 included
     idx = np.concatenate([rng.integers(a, b, 12) for a, b in mpnn.offsets().values()] + [[mpnn.N_PARAMS - 1]])
@@ -84,7 +89,18 @@ def test_gradient_matches_finite_differences():
     for i in idx:
         e = np.zeros_like(p)
         e[i] = h
-        lp, _ = mpnn.loss_and_grad(g, s, p + e, zt)
-        lm, _ = mpnn.loss_and_grad(g, s, p - e, zt)
+        lp, _ = mpnn.loss_and_grad(g, s, p + e, zt, rel_floor)
+        lm, _ = mpnn.loss_and_grad(g, s, p - e, zt, rel_floor)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grad[i]) <= 1e-6 * max(1e-3, abs(fd)), (i, fd, grad[i])
+
+
+def test_relative_weights_are_the_definition():
+    """The weighted loss equals the mean of ((z0 - z)/(z + floor))^2 written out."""
+    g = graphs.random_graph(20, 0.2, 13, directed=True, weighted=True)
+    s = synth.opinions(g.n, "bimodal", 14)
+    zt = synth.opinions(g.n, "uniform", 15)
+    p = mpnn.init_params(16)
+    z0 = mpnn.forward(g, s, p)["z0"]
+    want = sum(((a - b) / (b + 0.01)) ** 2 for a, b in zip(z0, zt)) / g.n
+    assert abs(mpnn.loss_and_grad(g, s, p, zt, 0.01)[0] - want) <= 1e-12 * want
