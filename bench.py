@@ -54,7 +54,7 @@ def make_input(wl):
     return g, s
 
 
-def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
+def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False, frontier=False):
     """Bytes the iteration kernel must move, without cache reuse.
 
     Colour-class sweep (pull form): per row scanned 28 B (row_ptr 4, s' 8,
@@ -68,7 +68,9 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
     is not counted.
     Push round: per node scanned 8 B (r, h), per push 44 B (row_ptr 8, r
     exchange 8, 1/(1+d) 4+8, zhat' RMW 16), per arc 12 B (col 4 + residual
-    atomic RMW 8), +4 B with weights."""
+    atomic RMW 8), +4 B with weights.  Over a frontier queue no node is
+    scanned; a popped node reads its queue entry, clears its queue flag and
+    reads r and h (16 B), counted per push."""
     if schedule == "sor" or gather_rounds:
         arcs = stats["edge_visits"]
         mirror_arcs = stats["mirror_edge_visits"] if schedule == "sor" else stats.get("mirror_rounds", 0) * nnz
@@ -77,6 +79,8 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False):
         return (28 * stats["rounds"] * n + 8 * skipped + 20 * stats["pushes"] + 4 * arcs + gather
                 + (4 * arcs if weighted else 0))
     per_arc = 16 if weighted else 12
+    if frontier:
+        return 60 * stats["pushes"] + per_arc * stats["edge_visits"]
     return 8 * stats["rounds"] * n + 44 * stats["pushes"] + per_arc * stats["edge_visits"]
 
 
@@ -301,6 +305,8 @@ def main():
                     help="also run one plain 512 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--gather-bits", type=int, default=0, choices=[0, 32, 64],
                     help="FP32 sweeps: gather the 32-bit fixed-point copy first (0, 32) or FP64 from the start (64)")
+    ap.add_argument("--push-frontier", action="store_true",
+                    help="push rounds over a frontier queue (atomic scatter of the popped nodes only)")
     ap.add_argument("--push-scatter", action="store_true",
                     help="push schedule: atomic scatter form of the rounds instead of the gather form")
     ap.add_argument("--no-tail-merge", action="store_true",
@@ -366,7 +372,8 @@ def main():
     def step(profile=False):
         zz, st = fj.solve(G, sd, eps=wl["eps"], omega=omega, precision=precision, schedule=args.schedule,
                           out=z, profile=profile, persistent=args.persistent, gather_bits=args.gather_bits,
-                          tail_merge=not args.no_tail_merge, push_scatter=args.push_scatter,
+                          tail_merge=not args.no_tail_merge,
+                          push_scatter="frontier" if args.push_frontier else args.push_scatter,
                           skip_below=args.skip_below, check_every=args.check_every)
         m = fj.metrics(G, sd, zz)
         return st, m
@@ -397,15 +404,18 @@ def main():
         # same step with every launch of the iteration kernel bracketed by HIP
         # events on the library's stream
         stp, _ = step(profile=True)
+        scatter = args.push_scatter or args.push_frontier
         bytes_total = algorithmic_bytes(args.schedule, stp, g.n, g.nnz, g.w is not None,
-                                        gather_rounds=args.schedule == "push" and not args.push_scatter)
+                                        gather_rounds=args.schedule == "push" and not scatter,
+                                        frontier=args.push_frontier)
         launches = max(stp["kernel_launches"], 1)
         avg_ms = stp["kernel_ms"] / launches
         achieved = bytes_total / (stp["kernel_ms"] * 1e-3) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4),
                         traffic=measured_traffic() if args.schedule == "sor" and args.workload == "cl10m" else None,
-                        kernel=("k_sor_class" if args.schedule == "sor" or not args.push_scatter
+                        kernel=("k_sor_class" if args.schedule == "sor" or not scatter
+                                else "k_frontier_small+k_frontier_big" if args.push_frontier
                                 else "k_push_light+k_push_heavy"),
                         algorithmic_bytes_per_launch=int(bytes_total / launches), avg_launch_ms=round(avg_ms, 5),
                         launches=int(stp["kernel_launches"]), kernel_ms=round(stp["kernel_ms"], 3))

@@ -137,10 +137,18 @@ typedef struct {
                                 copy of zhat' until quiet, then FP64; 64 = FP64 from the start.
                                 The copy holds |zhat'| < 2: it is used only when s' = s + c and
                                 the start are below 1.5, otherwise every sweep gathers FP64 */
-    int32_t push_scatter;    /* FJ_SCHED_PUSH: nonzero = every active node scatters omega r/(1+d)
-                                to its in-neighbours with atomics; 0 = the same rounds in gather
-                                form (each row recomputes its residual from the round's start
-                                estimate), used when no row of A exceeds 4095 x 256 arcs */
+    int32_t push_scatter;    /* FJ_SCHED_PUSH: 0 = rounds in gather form (each row recomputes its
+                                residual from the round's start estimate), used when no row of A
+                                exceeds 4095 x 256 arcs; 1 = every node above threshold scatters
+                                omega r/(1+d) to its in-neighbours with atomics, found by a scan
+                                of all nodes per round; 2 = rounds as in 1 while dense, then, once
+                                a batch of check_every rounds averaged fewer than 2% of the nodes
+                                pushing, over a frontier queue (Alg. 1's queue, as the round sets
+                                of the proof of Thm. 5): a round pops only the nodes the previous
+                                round lifted above threshold, appended by wave ballot and prefix
+                                count, nodes bucketed by degree (a wave per 64 nodes, or a block
+                                per node with more than 2048 arcs).  1 and 2 add in a
+                                run-dependent order */
     int32_t no_tail_merge;   /* nonzero: one launch per colour class always.  Otherwise, on an
                                 undirected graph, the trailing classes that each hold under 1% of
                                 the arcs are swept by one launch (a Jacobi step among their rows)
@@ -172,7 +180,8 @@ typedef struct {
     double kernel_ms;     /* profile mode: summed event time of the iteration kernel launches */
     int64_t kernel_launches; /* profile mode: launches timed */
     int32_t num_colours;  /* colour classes swept (SOR), 0 for push */
-    int64_t mirror_rounds; /* SOR sweeps whose light rows gathered the 32-bit fixed-point copy */
+    int64_t mirror_rounds; /* SOR sweeps whose light rows gathered the 32-bit fixed-point copy;
+                              push rounds with push_scatter = 2: rounds that popped a frontier queue */
     int32_t merged_classes; /* colour classes swept together as a merged tail (0: none) */
     int64_t skipped_rows;   /* row visits skipped by bound skipping */
     int64_t skipped_arcs;   /* the arcs of those rows */

@@ -54,10 +54,14 @@ __global__ void k_init_warm(int64_t n, const double* __restrict__ s, const doubl
 // ------------------------------------------------------------ certificate
 // r = s' - (I+L) zhat' in FP64 over CSR(A): r_i = s'_i - (1+d_i) zhat'_i +
 // sum_j a_ij zhat'_j.  Per block: max |r_i| / h_i and the count of rows with
-// |r_i| > h_i (Alg. 3's stopping test).  r_out != NULL also stores fl(r) as
-// the new tracked residual, which resets FP32 drift (Lemma 4 holds for any
-// zhat').  Light tiles finish their rows here; heavy rows leave one partial
-// sum per chunk for k_certify_heavy.
+// |r_i| > h_i (Alg. 3's stopping test).  r_out != NULL also stores r as the
+// new tracked residual, which resets FP32 drift (Lemma 4 holds for any
+// zhat').  In FP32 it is rounded away from zero: the FP32 threshold is the
+// FP64 one rounded down, so a row that fails the FP64 test (|r| > h) then
+// passes the FP32 push test |r32| > h32 however close it lies to h; rounded
+// to nearest, a row within half an ulp of h could round onto h32, never be
+// pushed, and fail every later certificate.  Light tiles finish their rows
+// here; heavy rows leave one partial sum per chunk for k_certify_heavy.
 struct RowOut {
     double ratio;
     int viol;
@@ -71,7 +75,10 @@ __device__ __forceinline__ RowOut certify_row(int64_t i, double sum, const doubl
     double ratio = fabs(ri) / (epsp * (s[i] + c_thr));
     RowOut o{ratio, !(ratio <= 1.0) ? 1 : 0};  // NaN counts as a violation
     if (!isfinite(o.ratio)) o.ratio = INFINITY;
-    if (r_out) r_out[i] = static_cast<T>(ri);
+    if (r_out) {
+        if constexpr (sizeof(T) == 4) r_out[i] = ri >= 0.0 ? __double2float_ru(ri) : __double2float_rd(ri);
+        else r_out[i] = ri;
+    }
     return o;
 }
 
@@ -277,6 +284,244 @@ __global__ __launch_bounds__(kBlock) void k_push_heavy(TileView tv, const int32_
     }
 }
 
+// ------------------------------------------------------- frontier push rounds
+// Alg. 1's queue made concurrent: a round pops every node of the current
+// frontier (the round set S^(i) of the proof of Thm. 5), pushes those above
+// threshold, and the pushes append the nodes they lift above threshold to the
+// next frontier.  Queues are grid-wide arrays of node ids in two degree
+// buckets (scatter rows of CSR(A^T) of at most kBigPush arcs: a wave takes 64
+// queue entries and scatters their arcs together, merge-path balanced;
+// longer: a block per node).  Appends are compacted per wave by ballot and
+// prefix count, one global atomic per bucket per wave step.  inq[v] = 1 while
+// v is queued.  Ordering without fences (a device-scope fence writes back and
+// invalidates the L2 of every XCD on this part): every access here is an
+// atomic performed at the device's coherence point, and each one that must
+// follow another is issued only after the other has returned.  A popped node
+// clears inq, and its read of r depends on the value the clear returned; a
+// push that lifts r_u above h_u tests inq[u] only after its add returned.  So
+// if the add came after the pop's take, the test sees the cleared flag and
+// queues u again; if before, the take collected it.  A node already queued is
+// not queued twice.  With omega < 1 a node whose remaining (1 - omega) r is
+// still above threshold queues itself.
+constexpr int kBigPush = 2048;
+constexpr int kFrontierUnroll = 4;
+// below this fraction of the nodes pushing per round, rounds pop a frontier queue
+constexpr double kFrontierDensity = 0.02;
+
+struct FrontierArgs {
+    int32_t* cur[2];   // this round's queues (bucket 0: small, 1: big)
+    int32_t* nxt[2];   // the next round's
+    const int* cnt_cur;  // [2]
+    int* cnt_nxt;        // [2]
+    int* inq;
+};
+
+__device__ __forceinline__ int push_bucket(const int32_t* __restrict__ t_row_ptr, int u) {
+    return t_row_ptr[u + 1] - t_row_ptr[u] > kBigPush ? 1 : 0;
+}
+
+// wave-uniform: lanes with `want` append u to the next queue of their bucket
+__device__ __forceinline__ void wave_append(bool want, int u, int bucket, const FrontierArgs& F) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const uint64_t m = __ballot(want && bucket == b);
+        if (!m) continue;
+        int base = 0;
+        if (lane_id() == 0) base = atomicAdd(&F.cnt_nxt[b], __popcll(m));
+        base = __shfl(base, 0, 64);
+        if (want && bucket == b) F.nxt[b][base + lanes_below(m)] = u;
+    }
+}
+
+// one arc of a push: r_u += delta; a lift above threshold queues u
+template <typename T>
+__device__ __forceinline__ bool push_arc(int u, T delta, T* r, const T* __restrict__ h, const FrontierArgs& F) {
+    const T old = unsafeAtomicAdd(&r[u], delta);
+    const T hu = h[u];
+    if (!(fabs(old + delta) > hu) || fabs(old) > hu) return false;  // the test waits for the add's return
+    return atomicExch(&F.inq[u], 1) == 0;
+}
+
+// pop v: clear inq, then take its residual if above threshold; returns the
+// push coefficient omega x / (1 + d_v) (0 when v is below threshold) and
+// whether v must queue itself again
+template <typename T>
+__device__ __forceinline__ T pop_node(int v, T* r, const T* __restrict__ h, const T* __restrict__ inv,
+                                      const double* __restrict__ inv64, double* zh, double omega,
+                                      const FrontierArgs& F, bool* requeue) {
+    const int was = atomicExch(&F.inq[v], 0);
+    // a zero that the compiler cannot fold, computed from the returned flag:
+    // the read of r below is issued only after the clear has returned
+    int dep;
+    __asm__ volatile("v_mov_b32 %0, 0 ; after %1" : "=v"(dep) : "v"(was));
+    T* rv = r + v + dep;
+    *requeue = false;
+    const T hv = h[v];
+    if (!(fabs(unsafeAtomicAdd(rv, static_cast<T>(0))) > hv)) return static_cast<T>(0);  // atomic read
+    const T x = atomic_exch(rv, static_cast<T>(0));
+    if (omega != 1.0) {
+        const T rest = static_cast<T>((1.0 - omega) * static_cast<double>(x));
+        const T old = unsafeAtomicAdd(&r[v], rest);
+        if (fabs(old + rest) > hv && !(fabs(old) > hv)) *requeue = atomicExch(&F.inq[v], 1) == 0;
+    }
+    zh[v] += omega * static_cast<double>(x) * inv64[v];
+    return static_cast<T>(omega) * x * inv[v];
+}
+
+// small bucket: a wave per 64 queue entries, grid-stride
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_frontier_small(FrontierArgs F, const int32_t* __restrict__ t_row_ptr,
+                                                           const int32_t* __restrict__ t_col,
+                                                           const float* __restrict__ t_w, T* r,
+                                                           const T* __restrict__ h, const T* __restrict__ inv,
+                                                           const double* __restrict__ inv64, double* zh,
+                                                           double omega, unsigned long long* stats) {
+    __shared__ int s_beg[kWavesPerBlock][64];
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ T s_cf[kWavesPerBlock][64];
+    const int cnt = F.cnt_cur[0];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    unsigned long long pushes = 0, visits = 0;
+    for (int64_t base = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64; base < cnt;
+         base += waves * 64) {
+        const int64_t idx = base + lane;
+        int v = -1;
+        T cf = 0;
+        bool requeue = false;
+        if (idx < cnt) {
+            v = F.cur[0][idx];
+            cf = pop_node<T>(v, r, h, inv, inv64, zh, omega, F, &requeue);
+        }
+        wave_append(requeue, v, 0, F);  // a small node stays small
+        const bool act = cf != static_cast<T>(0);
+        const uint64_t m = __ballot(act);
+        if (m == 0) continue;
+        int beg = 0, deg = 0;
+        if (act) {
+            beg = t_row_ptr[v];
+            deg = t_row_ptr[v + 1] - beg;
+        }
+        const int slot = lanes_below(m);
+        const int na = __popcll(m);
+        const int incl = wave_incl_scan(deg);
+        const int total = __shfl(incl, 63, 64);
+        if (act) {
+            s_beg[wid][slot] = beg;
+            s_pre[wid][slot] = incl - deg;
+            s_cf[wid][slot] = cf;
+        }
+        wave_sync_lds();
+        for (int e0 = 0; e0 < total; e0 += 64 * kFrontierUnroll) {  // wave-uniform trip count
+            // kFrontierUnroll returning atomics in flight per lane, then their tests
+            int u[kFrontierUnroll];
+            T delta[kFrontierUnroll], old[kFrontierUnroll];
+#pragma unroll
+            for (int j = 0; j < kFrontierUnroll; ++j) {
+                const int e = e0 + 64 * j + lane;
+                u[j] = -1;
+                if (e < total) {
+                    const int k = tile_find(s_pre[wid], na, e);
+                    const int a = s_beg[wid][k] + (e - s_pre[wid][k]);
+                    u[j] = t_col[a];
+                    delta[j] = (t_w ? static_cast<T>(t_w[a]) : static_cast<T>(1)) * s_cf[wid][k];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kFrontierUnroll; ++j)
+                if (u[j] >= 0) old[j] = unsafeAtomicAdd(&r[u[j]], delta[j]);
+#pragma unroll
+            for (int j = 0; j < kFrontierUnroll; ++j) {
+                bool want = false;
+                int bkt = 0;
+                if (u[j] >= 0) {
+                    const T hu = h[u[j]];
+                    if (fabs(old[j] + delta[j]) > hu && !(fabs(old[j]) > hu)) {
+                        want = atomicExch(&F.inq[u[j]], 1) == 0;
+                        if (want) bkt = push_bucket(t_row_ptr, u[j]);
+                    }
+                }
+                wave_append(want, u[j], bkt, F);
+            }
+        }
+        wave_sync_lds();
+        pushes += static_cast<unsigned long long>(na);
+        visits += static_cast<unsigned long long>(total);
+    }
+    if (lane == 0 && pushes) {
+        stripe_add(stats, 0, pushes);
+        stripe_add(stats, 1, visits);
+    }
+}
+
+// big bucket: a block per queue entry, grid-stride
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_frontier_big(FrontierArgs F, const int32_t* __restrict__ t_row_ptr,
+                                                         const int32_t* __restrict__ t_col,
+                                                         const float* __restrict__ t_w, T* r,
+                                                         const T* __restrict__ h, const T* __restrict__ inv,
+                                                         const double* __restrict__ inv64, double* zh, double omega,
+                                                         unsigned long long* stats) {
+    __shared__ T s_cf;
+    __shared__ int s_req;
+    const int cnt = F.cnt_cur[1];
+    for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
+        const int v = F.cur[1][idx];
+        if (threadIdx.x == 0) {
+            bool rq = false;
+            s_cf = pop_node<T>(v, r, h, inv, inv64, zh, omega, F, &rq);
+            s_req = rq ? 1 : 0;
+        }
+        __syncthreads();
+        const T cf = s_cf;
+        if (threadIdx.x < 64) wave_append(threadIdx.x == 0 && s_req, v, 1, F);
+        if (cf != static_cast<T>(0)) {
+            const int beg = t_row_ptr[v], end = t_row_ptr[v + 1];
+            for (int k0 = beg; k0 < end; k0 += kBlock) {  // block-uniform trip count
+                const int k = k0 + static_cast<int>(threadIdx.x);
+                bool want = false;
+                int u = 0, bkt = 0;
+                if (k < end) {
+                    u = t_col[k];
+                    const T wgt = t_w ? static_cast<T>(t_w[k]) : static_cast<T>(1);
+                    want = push_arc<T>(u, wgt * cf, r, h, F);
+                    if (want) bkt = push_bucket(t_row_ptr, u);
+                }
+                wave_append(want, u, bkt, F);
+            }
+            if (threadIdx.x == 0) {
+                stripe_add(stats, 0, 1ull);
+                stripe_add(stats, 1, static_cast<unsigned long long>(end - beg));
+            }
+        }
+        __syncthreads();  // s_cf is rewritten for the next entry
+    }
+}
+
+// queue every node above threshold (start, or after a refinement re-seeded r)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_frontier_seed(int64_t n, const T* __restrict__ r, const T* __restrict__ h,
+                                                          const int32_t* __restrict__ t_row_ptr, FrontierArgs F) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    bool act = false;
+    int bkt = 0;
+    if (v < n) {
+        act = fabs(r[v]) > h[v];
+        F.inq[v] = act ? 1 : 0;
+        if (act) bkt = push_bucket(t_row_ptr, static_cast<int>(v));
+    }
+    wave_append(act, static_cast<int>(v), bkt, F);
+}
+
+// end of a round: the consumed counters are cleared for reuse; flag = the
+// next frontier is not empty
+__global__ void k_frontier_flip(int* cnt_cur, const int* cnt_nxt, int* flag) {
+    if (threadIdx.x != 0) return;
+    cnt_cur[0] = 0;
+    cnt_cur[1] = 0;
+    *flag = cnt_nxt[0] + cnt_nxt[1] > 0 ? 1 : 0;
+}
+
 // ---------------------------------------------------------- colour-ordered SOR
 // Relabelled graph: colour class k occupies a contiguous row range.  Rows of
 // one class are not adjacent in A + A^T, so updating them together is exactly
@@ -400,6 +645,7 @@ struct SolveLayout {
     double* part_max; long long* part_viol; double* cert_max; long long* cert_viol;
     unsigned long long* hacc; unsigned long long* zmax_bits; double* zsh; int32_t* zqsh;
     double* ub; double* ub_tail; int* modes; unsigned long long* snaps;
+    int32_t* fq[2][2]; int* fcnt; int* inq;  // frontier push: queues [parity][bucket], counters [parity][bucket]
 };
 
 
@@ -407,7 +653,7 @@ int64_t cert_parts(const fj_graph* g) {
     return waves_to_blocks(g->tiles_a.nchunks + g->tiles_a.ntiles) + waves_to_blocks(g->tiles_a.nheavy) + 2;
 }
 
-SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
+SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision, bool frontier = false) {
     SolveLayout L{};
     const int64_t n = g->n;
     size_t tsz = precision == FJ_FP64 ? sizeof(double) : sizeof(float);
@@ -439,6 +685,12 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision) {
     L.part_viol = cv.take<long long>(nb);
     L.cert_max = cv.take<double>(1);
     L.cert_viol = cv.take<long long>(1);
+    if (frontier) {
+        for (int par = 0; par < 2; ++par)
+            for (int b = 0; b < 2; ++b) L.fq[par][b] = cv.take<int32_t>(n + 1);
+        L.fcnt = cv.take<int>(4);
+        L.inq = cv.take<int>(n + 1);
+    }
     return L;
 }
 
@@ -626,6 +878,180 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
     out->refinements = refinements;
     out->certified = converged ? 1 : 0;
     out->max_ratio = max_ratio;
+    if (!converged) {
+        set_error(capped ? "work cap reached before the certificate held"
+                         : "certificate failed after the refinement budget (or the iteration diverged)");
+        return FJ_ERR_NOT_CONVERGED;
+    }
+    return FJ_OK;
+}
+
+// Push rounds that switch from a scan of every node to a frontier queue
+// (push_scatter = 2).  While many nodes are above threshold a round scans
+// all of them and scatters with atomics that return nothing (k_push_light /
+// k_push_heavy); once a batch of check_every rounds averaged fewer pushes per
+// round than kFrontierDensity of the nodes, the queue is seeded with the
+// nodes above threshold and each round pops only the previous round's
+// appends, whose detection needs atomics that return the old residual.  The
+// host checks every check_every rounds; a round with nothing to push (scan)
+// or an empty next frontier is quiet.  FP32 or FP64 residual; the order of
+// concurrent atomic additions is not fixed, so the pushes (not the
+// certificate) may differ run to run.
+template <typename T>
+fj_status solve_push_frontier(const fj_graph* g, const double* s, const fj_solve_opts* o, double epsp, double* z,
+                              const SolveLayout& L, fj_solve_stats* out, hipStream_t st, int64_t cap) {
+    const int64_t n = g->n;
+    T* r = static_cast<T*>(L.r);
+    T* h = static_cast<T*>(L.h);
+    const T* inv = sizeof(T) == 4 ? reinterpret_cast<const T*>(g->inv32) : reinterpret_cast<const T*>(g->inv64);
+    const int bs = 256;
+    if (n > 0) {
+        if (o->z0) {
+            hipLaunchKernelGGL(k_init_warm<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->z0, o->c, epsp, h, L.zh,
+                               L.bad);
+            double mr; long long vi;
+            fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &mr, &vi);
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL(k_init_cold<T>, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, s, o->c, epsp, r, h, L.zh,
+                               L.bad);
+        }
+    }
+    int hbad = 0;
+    FJ_HIP(hipMemcpyAsync(&hbad, L.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+        set_error("s must be finite and >= 0, and z0 finite");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    const int K = o->check_every > 0 ? o->check_every : 8;
+    const int max_ref = o->max_refinements >= 0 ? o->max_refinements : 8;
+    // grids sized to fill the chip; the kernels stride over their queue
+    const unsigned nb_small = 2048, nb_big = 512;
+    const TileView tv = tile_view_all(g->tiles_t);
+    const unsigned nb_light = waves_to_blocks(tv.ntiles);
+    const unsigned nb_heavy = waves_to_blocks(tv.nchunks);
+    T* coef = static_cast<T*>(L.heavy_coef);
+    int64_t rounds = 0, launches = 0;
+    int refinements = 0;
+    bool converged = false, capped = false;
+    double max_ratio = 0.0;
+    std::vector<int> hf(K);
+    HostStats hs;
+    LaunchTimer timer;
+    timer.on = o->profile != 0;
+    timer.st = st;
+    auto args = [&](int par) {
+        FrontierArgs F{};
+        F.cur[0] = L.fq[par][0];
+        F.cur[1] = L.fq[par][1];
+        F.nxt[0] = L.fq[par ^ 1][0];
+        F.nxt[1] = L.fq[par ^ 1][1];
+        F.cnt_cur = L.fcnt + 2 * par;
+        F.cnt_nxt = L.fcnt + 2 * (par ^ 1);
+        F.inq = L.inq;
+        return F;
+    };
+    int par = 0;
+    int64_t frontier_rounds = 0;
+    while (true) {
+        bool queued = false;  // this phase has switched to the frontier queue
+        bool quiet = n == 0;
+        const int* prev = L.one;
+        while (!quiet) {
+            if (rounds + K > kMaxRounds) { capped = true; break; }
+            FJ_HIP(hipMemsetAsync(L.flags + rounds, 0, sizeof(int) * K, st));
+            const unsigned long long pushes_before = hs.pushes;
+            if (!queued) {  // scan rounds
+                for (int b = 0; b < K; ++b) {
+                    int* cur = L.flags + rounds + b;
+                    fj_status rc0 = timer.before();
+                    if (rc0) return rc0;
+                    hipLaunchKernelGGL(k_push_light<T>, dim3(nb_light), dim3(kBlock), 0, st, tv, g->t_row_ptr,
+                                       g->t_col, g->t_w, r, h, inv, g->inv64, L.zh, o->omega, coef, prev, cur,
+                                       L.stats);
+                    ++launches;
+                    if (nb_heavy > 0) {
+                        hipLaunchKernelGGL(k_push_heavy<T>, dim3(nb_heavy), dim3(kBlock), 0, st, tv, g->t_row_ptr,
+                                           g->t_col, g->t_w, r, coef, prev);
+                        ++launches;
+                    }
+                    rc0 = timer.after();
+                    if (rc0) return rc0;
+                    prev = cur;
+                }
+                FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + rounds, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+                fj_status rc = read_stats(L, st, &hs);
+                if (rc) return rc;
+                int used = K;
+                for (int b = 0; b < K; ++b)
+                    if (hf[b] == 0) { used = b; quiet = true; break; }
+                rounds += used;
+                if (static_cast<int64_t>(hs.visits) > cap) { capped = true; break; }
+                if (!quiet && static_cast<double>(hs.pushes - pushes_before) <
+                                  kFrontierDensity * static_cast<double>(n) * static_cast<double>(used)) {
+                    // sparse: the frontier is every node above threshold now
+                    FJ_HIP(hipMemsetAsync(L.fcnt, 0, sizeof(int) * 4, st));
+                    hipLaunchKernelGGL(k_frontier_seed<T>, dim3(grid1d(n, kBlock)), dim3(kBlock), 0, st, n, r, h,
+                                       g->t_row_ptr, args(1));
+                    ++launches;
+                    par = 0;  // the seed filled the queues of parity 0 (the "next" of parity 1)
+                    queued = true;
+                }
+                continue;
+            }
+            for (int b = 0; b < K; ++b) {
+                const FrontierArgs F = args(par);
+                fj_status rc0 = timer.before();
+                if (rc0) return rc0;
+                hipLaunchKernelGGL(k_frontier_small<T>, dim3(nb_small), dim3(kBlock), 0, st, F, g->t_row_ptr,
+                                   g->t_col, g->t_w, r, h, inv, g->inv64, L.zh, o->omega, L.stats);
+                hipLaunchKernelGGL(k_frontier_big<T>, dim3(nb_big), dim3(kBlock), 0, st, F, g->t_row_ptr, g->t_col,
+                                   g->t_w, r, h, inv, g->inv64, L.zh, o->omega, L.stats);
+                rc0 = timer.after();
+                if (rc0) return rc0;
+                hipLaunchKernelGGL(k_frontier_flip, dim3(1), dim3(64), 0, st, L.fcnt + 2 * par,
+                                   L.fcnt + 2 * (par ^ 1), L.flags + rounds + b);
+                launches += 3;
+                par ^= 1;
+            }
+            FJ_HIP(hipMemcpyAsync(hf.data(), L.flags + rounds, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+            fj_status rc = read_stats(L, st, &hs);
+            if (rc) return rc;
+            int used = K;
+            for (int b = 0; b < K; ++b)
+                if (hf[b] == 0) { used = b + 1; quiet = true; break; }
+            rounds += used;
+            frontier_rounds += used;
+            if (static_cast<int64_t>(hs.visits) > cap) { capped = true; break; }
+        }
+        if (capped) break;
+        long long viol = 0;
+        fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &max_ratio, &viol);
+        if (rc) return rc;
+        if (viol == 0) { converged = true; break; }
+        if (!std::isfinite(max_ratio) || refinements >= max_ref) break;
+        ++refinements;  // r now holds the FP64 residual rounded to T; the rounds resume from it
+    }
+    if (!converged) {
+        long long viol = 0;
+        fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, static_cast<T*>(nullptr), L, st, &max_ratio, &viol);
+        if (rc) return rc;
+    }
+    if (n > 0) hipLaunchKernelGGL(k_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, L.zh, o->c, z);
+    FJ_HIP(hipStreamSynchronize(st));
+    {
+        fj_status rc0 = timer.total_ms(&out->kernel_ms, &out->kernel_launches);
+        if (rc0) return rc0;
+    }
+    out->pushes = static_cast<int64_t>(hs.pushes);
+    out->edge_visits = static_cast<int64_t>(hs.visits);
+    out->rounds = rounds;
+    out->launches = launches;
+    out->refinements = refinements;
+    out->certified = converged ? 1 : 0;
+    out->max_ratio = max_ratio;
+    out->mirror_rounds = frontier_rounds;  // push rounds: the rounds that popped a frontier queue
     if (!converged) {
         set_error(capped ? "work cap reached before the certificate held"
                          : "certificate failed after the refinement budget (or the iteration diverged)");
@@ -1137,7 +1563,7 @@ extern "C" fj_status fj_certify(const fj_graph* g, const double* s, const double
 extern "C" size_t fj_solve_workspace_bytes(const fj_graph* g, const fj_solve_opts* opts) {
     if (!g || !opts) return 0;
     Carver cv(nullptr);
-    carve_solve(cv, g, opts->precision);
+    carve_solve(cv, g, opts->precision, opts->push_scatter == 2);
     return cv.bytes();
 }
 
@@ -1171,8 +1597,12 @@ extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve
         set_error("fj_solve: unknown schedule");
         return FJ_ERR_INVALID_ARGUMENT;
     }
+    if (o->push_scatter < 0 || o->push_scatter > 2) {
+        set_error("fj_solve: push_scatter must be 0, 1 or 2");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
     Carver cv(ws);
-    SolveLayout L = carve_solve(cv, g, o->precision);
+    SolveLayout L = carve_solve(cv, g, o->precision, o->push_scatter == 2);
     if (cv.bytes() > ws_bytes) {
         set_error("fj_solve: workspace too small: need " + std::to_string(cv.bytes()) + " bytes");
         return FJ_ERR_WORKSPACE_TOO_SMALL;
@@ -1188,6 +1618,9 @@ extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve
     fj_status rc;
     if (sched == FJ_SCHED_SOR)
         rc = solve_sor(g, s, o, epsp, z, L, &local, st, cap);
+    else if (o->push_scatter == 2)
+        rc = o->precision == FJ_FP64 ? solve_push_frontier<double>(g, s, o, epsp, z, L, &local, st, cap)
+                                     : solve_push_frontier<float>(g, s, o, epsp, z, L, &local, st, cap);
     else if (!o->push_scatter && g->a_packed)
         rc = solve_rounds_gather(g, s, o, epsp, z, L, &local, st, cap);
     else if (o->precision == FJ_FP64)

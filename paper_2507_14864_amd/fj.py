@@ -234,6 +234,16 @@ class Graph:
             self._h = None
 
 
+def _scatter_mode(push_scatter) -> int:
+    """push_scatter: False/0 gather-form rounds, True/1 atomic scatter over a
+    scan of all nodes, "frontier"/2 atomic scatter over a frontier queue."""
+    if push_scatter == "frontier":
+        return 2
+    if isinstance(push_scatter, bool):
+        return 1 if push_scatter else 0
+    return int(push_scatter)
+
+
 def make_opts(eps=1e-4, omega=1.0, c=1e-5, sigma=1e-5, precision="fp32", schedule="auto",
               max_edge_visits=0, max_refinements=-1, check_every=8, z0=None, profile=False,
               persistent=False, gather_bits=0, tail_merge=True, push_scatter=False,
@@ -241,7 +251,7 @@ def make_opts(eps=1e-4, omega=1.0, c=1e-5, sigma=1e-5, precision="fp32", schedul
     return SolveOpts(float(eps), float(omega), float(c), float(sigma), PRECISIONS[precision],
                      SCHEDULES[schedule], int(max_edge_visits), int(max_refinements), int(check_every),
                      None if z0 is None else ctypes.c_void_p(z0.data_ptr()), 1 if profile else 0,
-                     1 if persistent else 0, int(gather_bits), 1 if push_scatter else 0, 0 if tail_merge else 1,
+                     1 if persistent else 0, int(gather_bits), _scatter_mode(push_scatter), 0 if tail_merge else 1,
                      float(skip_below))
 
 

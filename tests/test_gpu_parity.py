@@ -583,3 +583,74 @@ def test_gather_probe_reports_a_rate():
             fj.gather_probe(G, 2, 1)
         with pytest.raises(fj.FJError):
             fj.gather_probe(G, 4, 0)
+
+
+@pytest.mark.parametrize("directed,precision,omega", [(False, "fp32", 1.0), (True, "fp32", 1.0), (False, "fp64", 1.0),
+                                                      (True, "fp32", 0.8), (False, "fp64", 0.7)])
+def test_frontier_push_rounds(directed, precision, omega):
+    """Push rounds over the frontier queue (Alg. 1's queue as the round sets of
+    the proof of Thm. 5) reach the certificate; omega < 1 exercises the nodes
+    that queue themselves again.  Its pushes are the scan form's: the same
+    certificate from a similar number of updates."""
+    fj = fjmod()
+    g = synth.chung_lu(40000, 400000, 2.2, 111 + directed, directed=directed, weighted=directed)
+    s = synth.opinions(g.n, "bimodal", 112)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV)
+    sd = to_dev(s)
+    eps = 1e-6 if precision == "fp64" else 1e-5
+    zf, stf = fj.solve(G, sd, eps=eps, omega=omega, schedule="push", precision=precision, push_scatter="frontier")
+    zf = zf.clone()
+    zs, sts = fj.solve(G, sd, eps=eps, omega=omega, schedule="push", precision=precision, push_scatter=True)
+    print(f"frontier {stf['rounds']} rounds ({stf['mirror_rounds']} over the queue) {stf['pushes']} pushes; "
+          f"scan {sts['rounds']} rounds {sts['pushes']} pushes", flush=True)
+    assert stf["mirror_rounds"] > 0  # the sparse rounds popped the queue
+    for z, st in ((zf, stf), (zs, sts)):
+        assert st["certified"] == 1
+        check_solution(g, s, z, zt, eps)
+    assert stf["pushes"] <= 2 * sts["pushes"]
+
+
+def test_frontier_hubs_refinement_and_warm_start():
+    """Nodes with more than 2048 arcs to scatter take the block-per-node
+    bucket; an FP32 residual at eps = 1e-7 forces refinements, which re-seed
+    the frontier from the FP64 residual; a warm start seeds it from the start's
+    residual (Lemma 4)."""
+    fj = fjmod()
+    g = synth.chung_lu(300000, 3000000, 2.1, 113)
+    assert np.diff(g.row_ptr).max() > 2048
+    s = synth.opinions(g.n, "uniform", 114)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV)
+    sd = to_dev(s)
+    z, st = fj.solve(G, sd, eps=1e-7, omega=1.0, precision="fp32", schedule="push", push_scatter="frontier")
+    print(f"frontier refinement: {st}", flush=True)
+    assert st["refinements"] >= 1 and st["certified"] == 1
+    check_solution(g, s, z, zt, 1e-7)
+    z2, st2 = fj.solve(G, sd, eps=1e-5, omega=1.0, schedule="push", push_scatter="frontier", z0=sd)
+    assert st2["certified"] == 1
+    check_solution(g, s, z2, zt, 1e-5)
+    # an empty frontier from the exact solution: no push at all
+    z3, st3 = fj.solve(G, sd, eps=1e-5, omega=1.0, precision="fp64", schedule="push", push_scatter="frontier",
+                       z0=to_dev(zt))
+    assert st3["certified"] == 1 and st3["pushes"] == 0
+
+
+@pytest.mark.parametrize("form", [True, "frontier"])
+def test_fp32_scatter_refinements_terminate(form):
+    """Repeated FP32 scatter solves (run-dependent order) on a directed
+    weighted graph of the 1M-node law: each ends certified after a few
+    refinements.  A refinement re-seeds the residual rounded away from zero,
+    so a row that fails the FP64 certificate by less than half an ulp of its
+    FP32 threshold is still pushed."""
+    fj = fjmod()
+    g = synth.chung_lu(200_000, 2_000_000, 2.1, 121, directed=True, weighted=True)
+    s = synth.opinions(g.n, "uniform", 122)
+    zt = oracle.exact(g, s)
+    G = fj.Graph.from_host(g, DEV)
+    sd = to_dev(s)
+    for rep in range(6):
+        z, st = fj.solve(G, sd, eps=1e-4, omega=1.0, precision="fp32", schedule="push", push_scatter=form)
+        assert st["certified"] == 1 and st["refinements"] <= 3, (rep, st)
+        if rep == 0:
+            check_solution(g, s, z, zt, 1e-4)
