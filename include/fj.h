@@ -201,7 +201,13 @@ size_t fj_solve_workspace_bytes(const fj_graph* g, const fj_solve_opts* opts);
  * FJ_ERR_NOT_CONVERGED: the work cap was hit, the iteration diverged (SOR with
  * omega > 1 on a directed graph is not guaranteed to converge), or the
  * refinement budget ran out; z then holds the last estimate and
- * stats->certified = 0.  stats: [host] or NULL.  Synchronizes `stream`. */
+ * stats->certified = 0.  stats: [host] or NULL.  Synchronizes `stream`.
+ * Tracing: with FJ_TRACE set in the environment (to anything but empty or
+ * 0), every host check of the iteration writes one JSON line to stderr --
+ * {"fj_trace": "sor"|"push", "event": "batch", "mode", "rounds",
+ * "batch_rounds", "updates", "edge_visits", "skipped_rows"} (cumulative counts)
+ * -- and every FP64 certificate one {"event": "certificate", "rounds",
+ * "max_ratio", "violations", "refinements"}. */
 fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve_opts* opts, double* z,
                    void* ws, size_t ws_bytes, fj_solve_stats* stats, void* stream);
 

@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cmath>
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -747,6 +749,29 @@ fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
     return FJ_OK;
 }
 
+// FJ_TRACE (any value but empty or 0) in the environment: one JSON line on
+// stderr per host check of a solve (cumulative updates, arcs and skipped
+// rows after each batch of rounds or sweeps) and per FP64 certificate.
+bool trace_on() {
+    static const bool on = [] {
+        const char* e = std::getenv("FJ_TRACE");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+void trace_batch(const char* sched, const char* mode, int64_t rounds, int used, const HostStats& hs) {
+    std::fprintf(stderr,
+                 "{\"fj_trace\": \"%s\", \"event\": \"batch\", \"mode\": \"%s\", \"rounds\": %lld, "
+                 "\"batch_rounds\": %d, \"updates\": %llu, \"edge_visits\": %llu, \"skipped_rows\": %llu}\n",
+                 sched, mode, static_cast<long long>(rounds), used, hs.pushes, hs.visits, hs.skipped);
+}
+void trace_cert(const char* sched, int64_t rounds, double max_ratio, long long viol, int refinements) {
+    std::fprintf(stderr,
+                 "{\"fj_trace\": \"%s\", \"event\": \"certificate\", \"rounds\": %lld, \"max_ratio\": %.17g, "
+                 "\"violations\": %lld, \"refinements\": %d}\n",
+                 sched, static_cast<long long>(rounds), max_ratio, viol, refinements);
+}
+
 // c_res: shift already inside zh (residual of the shifted system); c_thr: shift
 // of the threshold h = eps' (s + c_thr)
 template <typename T>
@@ -850,12 +875,14 @@ fj_status solve_push(const fj_graph* g, const double* s, const fj_solve_opts* o,
                 if (hf[b] == 0) { used = b; quiet = true; break; }
             rounds += used;
             if (n == 0) quiet = true;
+            if (trace_on()) trace_batch("push", "scan", rounds, used, hs);
             if (static_cast<int64_t>(hs.visits) > cap) { capped = true; break; }
         }
         if (capped) break;
         long long viol = 0;
         fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &max_ratio, &viol);
         if (rc) return rc;
+        if (trace_on()) trace_cert("push", rounds, max_ratio, viol, refinements);
         if (viol == 0) { converged = true; break; }
         if (!std::isfinite(max_ratio) || refinements >= max_ref) break;
         ++refinements;  // r now holds the FP64 residual rounded to T; resume pushing
@@ -987,6 +1014,7 @@ fj_status solve_push_frontier(const fj_graph* g, const double* s, const fj_solve
                 for (int b = 0; b < K; ++b)
                     if (hf[b] == 0) { used = b; quiet = true; break; }
                 rounds += used;
+                if (trace_on()) trace_batch("push", "scan", rounds, used, hs);
                 if (static_cast<int64_t>(hs.visits) > cap) { capped = true; break; }
                 if (!quiet && static_cast<double>(hs.pushes - pushes_before) <
                                   kFrontierDensity * static_cast<double>(n) * static_cast<double>(used)) {
@@ -1023,12 +1051,14 @@ fj_status solve_push_frontier(const fj_graph* g, const double* s, const fj_solve
                 if (hf[b] == 0) { used = b + 1; quiet = true; break; }
             rounds += used;
             frontier_rounds += used;
+            if (trace_on()) trace_batch("push", "queue", rounds, used, hs);
             if (static_cast<int64_t>(hs.visits) > cap) { capped = true; break; }
         }
         if (capped) break;
         long long viol = 0;
         fj_status rc = certify<T>(g, s, o->c, o->c, epsp, L.zh, r, L, st, &max_ratio, &viol);
         if (rc) return rc;
+        if (trace_on()) trace_cert("push", rounds, max_ratio, viol, refinements);
         if (viol == 0) { converged = true; break; }
         if (!std::isfinite(max_ratio) || refinements >= max_ref) break;
         ++refinements;  // r now holds the FP64 residual rounded to T; the rounds resume from it
@@ -1148,6 +1178,12 @@ fj_status solve_rounds_gather(const fj_graph* g, const double* s, const fj_solve
             rounds += used;
             if (mirror) mirror_rounds += used;
             if (n == 0) quiet = true;
+            if (trace_on()) {
+                HostStats hs;
+                fj_status rc0 = read_stats(L, st, &hs);
+                if (rc0) return rc0;
+                trace_batch("push", mirror ? "gather fixed-point" : "gather fp64", rounds, used, hs);
+            }
         }
         if (capped || diverged) break;
         long long viol = 0;
@@ -1433,6 +1469,14 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
                 if (hf[b] == 0) { used = b + 1; quiet = true; break; }
             sweeps += used;
             if (mirror) mirror_sweeps += used;
+            if (trace_on()) {
+                HostStats hs;
+                fj_status rc0 = read_stats(L, st, &hs);
+                if (rc0) return rc0;
+                trace_batch("sor", mirror ? (skip_batch ? "fixed-point skipping" : "fixed-point")
+                                          : (skip_batch ? "fp64 skipping" : "fp64"),
+                            sweeps, used, hs);
+            }
             // a batch whose last sweep skipped is followed by the grouped launches
             if (skipping) grouped = skip_batch && hmodes[used - 1] == 2;
             if (skipping) skip_batch = true;
@@ -1444,6 +1488,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
         long long viol = 0;
         fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L, st, &max_ratio, &viol);
         if (rc) return rc;
+        if (trace_on()) trace_cert("sor", sweeps, max_ratio, viol, refinements);
         if (viol == 0) { converged = true; break; }
         if (mirror) {  // finish with FP64 gathers
             mirror = false;

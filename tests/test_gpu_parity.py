@@ -654,3 +654,37 @@ def test_fp32_scatter_refinements_terminate(form):
         assert st["certified"] == 1 and st["refinements"] <= 3, (rep, st)
         if rep == 0:
             check_solution(g, s, z, zt, 1e-4)
+
+
+def test_fj_trace_writes_one_line_per_check(tmp_path):
+    """FJ_TRACE=1: the solve writes JSON lines per batch of sweeps and per
+    certificate to stderr, with nondecreasing cumulative counts, ending in a
+    certificate without violations."""
+    import json
+    import os
+    import subprocess
+    import sys
+    script = tmp_path / "trace_run.py"
+    script.write_text(
+        "import sys\n"
+        f"sys.path.insert(0, {os.path.dirname(os.path.dirname(os.path.abspath(__file__)))!r})\n"
+        "import torch, synth\n"
+        "import paper_2507_14864_amd as fj\n"
+        "g = synth.chung_lu(30000, 200000, 2.3, 131)\n"
+        "s = torch.from_numpy(synth.opinions(g.n, 'uniform', 132)).to('cuda:0')\n"
+        "G = fj.Graph.from_host(g, 'cuda:0', colour=True)\n"
+        "z, st = fj.solve(G, s, eps=1e-5, omega=1.5, schedule='sor')\n"
+        "z, st = fj.solve(G, s, eps=1e-5, omega=1.0, schedule='push', push_scatter='frontier')\n"
+        "print('done', flush=True)\n")
+    env = dict(os.environ, FJ_TRACE="1")
+    out = subprocess.run([sys.executable, str(script)], env=env, capture_output=True, text=True, timeout=180)
+    assert out.returncode == 0, out.stderr[-2000:]
+    lines = [json.loads(l) for l in out.stderr.splitlines() if l.startswith("{\"fj_trace\"")]
+    for sched in ("sor", "push"):
+        ev = [l for l in lines if l["fj_trace"] == sched]
+        batches = [l for l in ev if l["event"] == "batch"]
+        certs = [l for l in ev if l["event"] == "certificate"]
+        assert batches and certs, sched
+        ups = [b["updates"] for b in batches]
+        assert ups == sorted(ups) and batches[-1]["rounds"] >= batches[0]["rounds"]
+        assert certs[-1]["violations"] == 0 and certs[-1]["max_ratio"] <= 1.0
