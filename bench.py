@@ -478,6 +478,7 @@ def main():
                    "schedule": args.schedule, "precision": precision, "colours": info["num_colours"],
                    "sweeps_or_rounds": st["rounds"], "merged_tail_classes": st.get("merged_classes", 0),
                    "skipped_row_visits": st.get("skipped_rows", 0), "edge_visits": st["edge_visits"],
+                   "bound_atomic_adds": st.get("bound_adds", 0),
                    "certified": st["certified"],
                    "max_ratio": st["max_ratio"], "ingest_s": round(ingest_s, 3),
                    "metrics": {k: m[k] for k in ("P", "D", "I", "C")},

@@ -186,6 +186,8 @@ typedef struct {
     int64_t skipped_rows;   /* row visits skipped by bound skipping */
     int64_t skipped_arcs;   /* the arcs of those rows */
     int64_t mirror_edge_visits; /* arcs gathered in the sweeps that read the fixed-point copy */
+    int64_t bound_adds;     /* bound skipping: FP64 atomic additions to the residual bounds of the
+                               rows that read an updated value (one per arc of an updated row) */
 } fj_solve_stats;
 
 /* Bytes of solve workspace for this graph and options. */

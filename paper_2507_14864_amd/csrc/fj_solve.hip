@@ -732,19 +732,21 @@ struct LaunchTimer {
 
 struct HostStats {
     unsigned long long pushes = 0, visits = 0, skipped = 0, skipped_arcs_fix = 0, skipped_arcs_fp64 = 0;
+    unsigned long long bound_adds = 0;
 };
 
 fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
     std::vector<unsigned long long> buf(kStripes * kStripeStride);
     FJ_HIP(hipMemcpyAsync(buf.data(), L.stats, sizeof(unsigned long long) * buf.size(), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
-    hs->pushes = hs->visits = hs->skipped = hs->skipped_arcs_fix = hs->skipped_arcs_fp64 = 0;
+    hs->pushes = hs->visits = hs->skipped = hs->skipped_arcs_fix = hs->skipped_arcs_fp64 = hs->bound_adds = 0;
     for (int k = 0; k < kStripes; ++k) {
         hs->pushes += buf[k * kStripeStride + 0];
         hs->visits += buf[k * kStripeStride + 1];
         hs->skipped += buf[k * kStripeStride + 2];
         hs->skipped_arcs_fix += buf[k * kStripeStride + 3];
         hs->skipped_arcs_fp64 += buf[k * kStripeStride + 4];
+        hs->bound_adds += buf[k * kStripeStride + 5];
     }
     return FJ_OK;
 }
@@ -1514,6 +1516,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     out->skipped_rows = static_cast<int64_t>(hs.skipped);
     out->skipped_arcs = static_cast<int64_t>(hs.skipped_arcs_fix + hs.skipped_arcs_fp64);
     out->mirror_edge_visits = mirror_sweeps * g->nnz - static_cast<int64_t>(hs.skipped_arcs_fix);
+    out->bound_adds = static_cast<int64_t>(hs.bound_adds);
     out->pushes = static_cast<int64_t>(hs.pushes);
     out->edge_visits = sweeps * g->nnz - static_cast<int64_t>(hs.skipped_arcs_fix + hs.skipped_arcs_fp64);
     out->rounds = sweeps;

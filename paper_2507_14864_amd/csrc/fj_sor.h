@@ -386,11 +386,15 @@ __device__ __forceinline__ void sor_light_tile(int64_t tix, int md, const TileVi
         // the whole wave taking one row at a time
         if (sweep_row) S.ub[r0 + lane] = own_bound(rr, upd, S.omega, rd.opd);
         const double mag = upd ? change_mag(zn, rd.z) : 0.0;
+        unsigned long long adds = 0;
         for (uint64_t rem = um; rem; rem &= rem - 1) {
             const int l = __builtin_ctzll(rem);
             const int64_t i = r0 + l;
-            bound_arcs<4, SHADOW>(S, pcol, pw, prow_ptr[i], prow_ptr[i + 1], __shfl(mag, l, 64));
+            const int b = prow_ptr[i], e = prow_ptr[i + 1];
+            bound_arcs<4, SHADOW>(S, pcol, pw, b, e, __shfl(mag, l, 64));
+            adds += static_cast<unsigned long long>(e - b);
         }
+        if (adds && lane == 0) stripe_add(stats, 5, adds);  // counter 5: bound additions
     }
 }
 
@@ -576,8 +580,10 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
             }
         }
         // an updated heavy row raises its neighbours' bounds, the whole wave taking its arcs
-        if (SKIP && md >= 1 && __shfl(fin_upd, 0, 64))
+        if (SKIP && md >= 1 && __shfl(fin_upd, 0, 64)) {
             bound_arcs<16, SHADOW>(S, pcol, pw, prow_ptr[row], prow_ptr[row + 1], __shfl(mag, 0, 64));
+            if (lane == 0) stripe_add(stats, 5, static_cast<unsigned long long>(prow_ptr[row + 1] - prow_ptr[row]));
+        }
         return;
     }
     wv -= tv.nchunks;

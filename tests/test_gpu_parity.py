@@ -688,3 +688,26 @@ def test_fj_trace_writes_one_line_per_check(tmp_path):
         ups = [b["updates"] for b in batches]
         assert ups == sorted(ups) and batches[-1]["rounds"] >= batches[0]["rounds"]
         assert certs[-1]["violations"] == 0 and certs[-1]["max_ratio"] <= 1.0
+
+
+@pytest.mark.parametrize("omega", [1.5, 1.8])
+def test_directed_over_relaxation_fails_alike_in_oracle_and_gpu(omega):
+    """On a directed graph of the 1M-node law (out/in exponent 2.1, weights
+    U[0.5, 1.5]) at 100k nodes, over-relaxation beyond 1.2 is outside what
+    Sec. 5.2 argues (symmetric I+L).  The oracle's FIFO push and the GPU's
+    colour-ordered sweeps are pinned to fail alike: neither certifies within
+    its work cap (the oracle may also report divergence), and the GPU reports
+    it with FJ_ERR_NOT_CONVERGED and a finite estimate instead of a wrong
+    certificate."""
+    fj = fjmod()
+    g = synth.chung_lu(100_000, 1_000_000, 2.1, 141, directed=True, weighted=True)
+    s = synth.opinions(g.n, "uniform", 142)
+    cap = 200 * (g.nnz + g.n)
+    p = oracle.push(g, s, 1e-4, omega=omega, max_edge_visits=cap)
+    print(f"omega {omega}: oracle capped {p['capped']} diverged {p['diverged']}", flush=True)
+    assert p["capped"] or p["diverged"]
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    with pytest.raises(fj.FJNotConverged) as e:
+        fj.solve(G, to_dev(s), eps=1e-4, omega=omega, schedule="sor", max_edge_visits=cap)
+    assert e.value.stats["certified"] == 0
+    print(f"omega {omega}: GPU {e.value.stats['rounds']} sweeps, max ratio {e.value.stats['max_ratio']}", flush=True)
