@@ -78,7 +78,9 @@ size_t fj_graph_workspace_bytes(const fj_graph_desc* desc, int32_t flags);
  * of A^T (a push at v feeds every u with a_uv > 0, the column of A in the
  * proof of Lemma 4); with FJ_GRAPH_COLOUR a colouring of the symmetrised
  * pattern A + A^T and a relabelled copy of A whose colour classes are
- * contiguous (the order the SOR sweeps visit, Thm. 8 with Eq. (sor1)); on an
+ * contiguous (the order the SOR sweeps visit, Thm. 8 with Eq. (sor1)), on a
+ * directed graph with a relabelled copy of A^T beside it (the rows whose
+ * residual bounds an update raises, fj_solve_opts.skip_below); on an
  * undirected graph also, for the trailing small classes, the coupling bound
  * that decides whether a solve may sweep them together (fj_solve_opts).
  * The caller's row_ptr/col/w must outlive the handle.  Synchronizes `stream`.
@@ -155,12 +157,13 @@ typedef struct {
                                 when every such row's coupling to them, sum_j a_ij / (1 + d_i),
                                 is below 0.9 (2/omega - 1): the Householder-John condition for
                                 convergence of the resulting splitting */
-    double skip_below;       /* FJ_SCHED_SOR on an undirected graph, bound skipping.  From the
+    double skip_below;       /* FJ_SCHED_SOR, bound skipping.  From the
                                 second batch of check_every sweeps on, a sweep that follows one
                                 with fewer than skip_below * n updates keeps a bound on every row's residual: the
                                 row's own |r| at its sweep ((1 - omega) |r| after its update,
                                 Eq. (sor2)), raised by a_ij |change of zhat'_j| for each later
-                                update of a neighbour j (Lemma 4).  From the sweep after that, a
+                                update of a node j that row i reads (Lemma 4; on a directed graph
+                                the rows to raise come from the relabelled CSR(A^T)).  From the sweep after that, a
                                 row whose bound, plus the rounding of its gathered sum, stays
                                 below its update threshold keeps its value without gathering.
                                 It would not have updated: the result is bit for bit the one

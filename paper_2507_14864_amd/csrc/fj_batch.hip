@@ -762,7 +762,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
         auto* pcomp = cv.take<int32_t>(un);
         fj_graph_desc ud{un, unnz, rp, col, w, 1};
         if (!base) { ud.row_ptr = reinterpret_cast<const int32_t*>(256); ud.col = ud.row_ptr; if (uw) ud.w = reinterpret_cast<const float*>(256); }
-        size_t gb = graph_ws_bytes(&ud, FJ_GRAPH_COLOUR);
+        size_t gb = graph_ws_bytes(&ud, FJ_GRAPH_COLOUR | kGraphNoBoundCsr);
         void* gws = cv.take<char>(gb);
         auto* s_in = cv.take<double>(un);
         auto* z_out = cv.take<double>(un);
@@ -787,7 +787,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
         const int64_t n = items[i].graph.n, nnz = items[i].graph.nnz;
         const int k = items[i].k;
         fj_graph_desc d = items[i].graph;
-        size_t gb = graph_ws_bytes(&d, FJ_GRAPH_COLOUR);
+        size_t gb = graph_ws_bytes(&d, FJ_GRAPH_COLOUR | kGraphNoBoundCsr);
         void* gws = cv.take<char>(gb);
         auto* s_in = cv.take<double>(n * k);
         auto* z_out = cv.take<double>(n * k);
@@ -1057,7 +1057,7 @@ extern "C" fj_status fj_batch_create(const fj_batch_item_desc* items, int32_t nu
             return fail(FJ_ERR_INVALID_ARGUMENT);
         }
         fj_graph_desc ud{U.n, U.nnz, U.row_ptr, U.col, U.w, 1};
-        fj_status rc = graph_build(&U.g, &ud, FJ_GRAPH_COLOUR, U.gws, U.gws_bytes, st);
+        fj_status rc = graph_build(&U.g, &ud, FJ_GRAPH_COLOUR | kGraphNoBoundCsr, U.gws, U.gws_bytes, st);
         if (rc) return fail(rc);
         hipLaunchKernelGGL(k_union_symmetry, dim3(g1d(U.n, 256)), dim3(256), 0, st, U.n, U.row_ptr, U.col, U.w,
                            U.comp_of, U.comp_dir, err);
@@ -1071,7 +1071,7 @@ extern "C" fj_status fj_batch_create(const fj_batch_item_desc* items, int32_t nu
         b->num_colours = std::max(b->num_colours, U.g.num_colours);
     }
     for (auto& G : b->M) {
-        fj_status rc = graph_build(&G.g, &G.desc, FJ_GRAPH_COLOUR, G.gws, G.gws_bytes, st);
+        fj_status rc = graph_build(&G.g, &G.desc, FJ_GRAPH_COLOUR | kGraphNoBoundCsr, G.gws, G.gws_bytes, st);
         if (rc) return fail(rc);
         b->num_colours = std::max(b->num_colours, G.g.num_colours);
     }

@@ -436,7 +436,7 @@ __global__ void k_perm_copy(int64_t n, const int32_t* __restrict__ perm, const i
         pcol[pb + (k - b)] = iperm[col[k]];
         if (pw) pw[pb + (k - b)] = w[k];
     }
-    if (lane_id() == 0) {
+    if (lane_id() == 0 && popd) {
         popd[i] = opd[o];
         pinv64[i] = inv64[o];
     }
@@ -565,6 +565,7 @@ struct GraphLayout {
     int32_t* t_row_ptr; int32_t* t_col; float* t_w; int32_t* t_cursor;
     int32_t* colour; uint64_t* key; int32_t* cur1; int32_t* cur2; int32_t* perm; int32_t* iperm;
     int32_t* hist; int64_t* class_off; int32_t* prow_ptr; int32_t* pcol; float* pw; double* popd; double* pinv64;
+    int32_t* qrow_ptr; int32_t* qcol; float* qw;
     int* flags; void* scan_tmp;
     TileSet ta, tt, tp;
     TileTemps tmp;
@@ -602,6 +603,11 @@ GraphLayout carve_graph(Carver& cv, const fj_graph_desc* d, int32_t flags) {
         L.pw = weighted ? cv.take<float>(nnz) : nullptr;
         L.popd = cv.take<double>(n);
         L.pinv64 = cv.take<double>(n);
+        if (d->directed && !(flags & kGraphNoBoundCsr)) {
+            L.qrow_ptr = cv.take<int32_t>(n + 1);
+            L.qcol = cv.take<int32_t>(nnz);
+            L.qw = weighted ? cv.take<float>(nnz) : nullptr;
+        }
         scan_n = std::max<int64_t>(scan_n, static_cast<int64_t>(kMaxColours) * nchunks);
     }
     L.scan_tmp = cv.take<char>(scan_tmp_bytes(scan_n));
@@ -798,6 +804,14 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     exclusive_scan_i32(L.prow_ptr, L.prow_ptr, n + 1, L.scan_tmp, st);
     hipLaunchKernelGGL(k_perm_copy, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, L.perm, L.iperm, d->row_ptr, d->col,
                        d->w, L.opd, L.inv64, L.prow_ptr, L.pcol, L.pw, L.popd, L.pinv64);
+    if (L.qrow_ptr) {
+        // relabelled CSR(A^T): row i lists the rows of A that read node i (bound skipping)
+        hipLaunchKernelGGL(k_perm_rowlen, dim3(grid1d(n + 1, bs)), dim3(bs), 0, st, n, L.perm, g->t_row_ptr,
+                           L.qrow_ptr);
+        exclusive_scan_i32(L.qrow_ptr, L.qrow_ptr, n + 1, L.scan_tmp, st);
+        hipLaunchKernelGGL(k_perm_copy, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, L.perm, L.iperm, g->t_row_ptr,
+                           g->t_col, g->t_w, nullptr, nullptr, L.qrow_ptr, L.qcol, L.qw, nullptr, nullptr);
+    }
     FJ_HIP(hipStreamSynchronize(st));
     g->tiles_p = L.tp;
     {
@@ -851,6 +865,9 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     g->prow_ptr = L.prow_ptr;
     g->pcol = L.pcol;
     g->pw = L.pw;
+    g->qrow_ptr = L.qrow_ptr;
+    g->qcol = L.qcol;
+    g->qw = L.qw;
     g->popd = L.popd;
     g->pinv64 = L.pinv64;
     return FJ_OK;

@@ -144,6 +144,9 @@ struct fj_graph {
     int32_t* prow_ptr = nullptr;     // relabelled CSR(A)
     int32_t* pcol = nullptr;
     float* pw = nullptr;
+    int32_t* qrow_ptr = nullptr;     // relabelled CSR(A^T), directed graphs: row i lists
+    int32_t* qcol = nullptr;         // the rows of A that read zhat'_i, with a_ji
+    float* qw = nullptr;
     double* popd = nullptr;          // 1 + d, relabelled
     double* pinv64 = nullptr;
     // wave work partitions
@@ -154,7 +157,10 @@ struct fj_graph {
 
 namespace fj {
 
-// Kernel launchers (fj_graph.hip)
+// Kernel launchers (fj_graph.hip).  Besides the public flags, graph_build
+// takes kGraphNoBoundCsr: a directed coloured graph then skips the relabelled
+// CSR(A^T) that only the single-graph sweeps' bound skipping reads.
+constexpr int32_t kGraphNoBoundCsr = 1 << 16;
 fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* ws, size_t ws_bytes,
                       hipStream_t st);
 size_t graph_ws_bytes(const fj_graph_desc* d, int32_t flags);

@@ -1302,6 +1302,9 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     // FP64 rounding of the standalone certificate (different summation order).
     SorState S64{L.sp, g->popd, g->pinv64, L.zh, L.zq, o->omega, 1.0 - 1e-6, epsp, L.hacc, L.zmax_bits,
                  L.zsh, L.zqsh, 0};
+    S64.brow = g->directed ? g->qrow_ptr : g->prow_ptr;
+    S64.bcol = g->directed ? g->qcol : g->pcol;
+    S64.bw = g->directed ? g->qw : g->pw;
     // Merged tail: the trailing small classes [merge_T, nc) are swept by one
     // launch in which their rows see each other's values from before it (a
     // Jacobi step among them).  With A = (I+D) - W, the sweep is the splitting
@@ -1343,12 +1346,12 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     const int KP = std::max(K, 32);
     std::vector<int> hfp(KP);
     // Bound skipping: an update raises the bounds of the rows of A that read
-    // the updated value through the updated row's own arcs, which needs a
-    // symmetric pattern; every class must run in k_sor_class (which keeps the
-    // bounds).  Considered from the second sweep of each phase (fixed-point
+    // the updated value, through the updated row's arcs in CSR(A) (symmetric
+    // pattern) or in the relabelled CSR(A^T) (directed); every class must run
+    // in k_sor_class (which keeps the bounds).  Considered from the second sweep of each phase (fixed-point
     // sweeps, FP64 sweeps, each refinement), once a sweep updated fewer than
     // `limit` rows.
-    bool skipping = o->skip_below >= 0.0 && n > 0 && !g->directed;
+    bool skipping = o->skip_below >= 0.0 && n > 0 && S64.brow != nullptr;
     for (int k = 0; k < nc && skipping; ++k)
         if (!g->class_packed[k]) skipping = false;
     const double limit = (o->skip_below > 0.0 ? o->skip_below : kSkipBelow) * static_cast<double>(n);

@@ -48,7 +48,7 @@ struct SorState {
     double* zsh;                          // merged tail: new zhat' of rows >= sh_base (shadow)
     int32_t* zqsh;                        // merged tail: new fixed-point copy (shadow)
     int64_t sh_base;
-    // Bound skipping (k_sor_class, symmetric pattern).  ub[i] bounds |r_i|
+    // Bound skipping (k_sor_class).  ub[i] bounds |r_i|
     // for the current estimate: the row's own residual at its last sweep
     // (after its own update, (1 - omega) of it, Eq. (sor2)), plus
     // a_ij |change of zhat'_j| for every neighbour update since (Lemma 4: a
@@ -59,6 +59,12 @@ struct SorState {
     double* ub;       // [n]
     double* ub_tail;  // [n - sh_base]: adds made inside a merged-tail launch to
                       // its own rows, merged into ub at the next sweep's start
+    // The rows whose bounds an update of row i raises, with the arc weights:
+    // the rows j with a_ji > 0, i.e. row i of the relabelled CSR(A^T) (of
+    // CSR(A) itself when the pattern is symmetric).
+    const int32_t* brow;
+    const int32_t* bcol;
+    const float* bw;
 };
 
 // Grid-stride over the nodes; one atomic per block for the magnitude bound.
@@ -166,13 +172,14 @@ __device__ __forceinline__ bool bound_quiet(double ub, const RowData& d, const S
     return ub + resid_err(d.opd) < 0.999 * S.thr * S.epsp * d.sp;
 }
 // An update of zhat'_i by delta (mag >= |delta|) adds a_ji mag to the bound of
-// every neighbour j (the pattern is symmetric: the columns of row i).  The
-// whole wave takes the arcs [beg, end), U loads in flight per lane (the
+// every row j that reads it (row i of S.brow/S.bcol/S.bw).  The whole wave
+// takes the arcs [beg, end) of that row, U loads in flight per lane (the
 // atomics return nothing).  Inside a merged-tail launch the tail's own rows
 // collect in ub_tail, since they may be computing their bounds concurrently.
 template <int U, bool SHADOW>
-__device__ __forceinline__ void bound_arcs(const SorState& S, const int32_t* __restrict__ pcol,
-                                           const float* __restrict__ pw, int beg, int end, double mag) {
+__device__ __forceinline__ void bound_arcs(const SorState& S, int beg, int end, double mag) {
+    const int32_t* __restrict__ pcol = S.bcol;
+    const float* __restrict__ pw = S.bw;
     for (int k0 = beg + lane_id(); k0 < end; k0 += 64 * U) {
         int j[U];
         double a[U];
@@ -390,8 +397,8 @@ __device__ __forceinline__ void sor_light_tile(int64_t tix, int md, const TileVi
         for (uint64_t rem = um; rem; rem &= rem - 1) {
             const int l = __builtin_ctzll(rem);
             const int64_t i = r0 + l;
-            const int b = prow_ptr[i], e = prow_ptr[i + 1];
-            bound_arcs<4, SHADOW>(S, pcol, pw, b, e, __shfl(mag, l, 64));
+            const int b = S.brow[i], e = S.brow[i + 1];
+            bound_arcs<4, SHADOW>(S, b, e, __shfl(mag, l, 64));
             adds += static_cast<unsigned long long>(e - b);
         }
         if (adds && lane == 0) stripe_add(stats, 5, adds);  // counter 5: bound additions
@@ -581,8 +588,8 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
         }
         // an updated heavy row raises its neighbours' bounds, the whole wave taking its arcs
         if (SKIP && md >= 1 && __shfl(fin_upd, 0, 64)) {
-            bound_arcs<16, SHADOW>(S, pcol, pw, prow_ptr[row], prow_ptr[row + 1], __shfl(mag, 0, 64));
-            if (lane == 0) stripe_add(stats, 5, static_cast<unsigned long long>(prow_ptr[row + 1] - prow_ptr[row]));
+            bound_arcs<16, SHADOW>(S, S.brow[row], S.brow[row + 1], __shfl(mag, 0, 64));
+            if (lane == 0) stripe_add(stats, 5, static_cast<unsigned long long>(S.brow[row + 1] - S.brow[row]));
         }
         return;
     }
