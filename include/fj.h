@@ -432,6 +432,15 @@ typedef struct {
 } fj_batch_info;
 fj_status fj_batch_get_info(const fj_batch* b, fj_batch_info* out);
 
+/* Set the launch parameters fj_batch_tune picks by hand: 64-arc chunks in
+ * flight per light tile of the union (union_chunks: 2, 4 or 8) and arcs in
+ * flight per wave of the multi-vector rows (multi_arcs: 4, 8 or 16); 0 leaves
+ * a parameter as it is.
+ * Neither changes the sums, so results stay bit for bit the same.  A recorded
+ * hipGraph is recorded again with them.  Errors: FJ_ERR_INVALID_ARGUMENT,
+ * FJ_ERR_HIP. */
+fj_status fj_batch_set_launch(fj_batch* b, int32_t union_chunks, int32_t multi_arcs);
+
 /* Set the relaxation factor per item group by hand (each in (0,2); a value <= 0
  * leaves that group unchanged) and drop any recorded hipGraph, so that
  * fj_solve_batched enqueues the kernels directly with the current budget. */

@@ -234,34 +234,99 @@ __device__ __forceinline__ bool mrhs_active(const MState& S, int l) {
 }
 
 // active lane l: sum over arcs [beg, end) of a_e * zh[col_e][l], U arcs in
-// flight (a tuned launch parameter); added in arc order whatever U is
+// flight (a tuned launch parameter); added in arc order whatever U is.  The
+// arc range is the same in every lane: taken into scalar registers, the
+// column indices (and weights) arrive by scalar loads, the next U while the
+// current U gathers are in flight, and each gather is one coalesced row of k
+// values.  The last fewer than U arcs go in one step of B arcs (B the
+// smallest power of two >= their count), the indices past the end clamped to
+// the last arc and left out of the sum.
+template <int B, bool W>
+__device__ __forceinline__ double mrhs_arc_tail(double acc, int e, int end, const int32_t* __restrict__ pcol,
+                                                const float* __restrict__ pw, const double* __restrict__ zl, int k) {
+    int j[B];
+    float a[B];
+    double v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+        const int q = min(e + u, end - 1);
+        j[u] = pcol[q];
+        a[u] = W ? pw[q] : 1.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = zl[static_cast<int64_t>(j[u]) * k];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+        if (e + u < end) acc += static_cast<double>(a[u]) * v[u];
+    return acc;
+}
+template <int U, bool W>
+__device__ __forceinline__ double mrhs_arc_sum_w(int beg, int end, const int32_t* __restrict__ pcol,
+                                                 const float* __restrict__ pw, const double* __restrict__ zl, int k) {
+    double acc = 0.0;
+    int e = beg;
+    if (e + U <= end) {
+        int jn[U];
+        float an[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            jn[u] = pcol[e + u];
+            an[u] = W ? pw[e + u] : 1.0f;
+        }
+        while (true) {
+            double v[U];
+            float a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[u] = zl[static_cast<int64_t>(jn[u]) * k];
+                a[u] = an[u];
+            }
+            e += U;
+            const bool more = e + U <= end;
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    jn[u] = pcol[e + u];
+                    an[u] = W ? pw[e + u] : 1.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += static_cast<double>(a[u]) * v[u];
+            if (!more) break;
+        }
+    }
+    const int rem = end - e;  // 0 <= rem < U
+    if (rem <= 0) return acc;
+    if (U > 8 && rem > 8) return mrhs_arc_tail<(U > 8 ? 16 : 1), W>(acc, e, end, pcol, pw, zl, k);
+    if (U > 4 && rem > 4) return mrhs_arc_tail<(U > 4 ? 8 : 1), W>(acc, e, end, pcol, pw, zl, k);
+    if (rem > 2) return mrhs_arc_tail<4, W>(acc, e, end, pcol, pw, zl, k);
+    if (rem > 1) return mrhs_arc_tail<2, W>(acc, e, end, pcol, pw, zl, k);
+    return mrhs_arc_tail<1, W>(acc, e, end, pcol, pw, zl, k);
+}
 template <int U>
 __device__ __forceinline__ double mrhs_arc_sum(int beg, int end, const int32_t* __restrict__ pcol,
                                                const float* __restrict__ pw, const double* __restrict__ zh, int k,
                                                int l, bool act) {
-    double acc = 0.0;
-    int e = beg;
-    for (; e + U - 1 < end; e += U) {
-        int j[U];
-        double a[U], v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            j[u] = pcol[e + u];
-            a[u] = pw ? pw[e + u] : 1.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = act ? zh[static_cast<int64_t>(j[u]) * k + l] : 0.0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc += a[u] * v[u];
-    }
-    for (; e < end; ++e) {
-        int j = pcol[e];
-        double a = pw ? pw[e] : 1.0;
-        if (act) acc += a * zh[static_cast<int64_t>(j) * k + l];
-    }
-    return acc;
+    beg = __builtin_amdgcn_readfirstlane(beg);
+    end = __builtin_amdgcn_readfirstlane(end);
+    if (!act) return 0.0;
+    return pw ? mrhs_arc_sum_w<U, true>(beg, end, pcol, pw, zh + l, k)
+              : mrhs_arc_sum_w<U, false>(beg, end, pcol, pw, zh + l, k);
 }
 
+// the update of row i, vector l, with zhat'[i][l] and s'[i][l] already loaded
+__device__ __forceinline__ bool mrhs_row_with(int64_t i, int l, double sum, const MState& S, double z, double sp,
+                                              bool* nf, bool act) {
+    if (!act) return false;
+    const int64_t q = i * S.k + l;
+    double r = sp - S.popd[i] * z + sum;
+    *nf = !isfinite(r);
+    if (fabs(r) > S.thr * S.epsp * sp) {
+        S.zh[q] = z + S.omega * r * S.pinv[i];
+        return true;
+    }
+    return false;
+}
 __device__ __forceinline__ bool mrhs_row(int64_t i, int l, double sum, const MState& S, bool* nf, bool act) {
     if (!act) return false;
     const int64_t q = i * S.k + l;
@@ -283,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, 
                                                        const int* __restrict__ done, const int* __restrict__ all_done,
                                                        int* bad) {
     if (*all_done || *done) return;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (wv < tv.nchunks) {
         const int64_t cidx = tv.c0 + wv;
@@ -299,9 +364,16 @@ __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, 
     const int b = prow_ptr[i], e = prow_ptr[i + 1];
     if (e - b > kArcBudget) return;  // heavy: chunks + k_msor_heavy
     const bool act = mrhs_active(S, lane);
+    // the row's own values load before the gathers (no row of the class
+    // reads another, so nothing writes them meanwhile)
+    double z = 0.0, sp = 0.0;
+    if (act) {
+        z = S.zh[i * S.k + lane];
+        sp = S.sp[i * S.k + lane];
+    }
     double acc = mrhs_arc_sum<U>(b, e, pcol, pw, S.zh, S.k, lane, act);
     bool nf = false;
-    bool u = mrhs_row(i, lane, acc, S, &nf, act);
+    bool u = mrhs_row_with(i, lane, acc, S, z, sp, &nf, act);
     const unsigned long long um = __ballot(u);
     if (um && lane == 0) {
         flag_set(upd);
@@ -314,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_msor_heavy(TileView tv, MState S, co
                                                        int* upd, const int* __restrict__ done,
                                                        const int* __restrict__ all_done, int* bad) {
     if (*all_done || *done) return;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
     const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
@@ -687,7 +759,7 @@ struct fj_batch {
     std::vector<double> tune_ms;
     // launch parameters (set by the tuner): 64-arc chunks in flight per light
     // tile of the union, arcs in flight per lane of the multi-vector rows
-    int nch = 4, mu = 4;
+    int nch = 4, mu = 8;
     int cache_hit = 0;
     // caller-bound inputs and outputs (fj_batch_bind)
     bool bound = false;
@@ -874,7 +946,7 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
                          b->vdone + slot, b->vupd + slot};
                 TileView tv = tile_view(G.g.tiles_p, k);
                 const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
-                auto kern = b->mu == 2 ? k_msor_class<2> : b->mu == 8 ? k_msor_class<8> : k_msor_class<4>;
+                auto kern = b->mu == 4 ? k_msor_class<4> : b->mu == 16 ? k_msor_class<16> : k_msor_class<8>;
                 hipLaunchKernelGGL(kern, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, st,
                                    tv, rb, re, G.g.prow_ptr, G.g.pcol, G.g.pw, S, G.partial, b->upd + slot,
                                    b->done + slot, b->all_done, b->bad);
@@ -1171,7 +1243,7 @@ fj_status record_graph(fj_batch* b) {
 // direction; eps, c, sigma) starts from them instead of timing candidates.
 struct TunedEntry {
     std::vector<double> slot_omega;
-    int nch = 4, mu = 4;
+    int nch = 4, mu = 8;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TunedEntry> g_tune_cache;
@@ -1279,7 +1351,7 @@ extern "C" fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_
     }
     if (!hit) {
         b->nch = 4;
-        b->mu = 4;
+        b->mu = 8;
         // sweeps[q][slot]: sweeps slot needed with candidate q (0: did not converge)
         std::vector<std::vector<int>> sweeps(n_omegas);
         for (int q = 0; q < n_omegas; ++q) {
@@ -1325,11 +1397,11 @@ extern "C" fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_
         if (rc) return rc;
         // Launch parameters at the chosen omegas and budget, one at a time:
         // 64-arc chunks in flight per light tile of the union (2, 4, 8), then
-        // arcs in flight per lane of the multi-vector rows (2, 4, 8).  Either
+        // arcs in flight per wave of the multi-vector rows (4, 8, 16).  Either
         // leaves the sums, hence the result, unchanged.
         const int run_budget = budget + 1;
         double best_ms = 0.0;
-        rc = time_solve(b, st, run_budget, &best_ms);  // nch = mu = 4
+        rc = time_solve(b, st, run_budget, &best_ms);  // nch = 4, mu = 8
         if (rc) return rc;
         const int cand[2] = {2, 8};
         if (b->has_union) {
@@ -1344,8 +1416,8 @@ extern "C" fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_
             b->nch = best;
         }
         if (!b->M.empty()) {
-            int best = 4;
-            for (int c : cand) {
+            int best = 8;
+            for (int c : {4, 16}) {
                 b->mu = c;
                 double ms = 0.0;
                 rc = time_solve(b, st, run_budget, &ms);
@@ -1476,6 +1548,18 @@ extern "C" fj_status fj_solve_batched(fj_batch* b, fj_solve_stats* stats_dev, fj
     if (metrics_dev)
         FJ_HIP(hipMemcpyAsync(metrics_dev, b->mets, sizeof(fj_metrics_out) * b->total_k, hipMemcpyDeviceToDevice, st));
     return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_set_launch(fj_batch* b, int32_t union_chunks, int32_t multi_arcs) {
+    const bool ok_u = union_chunks == 0 || union_chunks == 2 || union_chunks == 4 || union_chunks == 8;
+    const bool ok_m = multi_arcs == 0 || multi_arcs == 4 || multi_arcs == 8 || multi_arcs == 16;
+    if (!b || !ok_u || !ok_m) {
+        set_error("fj_batch_set_launch: need a batch, union_chunks in {0, 2, 4, 8} and multi_arcs in {0, 4, 8, 16}");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    if (union_chunks) b->nch = union_chunks;
+    if (multi_arcs) b->mu = multi_arcs;
+    return b->exec ? record_graph(b) : FJ_OK;
 }
 
 extern "C" fj_status fj_batch_set_omegas(fj_batch* b, double omega_undirected, double omega_directed,

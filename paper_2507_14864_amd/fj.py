@@ -451,6 +451,8 @@ def _batch_lib():
         L.fj_batch_get_info.restype = i32
         L.fj_batch_set_omegas.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.fj_batch_set_omegas.restype = i32
+        L.fj_batch_set_launch.argtypes = [vp, i32, i32]
+        L.fj_batch_set_launch.restype = i32
         L.fj_solve_batched.argtypes = [vp, vp, vp, vp]
         L.fj_solve_batched.restype = i32
         L.fj_batch_tune_cache_clear.argtypes = []
@@ -520,6 +522,12 @@ class Batch:
         arr = (ctypes.c_double * len(omegas))(*omegas)
         _check(_batch_lib().fj_batch_tune(self._h, arr, len(omegas), _stream()))
         return self.info()
+
+    def set_launch(self, union_chunks=0, multi_arcs=0):
+        """Override the tuned launch parameters (union_chunks 2, 4 or 8;
+        multi_arcs 4, 8 or 16; 0 keeps); a recorded graph is recorded again.
+        Results are unchanged bit for bit."""
+        _check(_batch_lib().fj_batch_set_launch(self._h, int(union_chunks), int(multi_arcs)))
 
     def set_omegas(self, undirected=0.0, directed=0.0, multi=0.0):
         """Per-group relaxation factors (<= 0 keeps a group's value); drops

@@ -241,7 +241,7 @@ def test_tuned_shape_is_reused_by_a_batch_of_the_same_shape():
         _fill(B, single, multi, k)
         info = B.tune([1.2, 1.5])
         assert info["cache_hit"] == trial, info
-        assert info["union_chunks_in_flight"] in (2, 4, 8) and info["multi_arcs_in_flight"] in (2, 4, 8)
+        assert info["union_chunks_in_flight"] in (2, 4, 8) and info["multi_arcs_in_flight"] in (4, 8, 16)
         stats, _ = B.solve()
         assert all(st["certified"] == 1 for st in stats)
         outs.append((info, [B.output(i).cpu().numpy().copy() for i in range(len(single) + 1)]))
@@ -252,3 +252,39 @@ def test_tuned_shape_is_reused_by_a_batch_of_the_same_shape():
         assert i0[key] == i1[key], key
     for a, b in zip(z0, z1):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_launch_parameters_leave_results_bit_identical(weighted):
+    """Arcs in flight per wave (4, 8, 16) and 64-arc chunks per union tile
+    (2, 4, 8) change only how the gathers are issued: the arc sums run in arc
+    order with every setting, so the replays agree bit for bit.  Row lengths
+    of the multi-vector graph (k = 64, and k = 5 with idle lanes) cover every
+    remainder below 16 and rows above the light-row budget."""
+    import paper_2507_14864_amd as fj
+    single, _ = _items()
+    multi = synth.chung_lu(20000, 150000, 2.1, 530, weighted=weighted)
+    deg = np.diff(multi.row_ptr)
+    assert set(range(1, 16)) <= set((deg % 16).tolist()) and deg.max() > 256
+    for k in (64, 5):
+        B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+        _fill(B, single, multi, k)
+        B.tune([1.3, 1.5])
+        ref = None
+        for nch, mu in ((4, 8), (2, 4), (8, 16), (4, 16), (2, 8)):
+            B.set_launch(nch, mu)
+            assert (B.info()["union_chunks_in_flight"], B.info()["multi_arcs_in_flight"]) == (nch, mu)
+            stats, mets = B.solve()
+            out = [B.output(i).cpu().numpy().copy() for i in range(len(single) + 1)]
+            assert all(s["certified"] == 1 for s in stats)
+            if ref is None:
+                ref = (out, [s["rounds"] for s in stats], mets)
+                continue
+            for i in range(len(out)):
+                assert np.array_equal(out[i], ref[0][i]), (k, nch, mu, i)
+            assert [s["rounds"] for s in stats] == ref[1]
+            assert mets == ref[2]
+        B.close()
+    with pytest.raises(fj.FJError):
+        B2 = fj.Batch([_dev(single[0])], [1], eps=EPS)
+        B2.set_launch(3, 8)
