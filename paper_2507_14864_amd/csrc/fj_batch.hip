@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
     if (*all_done) return;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     const double* __restrict__ zh = S.zh;
     auto arc = [&](int k) {
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_usor_heavy(TileView tv, SorState S, 
                                                        const int* __restrict__ done, const int* __restrict__ all_done,
                                                        int* bad) {
     if (*all_done) return;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     const int32_t row = tv.heavy_row[hh];
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, 
                                                        const int* __restrict__ done, const int* __restrict__ all_done,
                                                        int* bad) {
     if (*all_done || *done) return;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (wv < tv.nchunks) {
         const int64_t cidx = tv.c0 + wv;
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_msor_heavy(TileView tv, MState S, co
                                                        int* upd, const int* __restrict__ done,
                                                        const int* __restrict__ all_done, int* bad) {
     if (*all_done || *done) return;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_urows_tiles(TileView tv, const int32
                                                         double* partial, double* out) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (wv < tv.nchunks) {
         const int64_t cidx = tv.c0 + wv;
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_urows_heavy(TileView tv, const doubl
                                                         const double* __restrict__ z, const double* __restrict__ opd,
                                                         double c, double epsp, const double* __restrict__ partial,
                                                         double* out) {
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
@@ -591,10 +591,13 @@ __global__ __launch_bounds__(kBlock) void k_mresults(int64_t n, int k, const int
                                                      const double* __restrict__ z, double c, double epsp,
                                                      const double* __restrict__ means, double* part, int pass) {
     __shared__ double lds[kWavesPerBlock][64][6];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t W = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
     double a[6] = {0, 0, 0, 0, 0, 0};
     const double mean = (pass == 1 && lane < k) ? means[lane] : 0.0;
+    // the row is wave-uniform: its arc range and column indices come by
+    // scalar loads, kU value rows in flight per step, added in arc order
+    constexpr int kU = 8;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; i < n; i += W) {
         if (lane >= k) continue;
         const double zi = z[i * k + lane];
@@ -605,12 +608,24 @@ __global__ __launch_bounds__(kBlock) void k_mresults(int64_t n, int k, const int
         }
         const double si = s[i * k + lane];
         double sz = 0.0, sd = 0.0;
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            const int64_t j = col[e];
-            const double aw = w ? static_cast<double>(w[e]) : 1.0;
-            const double zj = z[j * k + lane];
-            sz += aw * zj;
-            sd += aw * (zi - zj) * (zi - zj);
+        const int end = __builtin_amdgcn_readfirstlane(row_ptr[i + 1]);
+        for (int e = __builtin_amdgcn_readfirstlane(row_ptr[i]); e < end; e += kU) {
+            int j[kU];
+            double aw[kU], zj[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int q = min(e + u, end - 1);  // past the end: clamped, left out
+                j[u] = col[q];
+                aw[u] = w ? static_cast<double>(w[q]) : 1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) zj[u] = z[static_cast<int64_t>(j[u]) * k + lane];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (e + u < end) {
+                    sz += aw[u] * zj[u];
+                    sd += aw[u] * (zi - zj[u]) * (zi - zj[u]);
+                }
         }
         const double r = si - opd[i] * zi + sz;
         double ratio = fabs(r) / (epsp * (si + c));

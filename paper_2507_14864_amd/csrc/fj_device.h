@@ -7,6 +7,10 @@
 namespace fj {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+// this wave's index in its block, in a scalar register: the compiler then
+// treats everything indexed by it (a row, a tile, a chunk) as wave-uniform
+// and loads it with scalar loads instead of 64 lanes of the same address
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // index of this lane among the set lanes of `mask` below it
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
@@ -53,7 +57,7 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* lds /*[NT/64]*/) {
     v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (lane_id() == 0) lds[w] = v;
     __syncthreads();
     double t = 0.0;

@@ -268,7 +268,7 @@ __device__ __forceinline__ int jp_count_higher(const int32_t* __restrict__ ptr, 
 __global__ void k_jp_count(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                            const int32_t* __restrict__ t_row_ptr, const int32_t* __restrict__ t_col, int directed,
                            const uint64_t* __restrict__ key, int32_t* wait, int32_t* ready, int* ready_count) {
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
     if (w >= n) return;  // uniform across the wave
     const int32_t v = static_cast<int32_t>(w);
     const uint64_t kv = key[v];
@@ -314,7 +314,7 @@ __global__ void k_jp_level(int32_t count, const int32_t* __restrict__ row_ptr, c
                            const int32_t* __restrict__ t_row_ptr, const int32_t* __restrict__ t_col, int directed,
                            const uint64_t* __restrict__ key, int32_t* colour, int32_t* wait,
                            const int32_t* __restrict__ ready, int32_t* next, int* next_count) {
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
     if (w >= count) return;  // uniform across the wave
     const int32_t v = ready[w];
     const uint64_t kv = key[v];
@@ -335,7 +335,7 @@ __global__ void k_jp_level(int32_t count, const int32_t* __restrict__ row_ptr, c
 __global__ __launch_bounds__(256) void k_merge_coupling(int64_t r0, int64_t n, const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col, const float* __restrict__ w,
                                                         const double* __restrict__ opd, unsigned long long* out) {
-    const int64_t i = r0 + static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t i = r0 + static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
     if (i >= n) return;  // uniform across the wave
     double s = 0.0;
     for (int32_t k = row_ptr[i] + lane_id(); k < row_ptr[i + 1]; k += 64)

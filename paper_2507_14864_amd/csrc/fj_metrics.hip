@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_metrics_edges(TileView tv, const int
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_z[kWavesPerBlock][64];
     __shared__ double lds[kWavesPerBlock];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     double acc = 0.0, acc1 = 0.0, acc2 = 0.0;
     auto arc = [&](double zi, int64_t i, int k) {
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_stress_tiles(TileView tv, const int3
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
     __shared__ double s_z[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (wv < tv.nchunks) {
         const int64_t c = tv.c0 + wv;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_stress_heavy(TileView tv, const doub
                                                          const double* __restrict__ z,
                                                          const double* __restrict__ partial, double* stress) {
     const int lane = lane_id();
-    const int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id();
     if (h >= tv.h1) return;
     double sum = 0.0;
     for (int32_t c = tv.heavy_chunk0[h] + lane; c < tv.heavy_chunk0[h + 1]; c += 64) sum += partial[c];

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_pow_tiles(TileView tv, const int32_t
                                                       double* partial) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     auto arc = [&](int k) { return (w ? static_cast<double>(w[k]) : 1.0) * v[col[k]]; };
     if (wv < tv.nchunks) {
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_pow_tiles(TileView tv, const int32_t
 __global__ __launch_bounds__(kBlock) void k_pow_heavy(TileView tv, const double* __restrict__ partial,
                                                       const double* __restrict__ rowscale, double* y) {
     const int lane = lane_id();
-    const int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id();
     if (h >= tv.h1) return;
     double sum = 0.0;
     for (int32_t c = tv.heavy_chunk0[h] + lane; c < tv.heavy_chunk0[h + 1]; c += 64) sum += partial[c];

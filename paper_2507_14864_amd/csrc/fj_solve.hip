@@ -88,7 +88,7 @@ __device__ __forceinline__ void block_max_count(double mx, int vc, double* part_
                                                 int slot) {
     __shared__ double s_mx[kWavesPerBlock];
     __shared__ long long s_vi[kWavesPerBlock];
-    const int wid = threadIdx.x >> 6;
+    const int wid = wave_id();
     mx = wave_max(mx);
     long long v = __popcll(__ballot(vc != 0));
     if (lane_id() == 0) { s_mx[wid] = mx; s_vi[wid] = v; }
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_certify_tiles(TileView tv, const int
                                                           double* partial, double* part_max, long long* part_viol) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     auto arc = [&](int k) {
         double a = w ? static_cast<double>(w[k]) : 1.0;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_certify_heavy(TileView tv, const dou
                                                           const double* __restrict__ opd, T* r_out,
                                                           const double* __restrict__ partial, double* part_max,
                                                           long long* part_viol, int slot0) {
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t h = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     RowOut ro{0.0, 0};
     if (h < tv.h1) {
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_push_light(TileView tv, const int32_
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ T s_cf[kWavesPerBlock][64];
     if (__atomic_load_n(prev_active, __ATOMIC_RELAXED) == 0) return;  // previous round changed nothing
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t tix = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (tix >= tv.ntiles) return;
     const int32_t r0 = tv.tile_start[tix];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_push_heavy(TileView tv, const int32_
                                                        const T* __restrict__ heavy_coef,
                                                        const int* __restrict__ prev_active) {
     if (__atomic_load_n(prev_active, __ATOMIC_RELAXED) == 0) return;
-    const int wid = threadIdx.x >> 6;
+    const int wid = wave_id();
     const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (c >= tv.nchunks) return;
     const int32_t hv = tv.chunk_heavy[c];
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_frontier_small(FrontierArgs F, const
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ T s_cf[kWavesPerBlock][64];
     const int cnt = F.cnt_cur[0];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
     unsigned long long pushes = 0, visits = 0;
     for (int64_t base = (static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid) * 64; base < cnt;
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kPBlock) void k_sor_persistent(SorArgs a) {
     __shared__ int s_pre[kPWaves][65];
     __shared__ double s_acc[kPWaves][64];
     __shared__ double s_red[kPWaves];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t gw = static_cast<int64_t>(blockIdx.x) * kPWaves + wid;
     const int64_t G = static_cast<int64_t>(gridDim.x) * kPWaves;
     unsigned epoch = 0;

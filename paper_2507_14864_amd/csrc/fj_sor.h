@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_tiles(TileView tv, const int32_t
     __shared__ double s_acc[kWavesPerBlock][64];
     __shared__ int s_flag[kWavesPerBlock][64];
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     const double* __restrict__ zh = S.zh;
     auto arc64 = [&](int k) {
@@ -393,11 +393,17 @@ __device__ __forceinline__ void sor_light_tile(int64_t tix, int md, const TileVi
         // the whole wave taking one row at a time
         if (sweep_row) S.ub[r0 + lane] = own_bound(rr, upd, S.omega, rd.opd);
         const double mag = upd ? change_mag(zn, rd.z) : 0.0;
+        // each updated row's range in the bound CSR, loaded by its own lane
+        // at once rather than row by row inside the loop
+        int bb = 0, be = 0;
+        if (upd) {
+            bb = S.brow[r0 + lane];
+            be = S.brow[r0 + lane + 1];
+        }
         unsigned long long adds = 0;
         for (uint64_t rem = um; rem; rem &= rem - 1) {
             const int l = __builtin_ctzll(rem);
-            const int64_t i = r0 + l;
-            const int b = S.brow[i], e = S.brow[i + 1];
+            const int b = __shfl(bb, l, 64), e = __shfl(be, l, 64);
             bound_arcs<4, SHADOW>(S, b, e, __shfl(mag, l, 64));
             adds += static_cast<unsigned long long>(e - b);
         }
@@ -508,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
     // other load so that the branches on it wait for nothing else
     int md = 0;
     if constexpr (SKIP) md = *mode;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const double* __restrict__ zh = S.zh;
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (wv < tv.nchunks) {  // heavy rows always gather FP64
@@ -679,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_heavy(TileView tv, SorState S, c
                                                       const int* prev, int* updated, int* bad,
                                                       unsigned long long* stats) {
     if (prev && __atomic_load_n(prev, __ATOMIC_RELAXED) == 0) return;
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];

@@ -103,7 +103,7 @@ __device__ __forceinline__ double block_arc_sum(int beg, int end, double* lds /*
         for (int j = 0; j < U; ++j) acc += a[j];
     }
     acc = wave_sum(acc);
-    const int w = threadIdx.x >> 6, nw = nt >> 6;
+    const int w = wave_id(), nw = nt >> 6;
     __syncthreads();
     if (lane_id() == 0) lds[w] = acc;
     __syncthreads();

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_s_prep(int64_t n, const double* __restr
         mn = fmin(mn, __shfl_xor(mn, o, 64));
         mx = fmax(mx, __shfl_xor(mx, o, 64));
     }
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (lane_id() == 0) { a[w] = sm; b[w] = mn; c[w] = mx; }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_rows(int64_t n, const int32_t* _
     const int lane = lane_id(), p = lane & 7;
     const int64_t groups = (n + 7) / 8;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
-    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); gi < groups;
+    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id(); gi < groups;
          gi += stride) {
         const int64_t i = gi * 8 + (lane >> 3);
         int b = 0, e = 0;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_chunks(TileView tv, const int32_
                                                       const float* __restrict__ w, const float* __restrict__ s32,
                                                       float* partial) {
     const int lane = lane_id();
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id();
     if (c >= tv.nchunks) return;
     const int64_t cidx = tv.c0 + c;
     const int beg = tv.chunk_beg[cidx], end = tv.chunk_end[cidx];
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_chunks(TileView tv, const int32_
 }
 __global__ __launch_bounds__(kBlock) void k_nbr_combine(TileView tv, const float* __restrict__ partial, float* rs) {
     const int lane = lane_id();
-    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id();
     if (hh >= tv.h1) return;
     float t = 0.f;
     for (int32_t q = tv.heavy_chunk0[hh] + lane; q < tv.heavy_chunk0[hh + 1]; q += 64) t += partial[q];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_rows16(int64_t n, const int32_t*
     const int lane = lane_id(), p = lane & 7, sub = p >> 1, half = p & 1;
     const int64_t groups = (n + 7) / 8;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
-    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); gi < groups;
+    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id(); gi < groups;
          gi += stride) {
         const int64_t i = gi * 8 + (lane >> 3);
         int b = 0, e = 0;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_agg16_chunks(TileView tv, const int3
                                                         const float* __restrict__ w, const uint16_t* __restrict__ X,
                                                         float* partial) {
     const int lane = lane_id(), half = lane & 1, sub = lane >> 1;
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id();
     if (c >= tv.nchunks) return;
     const int64_t cidx = tv.c0 + c;
     const int beg = tv.chunk_beg[cidx], end = tv.chunk_end[cidx];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_agg16_chunks(TileView tv, const int3
 __global__ __launch_bounds__(kBlock) void k_agg16_combine(TileView tv, const float* __restrict__ partial,
                                                          const float* __restrict__ invd, uint16_t* M) {
     const int lane = lane_id();
-    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id();
     if (hh >= tv.h1 || lane >= kMsg) return;
     float t = 0.f;
     for (int32_t q = tv.heavy_chunk0[hh]; q < tv.heavy_chunk0[hh + 1]; ++q) t += partial[static_cast<int64_t>(q) * kMsg + lane];
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_net_l1(NetIn I, uint16_t* __restrict
     __shared__ NetW W;
     load_weights(I.p, W);
     __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int wid = wave_id(), lane = lane_id(), li = lane & 15, kq = lane >> 4;
     const int64_t tiles = (I.n + 15) / 16;
     for (int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; tt < tiles;
          tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_net_l2(NetIn I, const uint16_t* __re
     __shared__ NetW W;
     load_weights(I.p, W);
     __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int wid = wave_id(), lane = lane_id(), li = lane & 15, kq = lane >> 4;
     const double lo = I.stats[1], hi = I.stats[2];
     const float c0 = I.p[kOffC0];
     const int64_t tiles = (I.n + 15) / 16;
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_net_bwd2(NetIn I, const uint16_t* __
     load_weights(I.p, W);
     load_weights_bwd(I.p, WB);
     __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int wid = wave_id(), lane = lane_id(), li = lane & 15, kq = lane >> 4;
     const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     f32x4 gW2[5][4];
 #pragma unroll
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_net_bwd1(NetIn I, const uint16_t* __
     load_weights(I.p, W);
     load_weights_bwd(I.p, WB);
     __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = lane_id(), li = lane & 15, kq = lane >> 4;
+    const int wid = wave_id(), lane = lane_id(), li = lane & 15, kq = lane >> 4;
     const int64_t wave = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     f32x4 gW1[4], gWp[4];
 #pragma unroll
@@ -819,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_fj_step_tiles(TileView tv, const int
                                                           const double* __restrict__ opd, double* partial, double* zout) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     auto f = [&](int k) { return (w ? static_cast<double>(w[k]) : 1.0) * zin[col[k]]; };
     if (wv < tv.nchunks) {
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(kBlock) void k_fj_step_tiles(TileView tv, const int
 __global__ __launch_bounds__(kBlock) void k_fj_step_heavy(TileView tv, const double* __restrict__ s,
                                                           const double* __restrict__ opd,
                                                           const double* __restrict__ partial, double* zout) {
-    const int wid = threadIdx.x >> 6, lane = lane_id();
+    const int wid = wave_id(), lane = lane_id();
     const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     if (hh >= tv.h1) return;
     double sum = 0.0;
