@@ -120,6 +120,16 @@ fj_status fj_graph_colours(const fj_graph* g, int32_t* colours, void* stream);
 #define FJ_SCHED_PUSH 1 /* frontier push rounds (Alg. 1 order relaxed to rounds), omega in (0,1] */
 #define FJ_SCHED_SOR 2  /* colour-ordered over-relaxed sweeps, omega in (0,2); needs FJ_GRAPH_COLOUR */
 
+/* Table 1 measures of an opinion vector (fj_metrics, fj_solve_opts.measures). */
+typedef struct {
+    double P;    /* polarization  sum_i (z_i - mean)^2                      (Table 1) */
+    double D;    /* disagreement  sum over edges of a_ij (z_i - z_j)^2; an undirected
+                    edge counts once, a directed arc once                  (Table 1) */
+    double I;    /* internal conflict sum_i (z_i - s_i)^2                    (Table 1) */
+    double C;    /* controversy   sum_i z_i^2                                (Table 1) */
+    double mean; /* 1^T z / n, the centring of Sec. 3.4 */
+} fj_metrics_out;
+
 typedef struct {
     double eps;   /* relative error target eps in (0,1) (Alg. 2 input) */
     double omega; /* relaxation factor (Alg. 3 input); 1 = BoundLocalIter */
@@ -168,6 +178,13 @@ typedef struct {
                                 below its update threshold keeps its value without gathering.
                                 It would not have updated: the result is bit for bit the one
                                 without skipping.  0 selects 0.05; negative: never */
+    fj_metrics_out* measures; /* [host] or NULL: also the Table 1 measures of the returned z, as
+                                fj_metrics gives them (within rounding: the sums run in another
+                                order).  FJ_SCHED_SOR forms D in the gather pass of its final
+                                certificate, from the differences of zhat' (the shift cancels in
+                                zhat'_i - zhat'_j), and only the node passes run after it; the
+                                other schedules run fj_metrics' passes on z.  Written on FJ_OK
+                                and FJ_ERR_NOT_CONVERGED.  fj_solve_batched ignores it */
 } fj_solve_opts;
 
 typedef struct {
@@ -247,15 +264,6 @@ fj_status fj_tune_omega(const fj_graph* g, const double* s, const fj_solve_opts*
                         void* ws, size_t ws_bytes, void* stream);
 
 /* --------------------------------------------------------------- measures */
-
-typedef struct {
-    double P;    /* polarization  sum_i (z_i - mean)^2                      (Table 1) */
-    double D;    /* disagreement  sum over edges of a_ij (z_i - z_j)^2; an undirected
-                    edge counts once, a directed arc once                  (Table 1) */
-    double I;    /* internal conflict sum_i (z_i - s_i)^2                    (Table 1) */
-    double C;    /* controversy   sum_i z_i^2                                (Table 1) */
-    double mean; /* 1^T z / n, the centring of Sec. 3.4 */
-} fj_metrics_out;
 
 size_t fj_metrics_workspace_bytes(const fj_graph* g);
 

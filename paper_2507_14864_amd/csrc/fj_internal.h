@@ -165,6 +165,15 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
                       hipStream_t st);
 size_t graph_ws_bytes(const fj_graph_desc* d, int32_t flags);
 
+// Measures for fj_solve_opts.measures (fj_metrics.hip), in a workspace of
+// measures_ws_bytes: all passes over z, or the node passes with D's per-block
+// sums over every stored arc already in part_d[nbd].
+size_t measures_ws_bytes(const fj_graph* g);
+fj_status measures_full(const fj_graph* g, const double* s, const double* z, void* ws, hipStream_t st,
+                        fj_metrics_out* out);
+fj_status measures_with_d(const fj_graph* g, const double* s, const double* z, const double* part_d, int64_t nbd,
+                          void* ws, hipStream_t st, fj_metrics_out* out);
+
 // Scan helper (fj_graph.hip): exclusive scan of int32 in -> out (may alias), n entries,
 // returns total through *total_dev (device int64) when not null. tmp: scan_tmp_bytes(n).
 size_t scan_tmp_bytes(int64_t n);

@@ -191,6 +191,20 @@ __global__ __launch_bounds__(1024) void k_metrics_final(const double* part_p, in
     }
 }
 
+// D from per-block sums formed elsewhere (the certificate's gather pass, over
+// every stored arc: dscale 0.5 on an undirected graph, where each edge is
+// stored twice), P from the centred pass
+__global__ __launch_bounds__(1024) void k_measures_final(const double* part_p, int64_t nbp, const double* part_d,
+                                                         int64_t nbd, double dscale, double* out) {
+    __shared__ double lds[16];
+    const double p = reduce_parts(part_p, nbp, 2, 0, lds);
+    const double d = reduce_parts(part_d, nbd, 1, 0, lds);
+    if (threadIdx.x == 0) {
+        out[kOutP] = p;
+        out[kOutD] = dscale * d;
+    }
+}
+
 // ------------------------------------------------------------------ stress
 // Per-node stress of Sec. 3.4: (z_i - s_i)^2 + sum_j a_ij (z_i - z_j)^2 over
 // row i of A.  Light tiles finish their rows; each heavy-row chunk writes its
@@ -364,6 +378,48 @@ extern "C" size_t fj_metrics_workspace_bytes(const fj_graph* g) {
     size_t cert = certify_ws_bytes(g);  // fj_certify shares this workspace
     return cv.bytes() > cert ? cv.bytes() : cert;
 }
+
+namespace fj {
+
+size_t measures_ws_bytes(const fj_graph* g) { return fj_metrics_workspace_bytes(g); }
+
+// fj_metrics without the argument checks, for fj_solve_opts.measures
+fj_status measures_full(const fj_graph* g, const double* s, const double* z, void* ws, hipStream_t st,
+                        fj_metrics_out* out) {
+    Carver cv(ws);
+    const MetricsLayout L = carve_metrics(cv, g);
+    double h[kOutSlots];
+    const fj_status rc = metrics_passes(g, s, z, 0.0, L, st, h);
+    if (rc != FJ_OK) return rc;
+    *out = fj_metrics_out{h[kOutP], h[kOutD], h[kOutI], h[kOutC], h[kOutMean]};
+    return FJ_OK;
+}
+
+// The measures with D's per-block sums already formed over every stored arc
+// (nbd of them in part_d); the node passes run here.
+fj_status measures_with_d(const fj_graph* g, const double* s, const double* z, const double* part_d, int64_t nbd,
+                          void* ws, hipStream_t st, fj_metrics_out* out) {
+    const int64_t n = g->n;
+    if (n == 0) {
+        *out = fj_metrics_out{0.0, 0.0, 0.0, 0.0, 0.0};
+        return FJ_OK;
+    }
+    Carver cv(ws);
+    const MetricsLayout L = carve_metrics(cv, g);
+    const unsigned nbn = nblocks_nodes(n);
+    hipLaunchKernelGGL(k_metrics_nodes, dim3(nbn), dim3(kBlock), 0, st, n, s, z, 0.0, L.part1);
+    hipLaunchKernelGGL(k_metrics_mean, dim3(1), dim3(1024), 0, st, L.part1, static_cast<int64_t>(nbn), n, L.out);
+    hipLaunchKernelGGL(k_metrics_centred, dim3(nbn), dim3(kBlock), 0, st, n, z, 0.0, L.out, L.part2);
+    hipLaunchKernelGGL(k_measures_final, dim3(1), dim3(1024), 0, st, L.part2, static_cast<int64_t>(nbn), part_d, nbd,
+                       g->directed ? 1.0 : 0.5, L.out);
+    double h[kOutSlots];
+    FJ_HIP(hipMemcpyAsync(h, L.out, sizeof(double) * kOutSlots, hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    *out = fj_metrics_out{h[kOutP], h[kOutD], h[kOutI], h[kOutC], h[kOutMean]};
+    return FJ_OK;
+}
+
+}  // namespace fj
 
 extern "C" fj_status fj_metrics(const fj_graph* g, const double* s, const double* z, fj_metrics_out* out, void* ws,
                                 size_t ws_bytes, void* stream) {

@@ -101,40 +101,75 @@ __device__ __forceinline__ void block_max_count(double mx, int vc, double* part_
     }
 }
 
-template <typename T>
+// MEAS: the same gathers also form the disagreement D of Table 1 over every
+// stored arc, a_ij (zh_i - zh_j)^2 per lane in its arcs' fixed order and a
+// fixed-order block sum into part_d[block] (the shift of zh cancels in the
+// difference).
+template <typename T, bool MEAS = false>
 __global__ __launch_bounds__(kBlock) void k_certify_tiles(TileView tv, const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ col,
                                                           const float* __restrict__ w, const double* __restrict__ s,
                                                           double c_res, double c_thr, double epsp,
                                                           const double* __restrict__ zh,
                                                           const double* __restrict__ opd, T* r_out,
-                                                          double* partial, double* part_max, long long* part_viol) {
+                                                          double* partial, double* part_max, long long* part_viol,
+                                                          double* part_d) {
     __shared__ int s_pre[kWavesPerBlock][65];
     __shared__ double s_acc[kWavesPerBlock][64];
+    __shared__ double s_z[MEAS ? kWavesPerBlock : 1][64];
+    __shared__ double s_red[kWavesPerBlock];
     const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
     auto arc = [&](int k) {
         double a = w ? static_cast<double>(w[k]) : 1.0;
         return a * zh[col[k]];
     };
+    double dacc = 0.0;
     RowOut ro{0.0, 0};
     if (wv < tv.nchunks) {
         int64_t cidx = tv.c0 + wv;
         int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
         int beg = tv.chunk_beg[cidx];
         int end = min(beg + kArcBudget, row_ptr[row + 1]);
-        double sum = chunk_sum(beg, end, arc);
+        double sum;
+        if constexpr (MEAS) {
+            const double zi = zh[row];
+            sum = chunk_sum(beg, end, [&](int k) {
+                const double a = w ? static_cast<double>(w[k]) : 1.0;
+                const double zj = zh[col[k]], d = zi - zj;
+                dacc += a * d * d;
+                return a * zj;
+            });
+        } else {
+            sum = chunk_sum(beg, end, arc);
+        }
         if (lane == 0) partial[cidx] = sum;
     } else if (wv - tv.nchunks < tv.ntiles) {
         int64_t tix = tv.t0 + (wv - tv.nchunks);
         if (tv.tile_heavy[tix] < 0) {
             int32_t r0 = tv.tile_start[tix];
             int nrows = tv.tile_start[tix + 1] - r0;
-            double sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+            double sum;
+            if constexpr (MEAS) {
+                if (lane < nrows) s_z[wid][lane] = zh[r0 + lane];
+                wave_sync_lds();
+                sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], [&](int k, int slot) {
+                    const double a = w ? static_cast<double>(w[k]) : 1.0;
+                    const double zj = zh[col[k]], d = s_z[wid][slot] - zj;
+                    dacc += a * d * d;
+                    return a * zj;
+                });
+            } else {
+                sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], arc);
+            }
             if (lane < nrows) ro = certify_row<T>(r0 + lane, sum, s, c_res, c_thr, epsp, zh, opd, r_out);
         }
     }
     block_max_count(ro.ratio, ro.viol, part_max, part_viol, blockIdx.x);
+    if constexpr (MEAS) {
+        const double t = block_sum<kBlock>(dacc, s_red);
+        if (threadIdx.x == 0) part_d[blockIdx.x] = t;
+    }
 }
 
 template <typename T>
@@ -648,6 +683,7 @@ struct SolveLayout {
     unsigned long long* hacc; unsigned long long* zmax_bits; double* zsh; int32_t* zqsh;
     double* ub; double* ub_tail; int* modes; unsigned long long* snaps;
     int32_t* fq[2][2]; int* fcnt; int* inq;  // frontier push: queues [parity][bucket], counters [parity][bucket]
+    double* part_d; void* mws;  // opts.measures: D per certificate block; the measures' own workspace
 };
 
 
@@ -687,6 +723,8 @@ SolveLayout carve_solve(Carver& cv, const fj_graph* g, int precision, bool front
     L.part_viol = cv.take<long long>(nb);
     L.cert_max = cv.take<double>(1);
     L.cert_viol = cv.take<long long>(1);
+    L.part_d = cv.take<double>(nb);
+    L.mws = cv.take<char>(measures_ws_bytes(g));
     if (frontier) {
         for (int par = 0; par < 2; ++par)
             for (int b = 0; b < 2; ++b) L.fq[par][b] = cv.take<int32_t>(n + 1);
@@ -776,16 +814,20 @@ void trace_cert(const char* sched, int64_t rounds, double max_ratio, long long v
 
 // c_res: shift already inside zh (residual of the shifted system); c_thr: shift
 // of the threshold h = eps' (s + c_thr)
-template <typename T>
+// MEAS: the gather pass also leaves D's per-block sums in L.part_d (blocks
+// returned in *d_blocks) for measures_with_d.
+template <typename T, bool MEAS = false>
 fj_status certify(const fj_graph* g, const double* s, double c_res, double c_thr, double epsp, const double* zh,
-                  T* r_out, const SolveLayout& L, hipStream_t st, double* max_ratio, long long* viol) {
+                  T* r_out, const SolveLayout& L, hipStream_t st, double* max_ratio, long long* viol,
+                  int64_t* d_blocks = nullptr) {
     const int64_t n = g->n;
     if (n > 0) {
         TileView tv = tile_view_all(g->tiles_a);
         unsigned nb1 = waves_to_blocks(tv.nchunks + tv.ntiles);
         unsigned nb2 = waves_to_blocks(tv.h1 - tv.h0);
-        hipLaunchKernelGGL(k_certify_tiles<T>, dim3(nb1), dim3(kBlock), 0, st, tv, g->row_ptr, g->col, g->w, s, c_res,
-                           c_thr, epsp, zh, g->opd, r_out, L.partial, L.part_max, L.part_viol);
+        if (d_blocks) *d_blocks = nb1;
+        hipLaunchKernelGGL((k_certify_tiles<T, MEAS>), dim3(nb1), dim3(kBlock), 0, st, tv, g->row_ptr, g->col, g->w, s,
+                           c_res, c_thr, epsp, zh, g->opd, r_out, L.partial, L.part_max, L.part_viol, L.part_d);
         if (nb2 > 0)
             hipLaunchKernelGGL(k_certify_heavy<T>, dim3(nb2), dim3(kBlock), 0, st, tv, s, c_res, c_thr, epsp, zh,
                                g->opd, r_out, L.partial, L.part_max, L.part_viol, static_cast<int>(nb1));
@@ -1271,6 +1313,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     std::vector<TileView> views(nc);
     for (int k = 0; k < nc; ++k) views[k] = tile_view(g->tiles_p, k);
     int64_t sweeps = 0, launches = 0, mirror_sweeps = 0;
+    int64_t d_blocks = 0;  // opts.measures: D's block sums from the last certificate
     int refinements = 0;
     bool converged = false, capped = false, diverged = false;
     double max_ratio = 0.0;
@@ -1491,7 +1534,10 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
         // the last sweep changed nothing, so its residuals were final; confirm in the original labels
         if (n > 0) hipLaunchKernelGGL(k_sor_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, L.zh, o->c, z, L.zh2);
         long long viol = 0;
-        fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L, st, &max_ratio, &viol);
+        fj_status rc = o->measures ? certify<double, true>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr),
+                                                           L, st, &max_ratio, &viol, &d_blocks)
+                                   : certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L,
+                                                     st, &max_ratio, &viol);
         if (rc) return rc;
         if (trace_on()) trace_cert("sor", sweeps, max_ratio, viol, refinements);
         if (viol == 0) { converged = true; break; }
@@ -1505,7 +1551,14 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     if (!converged) {
         if (n > 0) hipLaunchKernelGGL(k_sor_unshift, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, g->perm, L.zh, o->c, z, L.zh2);
         long long viol = 0;
-        fj_status rc = certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L, st, &max_ratio, &viol);
+        fj_status rc = o->measures ? certify<double, true>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr),
+                                                           L, st, &max_ratio, &viol, &d_blocks)
+                                   : certify<double>(g, s, o->c, o->c, epsp, L.zh2, static_cast<double*>(nullptr), L,
+                                                     st, &max_ratio, &viol);
+        if (rc) return rc;
+    }
+    if (o->measures) {  // D came with the final certificate; the node passes run on z
+        fj_status rc = measures_with_d(g, s, z, L.part_d, d_blocks, L.mws, st, o->measures);
         if (rc) return rc;
     }
     HostStats hs;
@@ -1678,6 +1731,10 @@ extern "C" fj_status fj_solve(const fj_graph* g, const double* s, const fj_solve
         rc = solve_push<double>(g, s, o, epsp, z, L, &local, st, cap);
     else
         rc = solve_push<float>(g, s, o, epsp, z, L, &local, st, cap);
+    if (o->measures && sched != FJ_SCHED_SOR && (rc == FJ_OK || rc == FJ_ERR_NOT_CONVERGED)) {
+        const fj_status mrc = measures_full(g, s, z, L.mws, st, o->measures);
+        if (mrc != FJ_OK) rc = mrc;
+    }
     local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = local;
     return rc;

@@ -56,7 +56,7 @@ class SolveOpts(ctypes.Structure):
                 ("max_edge_visits", ctypes.c_int64), ("max_refinements", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("z0", ctypes.c_void_p), ("profile", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("gather_bits", ctypes.c_int32), ("push_scatter", ctypes.c_int32),
-                ("no_tail_merge", ctypes.c_int32), ("skip_below", ctypes.c_double)]
+                ("no_tail_merge", ctypes.c_int32), ("skip_below", ctypes.c_double), ("measures", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -260,11 +260,13 @@ def solve(graph: Graph, s: torch.Tensor, eps: float = 1e-4, omega: float = 1.0, 
           max_refinements: int = -1, check_every: int = 8, z0: Optional[torch.Tensor] = None,
           out: Optional[torch.Tensor] = None, profile: bool = False, persistent: bool = False,
           gather_bits: int = 0, tail_merge: bool = True, push_scatter: bool = False,
-          skip_below: float = 0.0):
+          skip_below: float = 0.0, measures: bool = False):
     """ImprovedBLISOR on the GPU.  Returns (z, stats dict).
 
-    Raises FJNotConverged (with .z and .stats) when the certificate could not
-    be reached."""
+    measures: also the Table 1 measures of z in stats["measures"]
+    (fj_solve_opts.measures; the SOR schedule forms D in its final
+    certificate's gather pass).  Raises FJNotConverged (with .z and .stats)
+    when the certificate could not be reached."""
     n = graph.n
     _dev_ptr(s, torch.float64, n, "s")
     if z0 is not None:
@@ -273,6 +275,9 @@ def solve(graph: Graph, s: torch.Tensor, eps: float = 1e-4, omega: float = 1.0, 
     _dev_ptr(z, torch.float64, n, "out")
     opts = make_opts(eps, omega, c, sigma, precision, schedule, max_edge_visits, max_refinements,
                      check_every, z0, profile, persistent, gather_bits, tail_merge, push_scatter, skip_below)
+    mo = MetricsOut() if measures else None
+    if mo is not None:
+        opts.measures = ctypes.addressof(mo)
     L = lib()
     nbytes = L.fj_solve_workspace_bytes(graph.handle, ctypes.byref(opts))
     if graph._solve_ws is None or graph._solve_ws.numel() < nbytes:
@@ -282,10 +287,13 @@ def solve(graph: Graph, s: torch.Tensor, eps: float = 1e-4, omega: float = 1.0, 
     rc = L.fj_solve(graph.handle, ctypes.c_void_p(s.data_ptr()), ctypes.byref(opts),
                     ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                     ctypes.byref(st), _stream())
+    stats = st.to_dict()
+    if mo is not None and rc in (FJ_OK, FJ_ERR_NOT_CONVERGED):
+        stats["measures"] = {k: getattr(mo, k) for k, _ in mo._fields_}
     if rc == FJ_ERR_NOT_CONVERGED:
-        raise FJNotConverged(rc, L.fj_last_error().decode(errors="replace"), z, st.to_dict())
+        raise FJNotConverged(rc, L.fj_last_error().decode(errors="replace"), z, stats)
     _check(rc)
-    return z, st.to_dict()
+    return z, stats
 
 
 def _metrics_ws(graph: Graph) -> torch.Tensor:

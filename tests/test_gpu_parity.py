@@ -117,6 +117,56 @@ def test_metrics_match_oracle_on_same_z_and_are_reproducible():
             assert abs(m1[k] - mo[k]) <= 1e-12 * abs(mo[k]), (k, m1[k], mo[k])
 
 
+@pytest.mark.parametrize("directed,weighted,schedule", [(False, False, "sor"), (False, True, "sor"),
+                                                        (True, True, "sor"), (True, False, "push"),
+                                                        (False, True, "push")])
+def test_solve_measures_match_fj_metrics_and_oracle(directed, weighted, schedule):
+    """fj_solve_opts.measures: on the SOR schedule D comes from the final
+    certificate's gather pass (every stored arc, the differences of zhat',
+    halved on an undirected graph), P/I/C/mean from the node passes on the
+    returned z; other schedules run fj_metrics' passes.  P, I, C and the mean
+    are the same kernels on the same z as fj_metrics, so bit for bit; D sums
+    in another order, so within rounding; all against the oracle's measures of
+    that z.  Heavy rows (over 256 arcs) are present, so the chunk waves add
+    their arcs too."""
+    fj = fjmod()
+    g = synth.chung_lu(60000, 480000, 2.1, 951 + directed, directed=directed, weighted=weighted)
+    assert np.diff(g.row_ptr).max() > 256
+    s = synth.opinions(g.n, "bimodal", 953)
+    G = fj.Graph.from_host(g, DEV, colour=schedule == "sor")
+    sd = to_dev(s)
+    z, st = fj.solve(G, sd, eps=1e-5, omega=1.0 if directed or schedule == "push" else 1.5, schedule=schedule,
+                     measures=True)
+    assert st["certified"] == 1
+    m = st["measures"]
+    ref = fj.metrics(G, sd, z)
+    for k in ("P", "I", "C", "mean"):
+        assert m[k] == ref[k], k
+    assert abs(m["D"] - ref["D"]) <= 1e-12 * abs(ref["D"])
+    mo = oracle.metrics(g, s, z.cpu().numpy())
+    for k in ("P", "D", "I", "C", "mean"):
+        assert abs(m[k] - mo[k]) <= 1e-12 * abs(mo[k]), (k, m[k], mo[k])
+    # the same z and statistics as without the option
+    z2, st2 = fj.solve(G, sd, eps=1e-5, omega=1.0 if directed or schedule == "push" else 1.5, schedule=schedule)
+    assert torch.equal(z, z2) and st2["rounds"] == st["rounds"] and st2["max_ratio"] == st["max_ratio"]
+    assert "measures" not in st2
+
+
+def test_solve_measures_on_a_capped_solve():
+    """A solve stopped by its work cap still returns the measures of its last
+    estimate, with FJ_ERR_NOT_CONVERGED."""
+    fj = fjmod()
+    g = synth.chung_lu(20000, 160000, 2.3, 957)
+    s = synth.opinions(g.n, "uniform", 958)
+    G = fj.Graph.from_host(g, DEV, colour=True)
+    with pytest.raises(fj.FJNotConverged) as e:
+        fj.solve(G, to_dev(s), eps=1e-6, omega=1.5, schedule="sor", max_edge_visits=12 * (g.nnz + g.n),
+                 measures=True)
+    m = e.value.stats["measures"]
+    ref = fj.metrics(G, to_dev(s), e.value.z)
+    assert m["C"] == ref["C"] and abs(m["D"] - ref["D"]) <= 1e-12 * abs(ref["D"])
+
+
 def test_certificate_matches_oracle():
     fj = fjmod()
     g = synth.chung_lu(40000, 200000, 2.3, 31, directed=True, weighted=True)
