@@ -146,8 +146,16 @@ __global__ __launch_bounds__(kBlock) void k_metrics_edges(TileView tv, const int
 
 // single block: fixed-order sum of `cnt` partials with stride `stride` starting at `off`
 __device__ double reduce_parts(const double* part, int64_t cnt, int stride, int off, double* lds) {
-    double a = 0.0;
-    for (int64_t i = threadIdx.x; i < cnt; i += 1024) a += part[i * stride + off];
+    // eight independent sums per thread so that eight loads are in flight,
+    // then added in a fixed order
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = threadIdx.x;
+    for (; i + 7 * 1024 < cnt; i += 8 * 1024) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] += part[(i + u * 1024) * stride + off];
+    }
+    for (int u = 0; i < cnt; i += 1024, ++u) q[u] += part[i * stride + off];
+    double a = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
     a = wave_sum(a);
     if (lane_id() == 0) lds[threadIdx.x >> 6] = a;
     __syncthreads();

@@ -195,8 +195,22 @@ __global__ __launch_bounds__(1024) void k_certify_final(const double* part_max, 
                                                         double* out_max, long long* out_viol) {
     __shared__ double sm[16];
     __shared__ long long sv[16];
+    // eight loads of each array in flight per thread (max and count do not
+    // depend on the order)
     double m = 0.0; long long v = 0;
-    for (int64_t i = threadIdx.x; i < nb; i += 1024) { m = fmax(m, part_max[i]); v += part_viol[i]; }
+    int64_t i = threadIdx.x;
+    for (; i + 7 * 1024 < nb; i += 8 * 1024) {
+        double pm[8];
+        long long pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            pm[u] = part_max[i + u * 1024];
+            pv[u] = part_viol[i + u * 1024];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { m = fmax(m, pm[u]); v += pv[u]; }
+    }
+    for (; i < nb; i += 1024) { m = fmax(m, part_max[i]); v += part_viol[i]; }
     m = wave_max(m);
     v = wave_sum_ll(v);
     if (lane_id() == 0) { sm[threadIdx.x >> 6] = m; sv[threadIdx.x >> 6] = v; }
