@@ -221,20 +221,10 @@ __device__ __forceinline__ bool higher(uint64_t ku, int32_t u, uint64_t kv, int3
 // a node whose count is zero is ready: its colour is the smallest one unused
 // by those neighbours (all coloured already), after which it decrements the
 // counts of its lower-priority neighbours, and those reaching zero form the
-// next level.  One wave per node, so hubs are scanned 64 arcs at a time.
+// next level.  One wave per node, scanning eight 64-arc chunks per step.
 // Work is O(arcs) in total; the number of levels is the longest chain of
-// decreasing priority.
-
-// append the lanes with `take` set to list[*count ...]
-__device__ __forceinline__ void wave_append(bool take, int32_t v, int* count, int32_t* list) {
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    const int leader = __builtin_ctzll(m);
-    int base = 0;
-    if (lane_id() == leader) base = atomicAdd(count, __popcll(m));
-    base = __shfl(base, leader, 64);
-    if (take) list[base + lanes_below(m)] = v;
-}
+// decreasing priority (976 on the 10M-node graph), so most levels are small
+// and are enqueued in batches without a host read of their sizes.
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t x) {
 #pragma unroll
@@ -280,55 +270,105 @@ __global__ void k_jp_count(int64_t n, const int32_t* __restrict__ row_ptr, const
     }
 }
 
+// kJpChunks 64-arc chunks of v's adjacency per step: their loads (the
+// neighbour, its key, its colour) are in flight together, so a hub's row
+// costs a round trip per 512 arcs instead of per 64
+constexpr int kJpChunks = 8;
+
 __device__ __forceinline__ uint64_t jp_used(const int32_t* __restrict__ ptr, const int32_t* __restrict__ adj,
                                             int32_t v, uint64_t kv, const uint64_t* __restrict__ key,
                                             const int32_t* __restrict__ colour, int base) {
     uint64_t m = 0;
-    for (int32_t k = ptr[v] + lane_id(); k < ptr[v + 1]; k += 64) {
-        const int32_t u = adj[k];
-        if (higher(key[u], u, kv, v)) {
-            const int c = colour[u] - base;
-            if (c >= 0 && c < 64) m |= 1ull << c;
-        }
+    const int32_t b = ptr[v], e = ptr[v + 1];
+    for (int32_t k0 = b + lane_id(); k0 < e; k0 += 64 * kJpChunks) {
+        int32_t u[kJpChunks];
+        int c[kJpChunks];
+#pragma unroll
+        for (int j = 0; j < kJpChunks; ++j) u[j] = k0 + 64 * j < e ? adj[k0 + 64 * j] : -1;
+#pragma unroll
+        for (int j = 0; j < kJpChunks; ++j)
+            c[j] = u[j] >= 0 && higher(key[u[j]], u[j], kv, v) ? colour[u[j]] - base : -1;
+#pragma unroll
+        for (int j = 0; j < kJpChunks; ++j)
+            if (c[j] >= 0 && c[j] < 64) m |= 1ull << c[j];
     }
     return m;
 }
 
+// append, per lane, the values u[j] with take[j] set to list[*count ...]:
+// one atomic per wave for all of them
+template <int N>
+__device__ __forceinline__ void wave_append_n(const bool* take, const int32_t* u, int* count, int32_t* list) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) c += take[j] ? 1 : 0;
+    const int incl = wave_incl_scan(c);
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) return;
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(count, total);
+    base = __shfl(base, 0, 64) + incl - c;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (take[j]) list[base++] = u[j];
+}
+
+// the lower-priority neighbours of v lose one wait each; those reaching zero
+// join the next level (kJpChunks chunks per step, their atomics in flight
+// together)
 __device__ __forceinline__ void jp_release(const int32_t* __restrict__ ptr, const int32_t* __restrict__ adj,
                                            int32_t v, uint64_t kv, const uint64_t* __restrict__ key, int32_t* wait,
                                            int32_t* next, int* next_count) {
     const int32_t b = ptr[v], e = ptr[v + 1];
-    for (int32_t k0 = b; k0 < e; k0 += 64) {  // uniform trip count: wave_append needs every lane
-        const int32_t k = k0 + lane_id();
-        bool now_ready = false;
-        int32_t u = 0;
-        if (k < e) {
-            u = adj[k];
-            if (higher(kv, v, key[u], u)) now_ready = atomicSub(&wait[u], 1) == 1;
+    for (int32_t k0 = b; k0 < e; k0 += 64 * kJpChunks) {  // uniform trip count: the append needs every lane
+        int32_t u[kJpChunks];
+        bool lower[kJpChunks], ready[kJpChunks];
+#pragma unroll
+        for (int j = 0; j < kJpChunks; ++j) {
+            const int32_t k = k0 + 64 * j + lane_id();
+            u[j] = k < e ? adj[k] : -1;
         }
-        wave_append(now_ready, u, next_count, next);
+#pragma unroll
+        for (int j = 0; j < kJpChunks; ++j) lower[j] = u[j] >= 0 && higher(kv, v, key[u[j]], u[j]);
+#pragma unroll
+        for (int j = 0; j < kJpChunks; ++j) ready[j] = lower[j] && atomicSub(&wait[u[j]], 1) == 1;
+        wave_append_n<kJpChunks>(ready, u, next_count, next);
     }
 }
 
-__global__ void k_jp_level(int32_t count, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+// One priority level.  Its size is read on the device: counts[cur] holds it,
+// the next level's nodes are appended to counts[(cur + 1) % 3], and
+// counts[(cur + 2) % 3] (the size of the level before, no longer read) is
+// cleared for the level after; so levels can be enqueued back to back
+// without the host reading their sizes.  The waves stride over the level.
+// counts[3] adds up the coloured nodes, counts[4] the non-empty levels.
+__global__ void k_jp_level(int* counts, int cur, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                            const int32_t* __restrict__ t_row_ptr, const int32_t* __restrict__ t_col, int directed,
                            const uint64_t* __restrict__ key, int32_t* colour, int32_t* wait,
-                           const int32_t* __restrict__ ready, int32_t* next, int* next_count) {
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
-    if (w >= count) return;  // uniform across the wave
-    const int32_t v = ready[w];
-    const uint64_t kv = key[v];
-    for (int base = 0;; base += 64) {
-        uint64_t m = jp_used(row_ptr, col, v, kv, key, colour, base);
-        if (directed) m |= jp_used(t_row_ptr, t_col, v, kv, key, colour, base);
-        m = wave_or(m);
-        if (~m) {
-            if (lane_id() == 0) colour[v] = base + __builtin_ctzll(~m);
-            break;
-        }
+                           const int32_t* __restrict__ ready, int32_t* next) {
+    const int count = __builtin_amdgcn_readfirstlane(counts[cur]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[(cur + 2) % 3] = 0;
+        counts[3] += count;
+        if (count > 0) counts[4] += 1;
     }
-    jp_release(row_ptr, col, v, kv, key, wait, next, next_count);
-    if (directed) jp_release(t_row_ptr, t_col, v, kv, key, wait, next, next_count);
+    int* next_count = counts + (cur + 1) % 3;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id(); w < count; w += nw) {
+        const int32_t v = ready[w];
+        const uint64_t kv = key[v];
+        for (int base = 0;; base += 64) {
+            uint64_t m = jp_used(row_ptr, col, v, kv, key, colour, base);
+            if (directed) m |= jp_used(t_row_ptr, t_col, v, kv, key, colour, base);
+            m = wave_or(m);
+            if (~m) {
+                if (lane_id() == 0) colour[v] = base + __builtin_ctzll(~m);
+                break;
+            }
+        }
+        jp_release(row_ptr, col, v, kv, key, wait, next, next_count);
+        if (directed) jp_release(t_row_ptr, t_col, v, kv, key, wait, next, next_count);
+    }
 }
 
 // max over rows i >= r0 of sum_{arcs j >= r0} a_ij / (1 + d_i), one wave per row
@@ -743,8 +783,9 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     // Jones-Plassmann colouring, one priority level per launch (perm and iperm
     // hold the ready lists and cur1 the waiting counts until the relabelling
     // overwrites them)
-    int* counts = err + 8;  // [0] current level size, [1] next level size
-    FJ_HIP(hipMemsetAsync(counts, 0, sizeof(int) * 2, st));
+    // counts[0..2]: level sizes in rotation (k_jp_level), [3] coloured nodes, [4] levels
+    int* counts = err + 8;
+    FJ_HIP(hipMemsetAsync(counts, 0, sizeof(int) * 5, st));
     hipLaunchKernelGGL(k_jp_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, d->row_ptr, g->t_row_ptr, g->directed,
                        L.key, L.colour);
     hipLaunchKernelGGL(k_jp_count, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, d->row_ptr, d->col, g->t_row_ptr,
@@ -752,29 +793,37 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     int level = 0;
     FJ_HIP(hipMemcpyAsync(&level, counts, sizeof(int), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
-    int32_t* lin = L.perm;
-    int32_t* lout = L.iperm;
-    int rounds = 0;
-    int64_t coloured = 0;
+    // A level of at least kJpBigLevel nodes is launched alone with a wave per
+    // node; smaller ones go kJpBatch at a time on a fixed grid, the host
+    // reading the size only after each batch (a level past the last finds
+    // size 0 and returns).
+    constexpr int kJpBigLevel = 4096, kJpBatch = 32, kJpSmallBlocks = 512;
+    int64_t launched = 0;
     while (level > 0) {
-        coloured += level;
-        if (rounds >= kMaxJpRounds || coloured > n) {
+        const int batch = level >= kJpBigLevel ? 1 : kJpBatch;
+        if (launched + batch > kMaxJpRounds) {
             set_error("colouring did not finish within the round limit");
             return FJ_ERR_UNSUPPORTED;
         }
-        FJ_HIP(hipMemsetAsync(counts + 1, 0, sizeof(int), st));
-        hipLaunchKernelGGL(k_jp_level, dim3(grid1d(static_cast<int64_t>(level) * 64, bs)), dim3(bs), 0, st, level,
-                           d->row_ptr, d->col, g->t_row_ptr, g->t_col, g->directed, L.key, L.colour, L.cur1, lin,
-                           lout, counts + 1);
-        FJ_HIP(hipMemcpyAsync(&level, counts + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        for (int b = 0; b < batch; ++b, ++launched) {
+            const unsigned grid = batch == 1 ? grid1d(static_cast<int64_t>(level) * 64, bs) : kJpSmallBlocks;
+            int32_t* lin = launched % 2 == 0 ? L.perm : L.iperm;
+            int32_t* lout = launched % 2 == 0 ? L.iperm : L.perm;
+            hipLaunchKernelGGL(k_jp_level, dim3(grid), dim3(bs), 0, st, counts, static_cast<int>(launched % 3),
+                               d->row_ptr, d->col, g->t_row_ptr, g->t_col, g->directed, L.key, L.colour, L.cur1, lin,
+                               lout);
+        }
+        FJ_HIP(hipMemcpyAsync(&level, counts + launched % 3, sizeof(int), hipMemcpyDeviceToHost, st));
         FJ_HIP(hipStreamSynchronize(st));
-        std::swap(lin, lout);
-        ++rounds;
     }
-    if (coloured != n) {
+    int tallies[2] = {0, 0};
+    FJ_HIP(hipMemcpyAsync(tallies, counts + 3, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+    FJ_HIP(hipStreamSynchronize(st));
+    if (tallies[0] != n) {
         set_error("colouring left nodes uncoloured");
         return FJ_ERR_UNSUPPORTED;
     }
+    const int rounds = tallies[1];
     g->colour_rounds = rounds;
     hipLaunchKernelGGL(k_colour_count, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, L.colour, maxcol);
     int hmax = 0;
