@@ -275,16 +275,22 @@ __global__ void k_jp_count(int64_t n, const int32_t* __restrict__ row_ptr, const
 // costs a round trip per 512 arcs instead of per 64
 constexpr int kJpChunks = 8;
 
+// chunks first, first + stride, ... of v's adjacency (a wave: 0, 1; a block's
+// wave w of W: w, W)
 __device__ __forceinline__ uint64_t jp_used(const int32_t* __restrict__ ptr, const int32_t* __restrict__ adj,
                                             int32_t v, uint64_t kv, const uint64_t* __restrict__ key,
-                                            const int32_t* __restrict__ colour, int base) {
+                                            const int32_t* __restrict__ colour, int base, int first = 0,
+                                            int stride = 1) {
     uint64_t m = 0;
     const int32_t b = ptr[v], e = ptr[v + 1];
-    for (int32_t k0 = b + lane_id(); k0 < e; k0 += 64 * kJpChunks) {
+    for (int32_t k0 = b + 64 * first + lane_id(); k0 < e; k0 += 64 * stride * kJpChunks) {
         int32_t u[kJpChunks];
         int c[kJpChunks];
 #pragma unroll
-        for (int j = 0; j < kJpChunks; ++j) u[j] = k0 + 64 * j < e ? adj[k0 + 64 * j] : -1;
+        for (int j = 0; j < kJpChunks; ++j) {
+            const int32_t k = k0 + 64 * stride * j;
+            u[j] = k < e ? adj[k] : -1;
+        }
 #pragma unroll
         for (int j = 0; j < kJpChunks; ++j)
             c[j] = u[j] >= 0 && higher(key[u[j]], u[j], kv, v) ? colour[u[j]] - base : -1;
@@ -318,14 +324,15 @@ __device__ __forceinline__ void wave_append_n(const bool* take, const int32_t* u
 // together)
 __device__ __forceinline__ void jp_release(const int32_t* __restrict__ ptr, const int32_t* __restrict__ adj,
                                            int32_t v, uint64_t kv, const uint64_t* __restrict__ key, int32_t* wait,
-                                           int32_t* next, int* next_count) {
+                                           int32_t* next, int* next_count, int first = 0, int stride = 1) {
     const int32_t b = ptr[v], e = ptr[v + 1];
-    for (int32_t k0 = b; k0 < e; k0 += 64 * kJpChunks) {  // uniform trip count: the append needs every lane
+    // uniform trip count within the wave: the append needs every lane
+    for (int32_t c0 = b + 64 * first; c0 < e; c0 += 64 * stride * kJpChunks) {
         int32_t u[kJpChunks];
         bool lower[kJpChunks], ready[kJpChunks];
 #pragma unroll
         for (int j = 0; j < kJpChunks; ++j) {
-            const int32_t k = k0 + 64 * j + lane_id();
+            const int32_t k = c0 + 64 * stride * j + lane_id();
             u[j] = k < e ? adj[k] : -1;
         }
 #pragma unroll
@@ -342,20 +349,33 @@ __device__ __forceinline__ void jp_release(const int32_t* __restrict__ ptr, cons
 // cleared for the level after; so levels can be enqueued back to back
 // without the host reading their sizes.  The waves stride over the level.
 // counts[3] adds up the coloured nodes, counts[4] the non-empty levels.
+// Nodes with kJpWideArcs or more arcs are left to k_jp_heavy (a block per
+// node), listed in heavy[] with their count in hcount[par] (par: the level's
+// parity; the other slot is cleared for the next level).  Nodes of one level
+// are never adjacent, so the two kernels may colour them in either order.
+constexpr int kJpWideArcs = 2048;
+
 __global__ void k_jp_level(int* counts, int cur, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                            const int32_t* __restrict__ t_row_ptr, const int32_t* __restrict__ t_col, int directed,
                            const uint64_t* __restrict__ key, int32_t* colour, int32_t* wait,
-                           const int32_t* __restrict__ ready, int32_t* next) {
+                           const int32_t* __restrict__ ready, int32_t* next, int32_t* heavy, int* hcount, int par) {
     const int count = __builtin_amdgcn_readfirstlane(counts[cur]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         counts[(cur + 2) % 3] = 0;
         counts[3] += count;
         if (count > 0) counts[4] += 1;
+        hcount[par ^ 1] = 0;
     }
     int* next_count = counts + (cur + 1) % 3;
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id(); w < count; w += nw) {
         const int32_t v = ready[w];
+        int32_t deg = row_ptr[v + 1] - row_ptr[v];
+        if (directed) deg += t_row_ptr[v + 1] - t_row_ptr[v];
+        if (deg >= kJpWideArcs) {
+            if (lane_id() == 0) heavy[atomicAdd(&hcount[par], 1)] = v;
+            continue;
+        }
         const uint64_t kv = key[v];
         for (int base = 0;; base += 64) {
             uint64_t m = jp_used(row_ptr, col, v, kv, key, colour, base);
@@ -368,6 +388,45 @@ __global__ void k_jp_level(int* counts, int cur, const int32_t* __restrict__ row
         }
         jp_release(row_ptr, col, v, kv, key, wait, next, next_count);
         if (directed) jp_release(t_row_ptr, t_col, v, kv, key, wait, next, next_count);
+    }
+}
+
+// The wide nodes of the same level: a block of 16 waves per node, wave w
+// taking chunks w, w + 16, ...; the used colours OR-ed across the block.
+constexpr int kJpHeavyThreads = 1024;
+__global__ __launch_bounds__(kJpHeavyThreads) void k_jp_heavy(int* counts, int cur, const int32_t* __restrict__ row_ptr,
+                                                              const int32_t* __restrict__ col,
+                                                              const int32_t* __restrict__ t_row_ptr,
+                                                              const int32_t* __restrict__ t_col, int directed,
+                                                              const uint64_t* __restrict__ key, int32_t* colour,
+                                                              int32_t* wait, int32_t* next,
+                                                              const int32_t* __restrict__ heavy,
+                                                              const int* hcount, int par) {
+    __shared__ uint64_t s_or[kJpHeavyThreads / 64];
+    constexpr int nwv = kJpHeavyThreads / 64;
+    const int cnt = __builtin_amdgcn_readfirstlane(hcount[par]);
+    const int wv = wave_id();
+    int* next_count = counts + (cur + 1) % 3;
+    for (int h = blockIdx.x; h < cnt; h += gridDim.x) {
+        const int32_t v = heavy[h];
+        const uint64_t kv = key[v];
+        for (int base = 0;; base += 64) {
+            uint64_t m = jp_used(row_ptr, col, v, kv, key, colour, base, wv, nwv);
+            if (directed) m |= jp_used(t_row_ptr, t_col, v, kv, key, colour, base, wv, nwv);
+            m = wave_or(m);
+            if (lane_id() == 0) s_or[wv] = m;
+            __syncthreads();
+            uint64_t all = 0;
+#pragma unroll
+            for (int q = 0; q < nwv; ++q) all |= s_or[q];
+            __syncthreads();  // s_or is written again by the next round
+            if (~all) {
+                if (threadIdx.x == 0) colour[v] = base + __builtin_ctzll(~all);
+                break;
+            }
+        }
+        jp_release(row_ptr, col, v, kv, key, wait, next, next_count, wv, nwv);
+        if (directed) jp_release(t_row_ptr, t_col, v, kv, key, wait, next, next_count, wv, nwv);
     }
 }
 
@@ -783,9 +842,10 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     // Jones-Plassmann colouring, one priority level per launch (perm and iperm
     // hold the ready lists and cur1 the waiting counts until the relabelling
     // overwrites them)
-    // counts[0..2]: level sizes in rotation (k_jp_level), [3] coloured nodes, [4] levels
+    // counts[0..2]: level sizes in rotation (k_jp_level), [3] coloured nodes,
+    // [4] levels, [5..6] wide nodes of the level by parity (their list in cur2)
     int* counts = err + 8;
-    FJ_HIP(hipMemsetAsync(counts, 0, sizeof(int) * 5, st));
+    FJ_HIP(hipMemsetAsync(counts, 0, sizeof(int) * 7, st));
     hipLaunchKernelGGL(k_jp_init, dim3(grid1d(n, bs)), dim3(bs), 0, st, n, d->row_ptr, g->t_row_ptr, g->directed,
                        L.key, L.colour);
     hipLaunchKernelGGL(k_jp_count, dim3(grid1d(n * 64, bs)), dim3(bs), 0, st, n, d->row_ptr, d->col, g->t_row_ptr,
@@ -797,7 +857,7 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     // node; smaller ones go kJpBatch at a time on a fixed grid, the host
     // reading the size only after each batch (a level past the last finds
     // size 0 and returns).
-    constexpr int kJpBigLevel = 4096, kJpBatch = 32, kJpSmallBlocks = 512;
+    constexpr int kJpBigLevel = 4096, kJpBatch = 32, kJpSmallBlocks = 512, kJpHeavyBlocks = 64;
     int64_t launched = 0;
     while (level > 0) {
         const int batch = level >= kJpBigLevel ? 1 : kJpBatch;
@@ -809,9 +869,12 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
             const unsigned grid = batch == 1 ? grid1d(static_cast<int64_t>(level) * 64, bs) : kJpSmallBlocks;
             int32_t* lin = launched % 2 == 0 ? L.perm : L.iperm;
             int32_t* lout = launched % 2 == 0 ? L.iperm : L.perm;
-            hipLaunchKernelGGL(k_jp_level, dim3(grid), dim3(bs), 0, st, counts, static_cast<int>(launched % 3),
-                               d->row_ptr, d->col, g->t_row_ptr, g->t_col, g->directed, L.key, L.colour, L.cur1, lin,
-                               lout);
+            const int cur = static_cast<int>(launched % 3), par = static_cast<int>(launched % 2);
+            hipLaunchKernelGGL(k_jp_level, dim3(grid), dim3(bs), 0, st, counts, cur, d->row_ptr, d->col, g->t_row_ptr,
+                               g->t_col, g->directed, L.key, L.colour, L.cur1, lin, lout, L.cur2, counts + 5, par);
+            hipLaunchKernelGGL(k_jp_heavy, dim3(kJpHeavyBlocks), dim3(kJpHeavyThreads), 0, st, counts, cur,
+                               d->row_ptr, d->col, g->t_row_ptr, g->t_col, g->directed, L.key, L.colour, L.cur1, lout,
+                               L.cur2, counts + 5, par);
         }
         FJ_HIP(hipMemcpyAsync(&level, counts + launched % 3, sizeof(int), hipMemcpyDeviceToHost, st));
         FJ_HIP(hipStreamSynchronize(st));
