@@ -456,9 +456,11 @@ __device__ __forceinline__ void tile_readout(const NetIn& I, const f32x4 y2[4], 
     for (int q = 0; q < 4; ++q) o[q] = pq[q] + c0;
 }
 
-inline unsigned fwd_blocks(int64_t n) {
+// grid-stride tile kernels: at most `cap` blocks, about one resident round
+// (k_net_l1: 7 waves per SIMD at its register count, k_net_l2: 3)
+inline unsigned fwd_blocks(int64_t n, int64_t cap = 1024) {
     const int64_t tiles = (n + 15) / 16;
-    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(1024, (tiles + kWavesPerBlock - 1) / kWavesPerBlock)));
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(cap, (tiles + kWavesPerBlock - 1) / kWavesPerBlock)));
 }
 inline unsigned bwd_blocks(int64_t n) {
     const int64_t tiles = (n + 15) / 16;
@@ -906,7 +908,7 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
                            L.rs);
     }
     const NetIn I{n, s, L.rs, g->opd, L.stats, params, 0.0};
-    hipLaunchKernelGGL(k_net_l1, dim3(fwd_blocks(n)), dim3(kBlock), 0, st, I, L.P);
+    hipLaunchKernelGGL(k_net_l1, dim3(fwd_blocks(n, 1792)), dim3(kBlock), 0, st, I, L.P);
     // layer 2's message
     hipLaunchKernelGGL(k_agg_rows16, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
                        g->w, L.invd, L.P, L.M);
@@ -916,7 +918,7 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
         hipLaunchKernelGGL(k_agg16_combine, dim3(waves_to_blocks(ta.h1 - ta.h0)), dim3(kBlock), 0, st, ta, L.cpart,
                            L.invd, L.M);
     }
-    if (!training) hipLaunchKernelGGL(k_net_l2, dim3(fwd_blocks(n)), dim3(kBlock), 0, st, I, L.M, z0);
+    if (!training) hipLaunchKernelGGL(k_net_l2, dim3(fwd_blocks(n, 768)), dim3(kBlock), 0, st, I, L.M, z0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "warm-start forward");
     return FJ_OK;
