@@ -163,6 +163,34 @@ def errors_vs_exact(g, s, z, zt, eps):
             **{k: float(f"{abs(m[k] - mt[k]) / abs(mt[k]):.3e}") for k in "PDIC"}, "eps": eps}
 
 
+# The network's two MFMA tile kernels, per node.  Flops: the products of the
+# layers (layer 1: 8 x 64 and P = H1 Wp, 64 x 16; k_net_l2: layer 1 again,
+# [H1 | M] W2, 80 x 64, and the readout u, 64), 2 per multiply-add.  Bytes:
+# s 8, 1 + d 8, the FP32 neighbour sum of s 4, then P written (16 BF16, 32)
+# or M read (32) and z0 written (8).
+NET_L1 = {"flop": 2 * (8 * 64 + 64 * 16), "bytes": 8 + 8 + 4 + 32}
+NET_L2 = {"flop": 2 * (8 * 64 + 80 * 64 + 64), "bytes": 8 + 8 + 4 + 32 + 8}
+MFMA_BF16_TFLOPS = 2500.0
+
+
+def dense_layer_roofline(G, sd, params, reps=7):
+    """Median stage times of the forward (HIP events) and the two MFMA tile
+    kernels against the bf16 dense MFMA peak and the HBM peak."""
+    import paper_2507_14864_amd as fj
+    runs = [fj.wsnet_forward_timed(G, sd, params)[1] for _ in range(reps)]
+    med = [sorted(r[q] for r in runs)[reps // 2] for q in range(4)]
+    n = G.n
+    out = {"stage_ms": {"gather_s": round(med[0], 4), "k_net_l1": round(med[1], 4), "gather_P": round(med[2], 4),
+                        "k_net_l2": round(med[3], 4)}}
+    for name, ms, spec in (("k_net_l1", med[1], NET_L1), ("k_net_l2", med[3], NET_L2)):
+        tf = spec["flop"] * n / (ms * 1e-3) / 1e12
+        gb = spec["bytes"] * n / (ms * 1e-3) / 1e9
+        out[name] = {"flop_per_node": spec["flop"], "bytes_per_node": spec["bytes"], "tflops": round(tf, 1),
+                     "mfma_frac": round(tf / MFMA_BF16_TFLOPS, 4), "gbs": round(gb, 1),
+                     "hbm_frac": round(gb / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def warm_start_eval(dev):
     """Warm vs cold start on the held-out directed graph (5M nodes, 50M arc
     samples, bimodal opinions) with the stored network weights: time to the
@@ -184,7 +212,8 @@ def warm_start_eval(dev):
            "sweeps": {k: v["sweeps"] for k, v in res.items() if isinstance(v, dict)},
            "speedup_vs_cold": round(res["speedup_net_vs_cold"], 3),
            "speedup_vs_best_untrained_control": round(res["speedup_net_vs_best_control"], 3),
-           "controls_s": {k: round(v["s"], 5) for k, v in res.items() if k.startswith("z0=")}}
+           "controls_s": {k: round(v["s"], 5) for k, v in res.items() if k.startswith("z0=")},
+           "dense_layers": dense_layer_roofline(G, sd, params)}
     del G
     torch.cuda.empty_cache()
     return out

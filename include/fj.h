@@ -485,6 +485,14 @@ size_t fj_wsnet_workspace_bytes(const fj_graph* g, int32_t training);
 /* z0: device [n] out.  s: device [n]. */
 fj_status fj_wsnet_forward(const fj_graph* g, const double* s, const float* params, double* z0, void* ws,
                            size_t ws_bytes, void* stream);
+/* fj_wsnet_forward with its four stages timed by HIP events on `stream`, for
+ * measuring the network against its rooflines.  stage_ms: [host] 4 out: the
+ * statistics and the gather of s (ns), k_net_l1 (features, layer 1 and P on
+ * MFMA tiles), the gather of P (M), k_net_l2 (layer 1 again, layer 2 and the
+ * readout on MFMA tiles).  Synchronizes the stream.  Errors as
+ * fj_wsnet_forward, and FJ_ERR_HIP if an event call fails. */
+fj_status fj_wsnet_forward_timed(const fj_graph* g, const double* s, const float* params, double* z0, void* ws,
+                                 size_t ws_bytes, double* stage_ms, void* stream);
 /* grad: device [param_count] out; loss: device scalar out (the weighted mean squared error). */
 fj_status fj_wsnet_grad(const fj_graph* g, const double* s, const double* z_target, const float* params,
                         double rel_floor, float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);

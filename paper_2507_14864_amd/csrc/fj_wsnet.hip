@@ -890,11 +890,14 @@ NetLayout carve_net(Carver& cv, const fj_graph* g, bool training) {
     return L;
 }
 
-// the forward up to the message M = nbr(P); then z0 unless training
+// the forward up to the message M = nbr(P); then z0 unless training.  ev:
+// NULL, or five events recorded before the statistics of s, then after the
+// gather of s, after layer 1, after the gather of P and after layer 2.
 fj_status net_forward(const fj_graph* g, const double* s, const float* params, double* z0, const NetLayout& L,
-                      bool training, hipStream_t st) {
+                      bool training, hipStream_t st, hipEvent_t* ev = nullptr) {
     const int64_t n = g->n;
     const int bs = 256;
+    if (ev) FJ_HIP(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_s_prep, dim3(kStatBlocks), dim3(256), 0, st, n, s, g->opd, L.stats_part, L.s32, L.invd);
     hipLaunchKernelGGL(k_s_final, dim3(1), dim3(64), 0, st, kStatBlocks, n, L.stats_part, L.stats);
     const TileView ta = tile_view_all(g->tiles_a);
@@ -908,7 +911,9 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
                            L.rs);
     }
     const NetIn I{n, s, L.rs, g->opd, L.stats, params, 0.0};
+    if (ev) FJ_HIP(hipEventRecord(ev[1], st));
     hipLaunchKernelGGL(k_net_l1, dim3(fwd_blocks(n, 1792)), dim3(kBlock), 0, st, I, L.P);
+    if (ev) FJ_HIP(hipEventRecord(ev[2], st));
     // layer 2's message
     hipLaunchKernelGGL(k_agg_rows16, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col,
                        g->w, L.invd, L.P, L.M);
@@ -918,7 +923,9 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
         hipLaunchKernelGGL(k_agg16_combine, dim3(waves_to_blocks(ta.h1 - ta.h0)), dim3(kBlock), 0, st, ta, L.cpart,
                            L.invd, L.M);
     }
+    if (ev) FJ_HIP(hipEventRecord(ev[3], st));
     if (!training) hipLaunchKernelGGL(k_net_l2, dim3(fwd_blocks(n, 768)), dim3(kBlock), 0, st, I, L.M, z0);
+    if (ev) FJ_HIP(hipEventRecord(ev[4], st));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "warm-start forward");
     return FJ_OK;
@@ -984,6 +991,37 @@ extern "C" fj_status fj_wsnet_forward(const fj_graph* g, const double* s, const 
     Carver cv(ws);
     NetLayout L = carve_net(cv, g, false);
     return net_forward(g, s, params, z0, L, false, static_cast<hipStream_t>(stream));
+}
+
+extern "C" fj_status fj_wsnet_forward_timed(const fj_graph* g, const double* s, const float* params, double* z0,
+                                            void* ws, size_t ws_bytes, double* stage_ms, void* stream) {
+    fj_status rc = net_args_ok(g, s, params, ws, ws_bytes, false);
+    if (rc) return rc;
+    if (!z0 || !stage_ms) {
+        set_error("fj_wsnet_forward_timed: z0 or stage_ms is NULL");
+        return FJ_ERR_INVALID_ARGUMENT;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[5] = {};
+    int made = 0;
+    for (; made < 5; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) break;
+    if (made == 5) {
+        Carver cv(ws);
+        NetLayout L = carve_net(cv, g, false);
+        rc = net_forward(g, s, params, z0, L, false, st, ev);
+        if (rc == FJ_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = hip_fail(hipGetLastError(), "event");
+        for (int q = 0; q < 4 && rc == FJ_OK; ++q) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            if (e != hipSuccess) rc = hip_fail(e, "hipEventElapsedTime");
+            stage_ms[q] = ms;
+        }
+    } else {
+        rc = hip_fail(hipGetLastError(), "hipEventCreate");
+    }
+    for (int q = 0; q < made; ++q) (void)hipEventDestroy(ev[q]);
+    return rc;
 }
 
 extern "C" fj_status fj_wsnet_grad(const fj_graph* g, const double* s, const double* z_target, const float* params,

@@ -634,6 +634,8 @@ def _net_lib():
         L.fj_wsnet_workspace_bytes.restype = sz
         L.fj_wsnet_forward.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.fj_wsnet_forward.restype = i32
+        L.fj_wsnet_forward_timed.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp]
+        L.fj_wsnet_forward_timed.restype = i32
         L.fj_wsnet_grad.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, sz, vp]
         L.fj_wsnet_grad.restype = i32
         L.fj_wsnet_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i32, fl, ctypes.c_double, vp, vp, sz, vp]
@@ -671,6 +673,21 @@ def wsnet_forward(graph: Graph, s: torch.Tensor, params: torch.Tensor, out: Opti
                                        ctypes.c_void_p(z0.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream()))
     return z0
+
+
+def wsnet_forward_timed(graph: Graph, s: torch.Tensor, params: torch.Tensor, out: Optional[torch.Tensor] = None):
+    """wsnet_forward with its stages timed by HIP events: (z0, [ms of the
+    gather of s, layer 1, the gather of P, layer 2])."""
+    n = graph.n
+    _dev_ptr(s, torch.float64, n, "s")
+    _dev_ptr(params, torch.float32, wsnet_param_count(), "params")
+    z0 = out if out is not None else torch.empty(n, dtype=torch.float64, device=graph.device)
+    ws = _net_ws(graph, False)
+    ms = (ctypes.c_double * 4)()
+    _check(_net_lib().fj_wsnet_forward_timed(graph.handle, ctypes.c_void_p(s.data_ptr()),
+                                             ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(z0.data_ptr()),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ms, _stream()))
+    return z0, [float(x) for x in ms]
 
 
 def wsnet_grad(graph: Graph, s: torch.Tensor, z_target: torch.Tensor, params: torch.Tensor, rel_floor: float = 0.0):

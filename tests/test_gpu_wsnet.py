@@ -128,3 +128,15 @@ def test_jacobi_steps_match_equation_one():
     fj.jacobi_steps(G, sd, z, 5)
     want = oracle.fj_iterate(g, s, s, 5)
     assert np.max(np.abs(z.cpu().numpy() - want)) <= 1e-13
+
+
+def test_timed_forward_matches_forward():
+    """fj_wsnet_forward_timed runs the same kernels as fj_wsnet_forward (the
+    same z0 bit for bit) and reports four positive stage times."""
+    fj, g, s, G = _setup(n=200_000, m=1_600_000, seed=961)
+    p = torch.from_numpy(mpnn.init_params(9).astype(np.float32)).to(DEV)
+    sd = torch.from_numpy(s).to(DEV)
+    z = fj.wsnet_forward(G, sd, p)
+    zt, ms = fj.wsnet_forward_timed(G, sd, p)
+    assert torch.equal(z, zt)
+    assert len(ms) == 4 and all(x > 0.0 for x in ms)
