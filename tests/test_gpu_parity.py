@@ -234,6 +234,16 @@ def test_colouring_is_proper_and_classes_cover_nodes():
         sizes = G.colour_sizes()
         assert sum(sizes) == g.n and len(sizes) == col.max() + 1
         assert np.array_equal(np.bincount(col, minlength=len(sizes)), sizes)
+        # first fit in some order (the colouring is first fit in priority
+        # order): a node of colour c has neighbours (in A + A^T) of every
+        # colour below c, whatever the order was
+        src = np.concatenate([rows, g.col]).astype(np.int64)
+        dst = np.concatenate([g.col, rows]).astype(np.int64)
+        below = col[dst] < col[src]
+        K = int(col.max()) + 1
+        pairs = np.unique(src[below] * K + col[dst][below])
+        have = np.bincount(pairs // K, minlength=g.n)
+        assert np.array_equal(have, col), "a node skips a colour no neighbour holds"
 
 
 def test_warm_start_reaches_same_certificate():
