@@ -1767,6 +1767,7 @@ extern "C" fj_status fj_tune_omega(const fj_graph* g, const double* s, const fj_
         fj_solve_opts o = *opts;
         o.omega = omegas[k];
         o.profile = 0;
+        o.measures = nullptr;  // the candidates' measures are not wanted
         fj_solve_stats st{};
         fj_status rc = fj_solve(g, s, &o, z, ws, ws_bytes, &st, stream);
         if (rc != FJ_OK && rc != FJ_ERR_NOT_CONVERGED) return rc;
