@@ -1,0 +1,97 @@
+"""Property tests of the GPU solve over random small graphs (Hypothesis).
+
+Every example draws a graph on 1..48 nodes (directed or undirected, unit or
+U[0.5, 1.5] weights, any density), opinions with zeros among them, a
+schedule and a relaxation factor it supports (colour-ordered sweeps: omega in
+(0, 2) on undirected graphs, (0, 1] on directed ones, where I + L is only
+row diagonally dominant; push rounds: omega in (0, 1]), a precision and eps,
+and checks the result against the dense definition z = (I+L)^{-1} s (Lemma 1,
+LU in the oracle): the entrywise bound of Lemma 7, the relative-error claim,
+the certificate recomputed by the oracle, and the measures returned with the
+solve against the oracle's measures of the same z.  Examples are
+derandomized, so a run is reproducible.
+"""
+import numpy as np
+import pytest
+
+hyp = pytest.importorskip("hypothesis")
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+C = SIGMA = 1e-5
+SETTINGS = settings(max_examples=300, deadline=None, derandomize=True, print_blob=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@st.composite
+def problems(draw, max_n=48):
+    n = draw(st.integers(1, max_n))
+    directed = draw(st.booleans())
+    weighted = draw(st.booleans())
+    p = draw(st.floats(0.0, 1.0))
+    seed = draw(st.integers(0, 2**31 - 1))
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        cols = [j for j in range(n) if j != i and rng.random() < p]
+        rows.append(cols)
+    if not directed:  # symmetrise: keep (i, j) iff drawn for i < j
+        sym = [set() for _ in range(n)]
+        for i in range(n):
+            for j in rows[i]:
+                if i < j:
+                    sym[i].add(j)
+                    sym[j].add(i)
+        rows = [sorted(r) for r in sym]
+    row_ptr = np.zeros(n + 1, np.int32)
+    for i in range(n):
+        row_ptr[i + 1] = row_ptr[i] + len(rows[i])
+    col = np.array([j for r in rows for j in r], dtype=np.int32)
+    w = None
+    if weighted:
+        wd = {}
+        for i in range(n):
+            for j in rows[i]:
+                key = (i, j) if directed else (min(i, j), max(i, j))
+                if key not in wd:
+                    wd[key] = rng.uniform(0.5, 1.5)
+        w = np.array([wd[(i, j) if directed else (min(i, j), max(i, j))] for i in range(n) for j in rows[i]],
+                     dtype=np.float32)
+    g = synth.CSRGraph(n, row_ptr, col, w, directed)
+    s = rng.uniform(0.0, 1.0, n)
+    s[rng.random(n) < draw(st.floats(0.0, 0.5))] = 0.0
+    schedule = draw(st.sampled_from(["sor", "push"]))
+    hi = 1.9 if (schedule == "sor" and not directed) else 1.0
+    omega = draw(st.floats(0.3, hi))
+    precision = draw(st.sampled_from(["fp32", "fp64"]))
+    eps = draw(st.sampled_from([1e-3, 1e-5, 1e-7]))
+    return g, s, schedule, omega, precision, eps
+
+
+@given(problems())
+@SETTINGS
+def test_random_small_graphs_against_the_dense_solution(prob):
+    import paper_2507_14864_amd as fj
+    g, s, schedule, omega, precision, eps = prob
+    zt = oracle.dense_solve(g, s)
+    G = fj.Graph.from_host(g, DEV, colour=schedule == "sor")
+    z, st_ = fj.solve(G, torch.from_numpy(s).to(DEV), eps=eps, omega=omega, c=C, sigma=SIGMA,
+                      precision=precision, schedule=schedule, measures=True)
+    assert st_["certified"] == 1
+    zc = z.cpu().numpy()
+    epsp = SIGMA * eps / (C + SIGMA)
+    assert np.all(np.abs(zc - zt) <= epsp * (zt + C) * (1 + 1e-9) + 1e-15)  # Lemma 7
+    assert oracle.certificate(g, s, zc, eps, sigma=SIGMA, c=C) <= 1.0 + 1e-9
+    m, mo = st_["measures"], oracle.metrics(g, s, zc)
+    for k in ("P", "D", "I", "C", "mean"):
+        assert abs(m[k] - mo[k]) <= 1e-12 * abs(mo[k]) + 1e-14, k
