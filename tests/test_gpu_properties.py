@@ -95,3 +95,57 @@ def test_random_small_graphs_against_the_dense_solution(prob):
     m, mo = st_["measures"], oracle.metrics(g, s, zc)
     for k in ("P", "D", "I", "C", "mean"):
         assert abs(m[k] - mo[k]) <= 1e-12 * abs(mo[k]) + 1e-14, k
+
+
+@st.composite
+def batches(draw):
+    items = draw(st.lists(problems(max_n=32), min_size=1, max_size=6))
+    ks = [draw(st.integers(1, 5)) for _ in items]
+    omega = draw(st.floats(0.3, 1.0))
+    eps = draw(st.sampled_from([1e-3, 1e-5]))
+    seed = draw(st.integers(0, 2**31 - 1))
+    return [it[0] for it in items], ks, omega, eps, seed
+
+
+@given(batches())
+@settings(max_examples=60, deadline=None, derandomize=True, print_blob=True)
+def test_random_small_batches_against_the_dense_solution(bat):
+    """fj_solve_batched over 1..6 random small graphs (1..5 vectors each; the
+    single-vector ones go to the block-diagonal union, the others are
+    multi-vector items) at one omega in (0.3, 1] (colour-ordered sweeps on
+    directed graphs need omega <= 1), continued by fj_batch_check where the
+    untuned sweep budget is short: every vector certified and within
+    Lemma 7's bound of the dense solution, its measures against the
+    oracle's measures of the returned z."""
+    import paper_2507_14864_amd as fj
+    graphs_, ks, omega, eps, seed = bat
+    rng = np.random.default_rng(seed)
+
+    def dev(g):
+        return (torch.from_numpy(g.row_ptr).to(DEV), torch.from_numpy(g.col).to(DEV),
+                None if g.w is None else torch.from_numpy(g.w).to(DEV), g.directed)
+
+    B = fj.Batch([dev(g) for g in graphs_], ks, eps=eps, omega=omega, c=C, sigma=SIGMA)
+    ss = []
+    for i, (g, k) in enumerate(zip(graphs_, ks)):
+        s = rng.uniform(0.0, 1.0, (g.n, k)) if k > 1 else rng.uniform(0.0, 1.0, g.n)
+        B.input(i).copy_(torch.from_numpy(np.ascontiguousarray(s)))
+        ss.append(s)
+    stats, mets = B.solve()
+    if not all(x["certified"] for x in stats):
+        # the untuned budget (256 sweeps) is short at small omega on dense
+        # graphs (K_21 at omega 0.5 needs 401); fj_batch_check sweeps on
+        assert B.check(8192) == 0
+        stats, mets = B.results()
+    epsp = SIGMA * eps / (C + SIGMA)
+    for i, (g, k) in enumerate(zip(graphs_, ks)):
+        assert stats[i]["certified"] == 1, i
+        z = B.output(i).cpu().numpy().reshape(g.n, k)
+        S = ss[i].reshape(g.n, k)
+        for q in range(k):
+            zt = oracle.dense_solve(g, S[:, q])
+            assert np.all(np.abs(z[:, q] - zt) <= epsp * (zt + C) * (1 + 1e-9) + 1e-15), (i, q)
+            mo = oracle.metrics(g, S[:, q], z[:, q])
+            for key in ("P", "D", "I", "C"):
+                assert abs(mets[i][q][key] - mo[key]) <= 1e-10 * abs(mo[key]) + 1e-14, (i, q, key)
+    B.close()
