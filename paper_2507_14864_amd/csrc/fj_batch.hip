@@ -137,12 +137,41 @@ __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* u
 }
 
 // ------------------------------------------------- union sweep (k = 1)
+// Heavy rows finish in the launch that sums their chunks.  A chunk wave
+// publishes its partial with returning atomic exchanges, which are performed
+// where every CU sees them (the chunk waves of one row run on any XCD, and
+// plain stores would stay in this XCD's L2), then counts its arrival on the
+// row's counter once every lane's exchange has returned: the counter's
+// address depends on the returned values.  The wave whose arrival completes
+// a multiple of the row's chunk count reads the partials back the same way
+// and adds them in chunk order, as a separate finishing launch would.  The
+// counters are cleared when a solve starts.
+__device__ __forceinline__ int after_all_lanes(unsigned long long v) {
+    const unsigned long long m = __ballot(v == 0x7ff4dead0badf00dull);  // every lane's v
+    int dep;
+    __asm__ volatile("v_mov_b32 %0, 0 ; after %1" : "=v"(dep) : "v"(static_cast<unsigned>(m)));
+    return dep;
+}
+__device__ __forceinline__ unsigned long long publish_ret(double* p, double v) {
+    return atomicExch(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+__device__ __forceinline__ double read_published(double* p) {
+    return __longlong_as_double(static_cast<long long>(atomicOr(reinterpret_cast<unsigned long long*>(p), 0ull)));
+}
+
+__global__ void k_fill_i32(int64_t count, int32_t* p, int32_t v) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
 // NCH: 64-arc chunks of a light tile in flight per step (a tuned launch
 // parameter; the sums are added in arc order whatever its value)
 template <int NCH>
 __global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_t* __restrict__ prow_ptr,
                                                        const int32_t* __restrict__ pcol, const float* __restrict__ pw,
-                                                       SorState S, double* partial, const int32_t* __restrict__ pcomp,
+                                                       SorState S, double* partial, int32_t* hcnt,
+                                                       const int32_t* __restrict__ pcomp,
                                                        const double* __restrict__ comp_omega, int* upd,
                                                        const int* __restrict__ done,
                                                        const int* __restrict__ all_done, int* bad) {
@@ -156,14 +185,33 @@ __global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_
         double a = pw ? static_cast<double>(__builtin_nontemporal_load(&pw[k])) : 1.0;
         return a * zh[__builtin_nontemporal_load(&pcol[k])];
     };
-    if (wv < tv.nchunks) {
-        int64_t cidx = tv.c0 + wv;
-        int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
-        if (done[pcomp[row]]) return;
-        int beg = tv.chunk_beg[cidx];
-        int end = min(beg + kArcBudget, prow_ptr[row + 1]);
-        double sum = chunk_sum(beg, end, arc);
-        if (lane == 0) partial[cidx] = sum;
+    if (wv < tv.nchunks) {  // a chunk of a heavy row; the last one finishes the row
+        const int64_t cidx = tv.c0 + wv;
+        const int32_t h = tv.chunk_heavy[cidx];
+        const int32_t row = tv.heavy_row[h];
+        const int c = pcomp[row];
+        if (done[c]) return;
+        const int beg = tv.chunk_beg[cidx];
+        const int end = min(beg + kArcBudget, prow_ptr[row + 1]);
+        const double part = chunk_sum(beg, end, arc);
+        unsigned long long ret = 0;
+        if (lane == 0) ret = publish_ret(partial + cidx, part);
+        const int dep = after_all_lanes(ret);
+        int old = 0;
+        if (lane == 0) old = atomicAdd(hcnt + h + dep, 1);
+        old = __shfl(old, 0, 64);
+        const int32_t q0 = tv.heavy_chunk0[h], q1 = tv.heavy_chunk0[h + 1];
+        if ((old + 1) % (q1 - q0) != 0) return;
+        double sum = 0.0;
+        for (int32_t q = q0 + lane; q < q1; q += 64) sum += read_published(partial + q);
+        sum = wave_sum(sum);
+        if (lane == 0) {
+            bool nf = false;
+            SorState Sc = S;
+            Sc.omega = comp_omega[c];
+            if (sor_row(row, sum, Sc, &nf)) flag_set(&upd[c]);
+            if (nf) flag_set(bad);
+        }
         return;
     }
     wv -= tv.nchunks;
@@ -184,31 +232,6 @@ __global__ __launch_bounds__(kBlock) void k_usor_tiles(TileView tv, const int32_
             if (sor_row(r0 + lane, sum, Sc, &nf)) flag_set(&upd[c]);
             if (nf) flag_set(bad);
         }
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_usor_heavy(TileView tv, SorState S, const double* __restrict__ partial,
-                                                       const int32_t* __restrict__ pcomp,
-                                                       const double* __restrict__ comp_omega, int* upd,
-                                                       const int* __restrict__ done, const int* __restrict__ all_done,
-                                                       int* bad) {
-    if (*all_done) return;
-    const int wid = wave_id(), lane = lane_id();
-    int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    if (hh >= tv.h1) return;
-    const int32_t row = tv.heavy_row[hh];
-    const int c = pcomp[row];
-    if (done[c]) return;
-    int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
-    double sum = 0.0;
-    for (int32_t q = c0 + lane; q < c1; q += 64) sum += partial[q];
-    sum = wave_sum(sum);
-    if (lane == 0) {
-        bool nf = false;
-        SorState Sc = S;
-        Sc.omega = comp_omega[c];
-        if (sor_row(row, sum, Sc, &nf)) flag_set(&upd[c]);
-        if (nf) flag_set(bad);
     }
 }
 
@@ -344,25 +367,45 @@ template <int U>
 __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, int64_t re,
                                                        const int32_t* __restrict__ prow_ptr,
                                                        const int32_t* __restrict__ pcol, const float* __restrict__ pw,
-                                                       MState S, double* partial, int* upd,
+                                                       MState S, double* partial, int32_t* hcnt, int* upd,
                                                        const int* __restrict__ done, const int* __restrict__ all_done,
                                                        int* bad) {
     if (*all_done || *done) return;
     const int wid = wave_id(), lane = lane_id();
     int64_t wv = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    if (wv < tv.nchunks) {
+    if (wv < tv.nchunks) {  // a chunk of a heavy row; the last one finishes the row
         const int64_t cidx = tv.c0 + wv;
-        const int32_t row = tv.heavy_row[tv.chunk_heavy[cidx]];
+        const int32_t h = tv.chunk_heavy[cidx];
+        const int32_t row = tv.heavy_row[h];
         const int beg = tv.chunk_beg[cidx];
         const int end = min(beg + kArcBudget, prow_ptr[row + 1]);
-        double acc = mrhs_arc_sum<U>(beg, end, pcol, pw, S.zh, S.k, lane, mrhs_active(S, lane));
-        if (lane < S.k) partial[cidx * S.k + lane] = acc;
+        const bool act = mrhs_active(S, lane);
+        const double acc = mrhs_arc_sum<U>(beg, end, pcol, pw, S.zh, S.k, lane, act);
+        unsigned long long ret = 0;
+        if (lane < S.k) ret = publish_ret(partial + cidx * S.k + lane, acc);
+        const int dep = after_all_lanes(ret);
+        int old = 0;
+        if (lane == 0) old = atomicAdd(hcnt + h + dep, 1);
+        old = __shfl(old, 0, 64);
+        const int32_t c0 = tv.heavy_chunk0[h], c1 = tv.heavy_chunk0[h + 1];
+        if ((old + 1) % (c1 - c0) != 0) return;
+        double sum = 0.0;
+        if (act)
+            for (int32_t q = c0; q < c1; ++q) sum += read_published(partial + static_cast<int64_t>(q) * S.k + lane);
+        bool nf = false;
+        const bool u = mrhs_row(row, lane, sum, S, &nf, act);
+        const unsigned long long um = __ballot(u);
+        if (um && lane == 0) {
+            flag_set(upd);
+            vmask_or(S.vupd, um);
+        }
+        if (__ballot(nf) && lane == 0) flag_set(bad);
         return;
     }
     const int64_t i = rb + (wv - tv.nchunks);
     if (i >= re) return;
     const int b = prow_ptr[i], e = prow_ptr[i + 1];
-    if (e - b > kArcBudget) return;  // heavy: chunks + k_msor_heavy
+    if (e - b > kArcBudget) return;  // heavy: its chunk waves
     const bool act = mrhs_active(S, lane);
     // the row's own values load before the gathers (no row of the class
     // reads another, so nothing writes them meanwhile)
@@ -374,28 +417,6 @@ __global__ __launch_bounds__(kBlock) void k_msor_class(TileView tv, int64_t rb, 
     double acc = mrhs_arc_sum<U>(b, e, pcol, pw, S.zh, S.k, lane, act);
     bool nf = false;
     bool u = mrhs_row_with(i, lane, acc, S, z, sp, &nf, act);
-    const unsigned long long um = __ballot(u);
-    if (um && lane == 0) {
-        flag_set(upd);
-        vmask_or(S.vupd, um);
-    }
-    if (__ballot(nf) && lane == 0) flag_set(bad);
-}
-
-__global__ __launch_bounds__(kBlock) void k_msor_heavy(TileView tv, MState S, const double* __restrict__ partial,
-                                                       int* upd, const int* __restrict__ done,
-                                                       const int* __restrict__ all_done, int* bad) {
-    if (*all_done || *done) return;
-    const int wid = wave_id(), lane = lane_id();
-    const int64_t hh = tv.h0 + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
-    if (hh >= tv.h1) return;
-    const int32_t c0 = tv.heavy_chunk0[hh], c1 = tv.heavy_chunk0[hh + 1];
-    const bool act = mrhs_active(S, lane);
-    double sum = 0.0;
-    if (act)
-        for (int32_t q = c0; q < c1; ++q) sum += partial[static_cast<int64_t>(q) * S.k + lane];
-    bool nf = false;
-    bool u = mrhs_row(tv.heavy_row[hh], lane, sum, S, &nf, act);
     const unsigned long long um = __ballot(u);
     if (um && lane == 0) {
         flag_set(upd);
@@ -734,6 +755,7 @@ struct UnionGroup {
     void* gws = nullptr; size_t gws_bytes = 0;
     double* s_in = nullptr; double* z_out = nullptr;
     double* sp = nullptr; double* zh = nullptr; int32_t* zq = nullptr; double* partial = nullptr;
+    int32_t* hcnt = nullptr; int64_t hcnt_len = 0;  // heavy-row arrival counters
     double* ratio = nullptr; double* drow = nullptr; double* seg = nullptr;
 };
 
@@ -744,6 +766,7 @@ struct MrhsGroup {
     void* gws = nullptr; size_t gws_bytes = 0;
     double* s_in = nullptr; double* z_out = nullptr;
     double* sp = nullptr; double* zh = nullptr; double* partial = nullptr;
+    int32_t* hcnt = nullptr; int64_t hcnt_len = 0;  // heavy-row arrival counters
     double* part = nullptr; double* tot = nullptr; double* means = nullptr;
 };
 
@@ -857,6 +880,8 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
         auto* zh = cv.take<double>(un);
         auto* zq = cv.take<int32_t>(un);
         auto* partial = cv.take<double>(2 * (unnz / kArcBudget) + 4);
+        const int64_t uhc = unnz / kArcBudget + 2;  // heavy rows have more than kArcBudget arcs
+        auto* uhcnt = cv.take<int32_t>(uhc);
         auto* ratio = cv.take<double>(un);
         auto* drow = cv.take<double>(un);
         auto* seg = cv.take<double>(8 * ncomp);
@@ -865,6 +890,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
             U->row_ptr = rp; U->col = col; U->w = w; U->d_node_off = noff; U->d_comp_item = citem;
             U->comp_dir = cdir; U->comp_of = cof; U->pcomp = pcomp; U->gws = gws; U->gws_bytes = gb;
             U->s_in = s_in; U->z_out = z_out; U->sp = sp; U->zh = zh; U->zq = zq; U->partial = partial;
+            U->hcnt = uhcnt; U->hcnt_len = uhc;
             U->ratio = ratio; U->drow = drow; U->seg = seg;
         }
     }
@@ -881,6 +907,8 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
         auto* sp = cv.take<double>(n * k);
         auto* zh = cv.take<double>(n * k);
         auto* partial = cv.take<double>((2 * (nnz / kArcBudget) + 4) * k);
+        const int64_t mhc = nnz / kArcBudget + 2;
+        auto* mhcnt = cv.take<int32_t>(mhc);
         auto* part = cv.take<double>(static_cast<int64_t>(kMBlocks) * 64 * 6);
         auto* tot = cv.take<double>(8 * 64);
         auto* means = cv.take<double>(64);
@@ -888,6 +916,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
             MrhsGroup& G = b->M[mi];
             G.item = i; G.k = k; G.desc = d; G.gws = gws; G.gws_bytes = gb; G.s_in = s_in; G.z_out = z_out;
             G.sp = sp; G.zh = zh; G.partial = partial; G.part = part; G.tot = tot; G.means = means;
+            G.hcnt = mhcnt; G.hcnt_len = mhc;
         }
         ++mi;
     }
@@ -921,15 +950,20 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
             ++launches;
         }
         if (b->has_union && U.n > 0) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(std::min<int64_t>(g1d(U.hcnt_len, bs), 1024)), dim3(bs), 0, st,
+                               U.hcnt_len, U.hcnt, 0);
+            ++launches;
             hipLaunchKernelGGL(k_sor_init, dim3(g1d(U.n, bs)), dim3(bs), 0, st, U.n, U.g.perm, U.s_in,
                                static_cast<const double*>(nullptr), b->c, U.sp, U.zh, U.zq, b->bad,
                                static_cast<unsigned long long*>(nullptr));
             ++launches;
         }
         for (auto& G : b->M) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(std::min<int64_t>(g1d(G.hcnt_len, bs), 1024)), dim3(bs), 0, st,
+                               G.hcnt_len, G.hcnt, 0);
             hipLaunchKernelGGL(k_minit, dim3(g1d(G.g.n * G.k, bs)), dim3(bs), 0, st, G.g.n, G.k, G.g.perm, G.s_in,
                                b->c, G.sp, G.zh, b->bad);
-            ++launches;
+            launches += 2;
         }
     }
     int max_cls = b->has_union ? U.g.num_colours : 0;
@@ -942,14 +976,8 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
                 if (tv.ntiles + tv.nchunks > 0) {
                     auto kern = b->nch == 2 ? k_usor_tiles<2> : b->nch == 8 ? k_usor_tiles<8> : k_usor_tiles<4>;
                     hipLaunchKernelGGL(kern, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0,
-                                       st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.pcomp,
+                                       st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.hcnt, U.pcomp,
                                        b->d_slot_omega, b->upd, b->done, b->all_done, b->bad);
-                    ++launches;
-                }
-                if (tv.h1 > tv.h0) {
-                    hipLaunchKernelGGL(k_usor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv,
-                                       SU, U.partial, U.pcomp, b->d_slot_omega, b->upd, b->done, b->all_done,
-                                       b->bad);
                     ++launches;
                 }
             }
@@ -963,14 +991,9 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
                 const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
                 auto kern = b->mu == 4 ? k_msor_class<4> : b->mu == 16 ? k_msor_class<16> : k_msor_class<8>;
                 hipLaunchKernelGGL(kern, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, st,
-                                   tv, rb, re, G.g.prow_ptr, G.g.pcol, G.g.pw, S, G.partial, b->upd + slot,
+                                   tv, rb, re, G.g.prow_ptr, G.g.pcol, G.g.pw, S, G.partial, G.hcnt, b->upd + slot,
                                    b->done + slot, b->all_done, b->bad);
                 ++launches;
-                if (tv.h1 > tv.h0) {
-                    hipLaunchKernelGGL(k_msor_heavy, dim3(waves_to_blocks(tv.h1 - tv.h0)), dim3(kBlock), 0, st, tv, S,
-                                       G.partial, b->upd + slot, b->done + slot, b->all_done, b->bad);
-                    ++launches;
-                }
             }
         }
         hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, st, b->nslots, sw, b->upd, b->done, b->sweeps_done,

@@ -618,8 +618,12 @@ class Batch:
     def __del__(self):
         # fj_batch_destroy calls into the HIP runtime (it frees the recorded
         # graph); at interpreter shutdown that runtime may already be gone, so
-        # the handle is left to the process's end there
-        if sys.is_finalizing():
+        # the handle is left to the process's end there (late in shutdown the
+        # module globals, sys among them, may already be None)
+        try:
+            if sys.is_finalizing():
+                return
+        except AttributeError:
             return
         self.close()
 
