@@ -283,6 +283,9 @@ def batch_eval(dev, steps, warmup):
     dt = (time.perf_counter() - t0) / max(steps, 1)
     stats, mets = B.results()
     cert = sum(s["certified"] for s in stats)
+    # gathered value bytes: 8 per arc and vector swept (a lower bound on the
+    # traffic: column indices, row data and writes come on top)
+    gathered = 8 * sum(s["edge_visits"] for s in stats)
     out = {"workload": "64 vectors (U[0,1], Beta(2,2), bimodal) on an undirected Chung-Lu graph with 2M nodes / "
                        "20M edge samples, plus 256 graphs of 1k-200k nodes (average degree 8, half directed)",
            "s_per_batch": round(dt, 5), "vector_solves_per_s": round(320 / dt, 1), "eps": 1e-4,
@@ -290,7 +293,9 @@ def batch_eval(dev, steps, warmup):
            "omega_directed": info["omega_directed"], "sweep_budget": info["sweep_budget"],
            "graph_nodes": info["graph_nodes"], "union_chunks_in_flight": info["union_chunks_in_flight"],
            "multi_arcs_in_flight": info["multi_arcs_in_flight"], "certified_items": cert, "items": len(stats),
-           "max_sweeps_used": max(s["rounds"] for s in stats), "ingest_s": round(ingest, 2),
+           "max_sweeps_used": max(s["rounds"] for s in stats),
+           "gathered_value_bytes": gathered, "gathered_GBs": round(gathered / dt / 1e9, 1),
+           "gathered_hbm_frac": round(gathered / dt / 1e9 / HBM_PEAK_GBS, 4), "ingest_s": round(ingest, 2),
            "tune_s": round(tune_s, 2), "steps": steps}
     B.close()  # release the recorded hipGraph while the runtime is up
     del B

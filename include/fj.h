@@ -457,7 +457,9 @@ fj_status fj_batch_set_omegas(fj_batch* b, double omega_undirected, double omega
 /* Solve every item.  Enqueues only (never synchronizes; uses no host memory):
  * the recorded hipGraph if fj_batch_tune ran, else the kernels directly.
  * stats_dev: device [num_items] or NULL; per item rounds = sweeps used,
- * certified, max_ratio (over its k vectors); other fields 0.
+ * certified, max_ratio (over its k vectors), edge_visits = arcs whose value
+ * was gathered (a multi-vector item: for each vector, its arcs times the
+ * sweeps until it went quiet); other fields 0.
  * metrics_dev: device [sum of k] or NULL, item-major then vector. */
 fj_status fj_solve_batched(fj_batch* b, fj_solve_stats* stats_dev, fj_metrics_out* metrics_dev, void* stream);
 

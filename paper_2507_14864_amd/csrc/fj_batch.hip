@@ -93,7 +93,7 @@ __global__ void k_gather_i32(int64_t n, const int32_t* __restrict__ idx, const i
 // --------------------------------------------------------- flags per slot
 // slot = one component of the union or one multi-vector item
 __global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done, int* all_done, int* bad,
-                              unsigned long long* vupd, unsigned long long* vdone) {
+                              unsigned long long* vupd, unsigned long long* vdone, int* vsw) {
     for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
         upd[s] = 0;
         done[s] = 0;
@@ -101,6 +101,7 @@ __global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done,
         vupd[s] = 0ull;
         vdone[s] = 0ull;
     }
+    for (int q = threadIdx.x; q < 64 * nslots; q += blockDim.x) vsw[q] = 0;
     if (threadIdx.x == 0) {
         *all_done = 0;
         *bad = 0;
@@ -112,7 +113,8 @@ __global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done,
 // independent systems on one graph, so a vector whose sweep changed nothing
 // is converged: its lane stops gathering (bit for bit the same result).
 __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* upd, int* done, int* sweeps_done,
-                                                   int* all_done, unsigned long long* vupd, unsigned long long* vdone) {
+                                                   int* all_done, unsigned long long* vupd, unsigned long long* vdone,
+                                                   int* vsw) {
     __shared__ int s_open;
     if (threadIdx.x == 0) s_open = 0;
     __syncthreads();
@@ -128,6 +130,8 @@ __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* u
             }
         }
         upd[s] = 0;
+        for (unsigned long long fresh = ~vupd[s] & ~vdone[s]; fresh; fresh &= fresh - 1)
+            vsw[64 * s + __builtin_ctzll(fresh)] = sweep + 1;
         vdone[s] |= ~vupd[s];
         vupd[s] = 0ull;
     }
@@ -577,7 +581,8 @@ __global__ __launch_bounds__(256) void k_useg(const int64_t* __restrict__ node_o
 
 // write per-item stats and measures of the union components
 __global__ void k_ufinish(int ncomp, const int32_t* __restrict__ comp_item, const int32_t* __restrict__ comp_dir,
-                          const int64_t* __restrict__ node_off, const int64_t* __restrict__ metric_slot,
+                          const int64_t* __restrict__ node_off, const int32_t* __restrict__ row_ptr,
+                          const int64_t* __restrict__ metric_slot,
                           const double* __restrict__ seg, const int* __restrict__ sweeps_done, int slot0,
                           int budget, fj_solve_stats* stats, fj_metrics_out* mets) {
     int cidx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -588,6 +593,7 @@ __global__ void k_ufinish(int ncomp, const int32_t* __restrict__ comp_item, cons
     fj_solve_stats st{};
     int sw = sweeps_done[slot0 + cidx];
     st.rounds = sw ? sw : budget;
+    st.edge_visits = st.rounds * static_cast<int64_t>(row_ptr[node_off[cidx + 1]] - row_ptr[node_off[cidx]]);
     st.max_ratio = o[4];
     st.certified = (o[4] <= 1.0) ? 1 : 0;
     stats[it] = st;
@@ -690,8 +696,9 @@ __global__ void k_mreduce(int k, int nb, const double* __restrict__ part, double
     }
 }
 
-__global__ void k_mfinish(int k, int item, int directed, int64_t n, int64_t mslot, const double* __restrict__ tot,
-                          const int* __restrict__ sweeps_done, int slot, int budget, fj_solve_stats* stats,
+__global__ void k_mfinish(int k, int item, int directed, int64_t n, int64_t nnz, int64_t mslot,
+                          const double* __restrict__ tot, const int* __restrict__ sweeps_done,
+                          const int* __restrict__ vsw, int slot, int budget, fj_solve_stats* stats,
                           fj_metrics_out* mets) {
     const int l = threadIdx.x;
     if (l >= k) return;
@@ -709,6 +716,10 @@ __global__ void k_mfinish(int k, int item, int directed, int64_t n, int64_t mslo
         fj_solve_stats st{};
         int sw = sweeps_done[slot];
         st.rounds = sw ? sw : budget;
+        // arcs gathered: each vector's row values over the sweeps until it went quiet
+        int64_t vs = 0;
+        for (int q = 0; q < k; ++q) vs += vsw[64 * slot + q] ? vsw[64 * slot + q] : st.rounds;
+        st.edge_visits = vs * nnz;
         st.max_ratio = mx;
         st.certified = mx <= 1.0 ? 1 : 0;
         stats[item] = st;
@@ -784,6 +795,7 @@ struct fj_batch {
     std::vector<double> slot_omega;   // relaxation factor per slot (union component or multi-vector item)
     double* d_slot_omega = nullptr;
     int* upd = nullptr; int* done = nullptr; int* sweeps_done = nullptr; int* all_done = nullptr; int* bad = nullptr;
+    int* vsw = nullptr;  // [nslots][64]: the sweep after which each vector went quiet (0: not yet)
     unsigned long long* vupd = nullptr; unsigned long long* vdone = nullptr;
     fj_solve_stats* stats = nullptr;
     fj_metrics_out* mets = nullptr;
@@ -840,6 +852,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
     int* upd = cv.take<int>(nslots + 1);
     int* done = cv.take<int>(nslots + 1);
     int* swd = cv.take<int>(nslots + 1);
+    int* vsw = cv.take<int>(64 * (nslots + 1));  // per slot and vector: the sweep after which it was quiet
     int* alld = cv.take<int>(1);
     int* bad = cv.take<int>(1);
     auto* vupd = cv.take<unsigned long long>(nslots + 1);
@@ -856,7 +869,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
         b->d_reopen = reopen;
         b->nslots = nslots;
         b->d_slot_omega = somega;
-        b->upd = upd; b->done = done; b->sweeps_done = swd; b->all_done = alld; b->bad = bad;
+        b->upd = upd; b->done = done; b->sweeps_done = swd; b->all_done = alld; b->bad = bad; b->vsw = vsw;
         b->vupd = vupd; b->vdone = vdone;
         b->stats = stats; b->mets = mets; b->metric_slot = mslot; b->total_k = total_k;
     }
@@ -943,7 +956,7 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
     SorState SU{U.sp, U.g.popd, U.g.pinv64, U.zh, U.zq, b->omega, 1.0 - 1e-6, epsp, nullptr, nullptr};
     if (init) {
         hipLaunchKernelGGL(k_flags_reset, dim3(1), dim3(256), 0, st, b->nslots, b->upd, b->done, b->sweeps_done,
-                           b->all_done, b->bad, b->vupd, b->vdone);
+                           b->all_done, b->bad, b->vupd, b->vdone, b->vsw);
         ++launches;
         if (b->bound) {
             enqueue_bound_copy(b, st, b->d_copy_in);
@@ -997,7 +1010,7 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
             }
         }
         hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, st, b->nslots, sw, b->upd, b->done, b->sweeps_done,
-                           b->all_done, b->vupd, b->vdone);
+                           b->all_done, b->vupd, b->vdone, b->vsw);
         ++launches;
     }
     // results
@@ -1019,7 +1032,8 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
         hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
                            U.seg, 1);
         hipLaunchKernelGGL(k_ufinish, dim3(g1d(U.ncomp, 256)), dim3(256), 0, st, U.ncomp, U.d_comp_item, U.comp_dir,
-                           U.d_node_off, b->metric_slot, U.seg, b->sweeps_done, 0, last, b->stats, b->mets);
+                           U.d_node_off, U.row_ptr, b->metric_slot, U.seg, b->sweeps_done, 0, last, b->stats,
+                           b->mets);
         launches += 7 + (nb2 ? 2 : 0);
     }
     for (size_t m = 0; m < b->M.size(); ++m) {
@@ -1033,8 +1047,8 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
             hipLaunchKernelGGL(k_mreduce, dim3(1), dim3(64), 0, st, G.k, kMBlocks, G.part, G.tot, G.means, G.g.n,
                                pass);
         }
-        hipLaunchKernelGGL(k_mfinish, dim3(1), dim3(64), 0, st, G.k, G.item, G.desc.directed, G.g.n,
-                           b->h_metric_slot[G.item], G.tot, b->sweeps_done, slot, last, b->stats, b->mets);
+        hipLaunchKernelGGL(k_mfinish, dim3(1), dim3(64), 0, st, G.k, G.item, G.desc.directed, G.g.n, G.g.nnz,
+                           b->h_metric_slot[G.item], G.tot, b->sweeps_done, b->vsw, slot, last, b->stats, b->mets);
         launches += 6;
     }
     if (b->bound) {

@@ -288,3 +288,31 @@ def test_launch_parameters_leave_results_bit_identical(weighted):
     with pytest.raises(fj.FJError):
         B2 = fj.Batch([_dev(single[0])], [1], eps=EPS)
         B2.set_launch(3, 8)
+
+
+def test_edge_visits_count_each_vector_until_quiet():
+    """Per item, edge_visits counts the arcs gathered: a single-vector graph
+    its sweeps times its arcs, a multi-vector item the sum over its vectors
+    of the sweeps until each went quiet, times the arcs.  Two identical
+    vectors go quiet together, at the item's last sweep; distinct ones add
+    up to between the slowest alone and all of them at the last sweep."""
+    import paper_2507_14864_amd as fj
+    single, multi = _items()
+    for same in (True, False):
+        k = 2 if same else 4
+        B = fj.Batch([_dev(g) for g in single] + [_dev(multi)], [1] * len(single) + [k], eps=EPS, omega=1.4)
+        _fill(B, single, multi, k)
+        if same:
+            x = B.input(len(single))
+            x[:, 1] = x[:, 0]
+        stats, _ = B.solve()
+        for i, g in enumerate(single):
+            assert stats[i]["edge_visits"] == stats[i]["rounds"] * g.nnz
+        st = stats[-1]
+        assert st["certified"] == 1 and st["edge_visits"] % multi.nnz == 0
+        per_vector = st["edge_visits"] // multi.nnz
+        if same:
+            assert per_vector == 2 * st["rounds"]
+        else:
+            assert st["rounds"] + (k - 1) <= per_vector <= k * st["rounds"]
+        B.close()
