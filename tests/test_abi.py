@@ -93,3 +93,21 @@ def test_noalloc_metrics_host_checks(lib):
     f.restype = ctypes.c_int32
     out = MetricsOut()
     assert f(None, None, None, ctypes.byref(out), None) == 1
+
+
+def test_null_handles_are_rejected_on_the_host(lib):
+    """Entry points added for tuning and measurement reject a null handle or
+    out-of-range launch parameters with FJ_ERR_INVALID_ARGUMENT (1) before
+    any device call."""
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.fj_batch_set_launch.argtypes = [vp, i32, i32]
+    lib.fj_batch_set_launch.restype = i32
+    for nch, mu in ((4, 8), (3, 8), (4, 5), (16, 8)):
+        assert lib.fj_batch_set_launch(None, nch, mu) == 1
+    lib.fj_wsnet_forward_timed.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp]
+    lib.fj_wsnet_forward_timed.restype = i32
+    ms = (ctypes.c_double * 4)()
+    assert lib.fj_wsnet_forward_timed(None, None, None, None, None, 0, ms, None) == 1
+    lib.fj_batch_set_omegas.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.fj_batch_set_omegas.restype = i32
+    assert lib.fj_batch_set_omegas(None, 1.0, 1.0, 1.0) == 1
