@@ -60,9 +60,10 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False, fr
     Colour-class sweep (pull form): per row scanned 28 B (row_ptr 4, s' 8,
     1+d 8, own zhat' 8); per updated row 20 B (1/(1+d) 8, zhat' write 8,
     fixed-point copy write 4); per arc 4 B column index plus the gathered
-    value, 8 B (FP64) or 4 B in the sweeps that gather the fixed-point copy
-    (heavy rows read 8 B there too: counted as 4, so the figure is low);
-    +4 B per arc with weights.  A row skipped by its residual bound counts
+    value, 8 B (FP64) or 4 B in the sweeps that gather the fixed-point copy,
+    where rows of more than 256 arcs still gather 8 B (light rows the copy
+    cannot resolve also do, and are counted at 4 B, so the figure is low by
+    those); +4 B per arc with weights.  A row skipped by its residual bound counts
     its row data and the bound (28 + 8 B) and none of its arcs; keeping the
     bounds (a write per swept row, an atomic add per arc of an updated row)
     is not counted.
@@ -74,7 +75,8 @@ def algorithmic_bytes(schedule, stats, n, nnz, weighted, gather_rounds=False, fr
     if schedule == "sor" or gather_rounds:
         arcs = stats["edge_visits"]
         mirror_arcs = stats["mirror_edge_visits"] if schedule == "sor" else stats.get("mirror_rounds", 0) * nnz
-        gather = 8 * (arcs - mirror_arcs) + 4 * mirror_arcs
+        mirror_fp64 = stats.get("mirror_fp64_edge_visits", 0) if schedule == "sor" else 0
+        gather = 8 * (arcs - mirror_arcs) + 4 * (mirror_arcs - mirror_fp64) + 8 * mirror_fp64
         skipped = stats.get("skipped_rows", 0)
         return (28 * stats["rounds"] * n + 8 * skipped + 20 * stats["pushes"] + 4 * arcs + gather
                 + (4 * arcs if weighted else 0))

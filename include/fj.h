@@ -208,6 +208,9 @@ typedef struct {
     int64_t mirror_edge_visits; /* arcs gathered in the sweeps that read the fixed-point copy */
     int64_t bound_adds;     /* bound skipping: FP64 atomic additions to the residual bounds of the
                                rows that read an updated value (one per arc of an updated row) */
+    int64_t mirror_fp64_edge_visits; /* of mirror_edge_visits, the arcs of rows with more than 256
+                                        arcs, which gather the FP64 estimate in every sweep (rows
+                                        the copy cannot resolve, also FP64, are not counted) */
 } fj_solve_stats;
 
 /* Bytes of solve workspace for this graph and options. */

@@ -932,9 +932,15 @@ fj_status graph_build(fj_graph* g, const fj_graph_desc* d, int32_t flags, void* 
     }
     {  // classes whose heavy rows the one-launch sweep can combine
         const TileSet& T = g->tiles_p;
-        std::vector<int32_t> hc(T.nheavy + 1);
+        std::vector<int32_t> hc(T.nheavy + 1), cb(T.nchunks), ce(T.nchunks);
         FJ_HIP(hipMemcpyAsync(hc.data(), T.heavy_chunk0, sizeof(int32_t) * (T.nheavy + 1), hipMemcpyDeviceToHost, st));
+        if (T.nchunks > 0) {
+            FJ_HIP(hipMemcpyAsync(cb.data(), T.chunk_beg, sizeof(int32_t) * T.nchunks, hipMemcpyDeviceToHost, st));
+            FJ_HIP(hipMemcpyAsync(ce.data(), T.chunk_end, sizeof(int32_t) * T.nchunks, hipMemcpyDeviceToHost, st));
+        }
         FJ_HIP(hipStreamSynchronize(st));
+        g->heavy_arcs_p = 0;
+        for (int64_t c = 0; c < T.nchunks; ++c) g->heavy_arcs_p += ce[c] - cb[c];
         g->class_packed.assign(K, 1);
         for (int k = 0; k < K; ++k)
             for (int64_t h = T.seg_heavy[k]; h < T.seg_heavy[k + 1]; ++h)

@@ -153,6 +153,7 @@ struct fj_graph {
     fj::TileSet tiles_a;   // CSR(A), original labels (certificate, measures)
     fj::TileSet tiles_t;   // CSR(A^T), original labels (push); same as tiles_a when undirected
     fj::TileSet tiles_p;   // relabelled CSR(A), one segment per colour class (SOR)
+    int64_t heavy_arcs_p = 0;  // arcs of the rows tiles_p splits into chunks (always gathered in FP64)
 };
 
 namespace fj {

@@ -785,6 +785,7 @@ struct LaunchTimer {
 struct HostStats {
     unsigned long long pushes = 0, visits = 0, skipped = 0, skipped_arcs_fix = 0, skipped_arcs_fp64 = 0;
     unsigned long long bound_adds = 0;
+    unsigned long long skipped_heavy_fix = 0;  // of skipped_arcs_fix, the arcs of heavy rows
 };
 
 fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
@@ -792,6 +793,7 @@ fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
     FJ_HIP(hipMemcpyAsync(buf.data(), L.stats, sizeof(unsigned long long) * buf.size(), hipMemcpyDeviceToHost, st));
     FJ_HIP(hipStreamSynchronize(st));
     hs->pushes = hs->visits = hs->skipped = hs->skipped_arcs_fix = hs->skipped_arcs_fp64 = hs->bound_adds = 0;
+    hs->skipped_heavy_fix = 0;
     for (int k = 0; k < kStripes; ++k) {
         hs->pushes += buf[k * kStripeStride + 0];
         hs->visits += buf[k * kStripeStride + 1];
@@ -799,7 +801,9 @@ fj_status read_stats(const SolveLayout& L, hipStream_t st, HostStats* hs) {
         hs->skipped_arcs_fix += buf[k * kStripeStride + 3];
         hs->skipped_arcs_fp64 += buf[k * kStripeStride + 4];
         hs->bound_adds += buf[k * kStripeStride + 5];
+        hs->skipped_heavy_fix += buf[k * kStripeStride + 6];
     }
+    hs->skipped_arcs_fix += hs->skipped_heavy_fix;
     return FJ_OK;
 }
 
@@ -1586,6 +1590,7 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     out->skipped_rows = static_cast<int64_t>(hs.skipped);
     out->skipped_arcs = static_cast<int64_t>(hs.skipped_arcs_fix + hs.skipped_arcs_fp64);
     out->mirror_edge_visits = mirror_sweeps * g->nnz - static_cast<int64_t>(hs.skipped_arcs_fix);
+    out->mirror_fp64_edge_visits = mirror_sweeps * g->heavy_arcs_p - static_cast<int64_t>(hs.skipped_heavy_fix);
     out->bound_adds = static_cast<int64_t>(hs.bound_adds);
     out->pushes = static_cast<int64_t>(hs.pushes);
     out->edge_visits = sweeps * g->nnz - static_cast<int64_t>(hs.skipped_arcs_fix + hs.skipped_arcs_fp64);

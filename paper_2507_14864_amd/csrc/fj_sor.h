@@ -537,8 +537,8 @@ __global__ __launch_bounds__(kBlock) void k_sor_class(TileView tv, const int32_t
             rd = row_load(row, S);  // the same address in every lane
             if (bound_quiet(S.ub[row], rd, S)) {
                 if (lane == 0 && cidx == tv.heavy_chunk0[h]) {
-                    stripe_add(stats, 2, 1ull);
-                    stripe_add(stats, MIRROR ? 3 : 4,
+                    stripe_add(stats, 2, 1ull);  // heavy rows' skipped arcs: counter 6 or 4
+                    stripe_add(stats, MIRROR ? 6 : 4,
                                static_cast<unsigned long long>(prow_ptr[row + 1] - prow_ptr[row]));
                     if constexpr (SHADOW) keep_row<SHADOW>(row, rd, S);
                 }

@@ -66,7 +66,8 @@ class SolveStats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int64), ("num_colours", ctypes.c_int32),
                 ("mirror_rounds", ctypes.c_int64), ("merged_classes", ctypes.c_int32),
                 ("skipped_rows", ctypes.c_int64), ("skipped_arcs", ctypes.c_int64),
-                ("mirror_edge_visits", ctypes.c_int64), ("bound_adds", ctypes.c_int64)]
+                ("mirror_edge_visits", ctypes.c_int64), ("bound_adds", ctypes.c_int64),
+                ("mirror_fp64_edge_visits", ctypes.c_int64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

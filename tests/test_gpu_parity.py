@@ -603,6 +603,11 @@ def test_bound_skipping_is_bit_exact(directed, weighted, precision, gather_bits,
     kw = dict(eps=1e-5, omega=omega, schedule="sor", precision=precision, gather_bits=gather_bits)
     z0, st0 = fj.solve(G, sd, skip_below=-1.0, **kw)
     assert st0["certified"] == 1 and st0["skipped_rows"] == 0
+    # rows of more than 256 arcs gather FP64 in every fixed-point sweep
+    deg = np.diff(g.row_ptr)
+    heavy_arcs = int(deg[deg > 256].sum())
+    assert heavy_arcs > 0
+    assert st0["mirror_fp64_edge_visits"] == st0["mirror_rounds"] * heavy_arcs
     for below in (1.0, 0.0):
         z1, st1 = fj.solve(G, sd, skip_below=below, **kw)
         assert torch.equal(z0, z1), below
@@ -612,6 +617,7 @@ def test_bound_skipping_is_bit_exact(directed, weighted, precision, gather_bits,
         # arcs gathered plus arcs of skipped rows cover every sweep
         assert st1["edge_visits"] + st1["skipped_arcs"] == st1["rounds"] * g.nnz
         assert 0 <= st1["mirror_edge_visits"] <= st1["mirror_rounds"] * g.nnz
+        assert 0 <= st1["mirror_fp64_edge_visits"] <= min(st1["mirror_edge_visits"], st1["mirror_rounds"] * heavy_arcs)
 
 
 def test_refinement_reseeds_from_the_fp64_residual():
