@@ -389,15 +389,18 @@ fj_status fj_batch_io(const fj_batch* b, int32_t item, double** s, double** z);
  * (undirected single-vector items, directed single-vector items, each
  * multi-vector item), the one that needed the fewest sweeps; then times the
  * launch parameters at those omegas, one at a time: 64-arc chunks in flight
- * per light tile of the single-vector union (2, 4 or 8) and arcs in flight
- * per lane of the multi-vector rows (2, 4 or 8), which leave the sums and the
- * result unchanged.  The choice is kept for the life of the process under the
+ * per light tile of the single-vector union (2, 4 or 8) and value rows in
+ * flight per wave of the multi-vector rows (4, 8 or 16), which leave the sums
+ * and the result unchanged.  The choice is kept for the life of the process under the
  * batch's shape (eps, c, sigma; per group the item count and the base-2
  * magnitude of nodes and arcs; per multi-vector item k, nodes, arcs and
  * direction): a later batch of the same shape takes it without timing (one
  * solve still measures the sweeps its inputs need).  The sweep budget is the
  * sweeps needed plus max(4, 25%), and the launch sequence is recorded into a
- * hipGraph that fj_solve_batched replays.  [host] omegas.
+ * hipGraph that fj_solve_batched replays, with the single-vector union and
+ * the multi-vector items as two concurrent branches (independent systems;
+ * each branch decides its own convergence, so the result is the same as
+ * the one-stream sequence's, bit for bit).  [host] omegas.
  * FJ_ERR_NOT_CONVERGED if an item needs more than 512 sweeps for every
  * candidate. */
 fj_status fj_batch_tune(fj_batch* b, const double* omegas, int32_t n_omegas, void* stream);

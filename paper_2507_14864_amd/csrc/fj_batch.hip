@@ -103,7 +103,7 @@ __global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done,
     }
     for (int q = threadIdx.x; q < 64 * nslots; q += blockDim.x) vsw[q] = 0;
     if (threadIdx.x == 0) {
-        *all_done = 0;
+        all_done[0] = all_done[1] = 0;
         *bad = 0;
     }
 }
@@ -112,7 +112,9 @@ __global__ void k_flags_reset(int nslots, int* upd, int* done, int* sweeps_done,
 // sweep / had a sweep without an update.  The vectors of an item are
 // independent systems on one graph, so a vector whose sweep changed nothing
 // is converged: its lane stops gathering (bit for bit the same result).
-__global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* upd, int* done, int* sweeps_done,
+// Slots [s0, s1) are one branch (the union's components, or the multi-vector
+// items), whose launches all test that branch's all_done flag.
+__global__ __launch_bounds__(256) void k_sweep_end(int s0, int s1, int sweep, int* upd, int* done, int* sweeps_done,
                                                    int* all_done, unsigned long long* vupd, unsigned long long* vdone,
                                                    int* vsw) {
     __shared__ int s_open;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void k_sweep_end(int nslots, int sweep, int* u
     __syncthreads();
     if (*all_done) return;
     int open = 0;
-    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+    for (int s = s0 + static_cast<int>(threadIdx.x); s < s1; s += blockDim.x) {
         if (!done[s]) {
             if (!upd[s]) {
                 done[s] = 1;
@@ -735,7 +737,8 @@ __global__ void k_batch_copy(const fj_batch_copy* __restrict__ tab) {
         e.dst[q] = e.src[q];
 }
 
-// reopen the listed slots for more sweeps (their vectors too)
+// reopen the listed slots for more sweeps (their vectors too); both branch
+// flags reopen (a branch with no open slot closes again at its next sweep end)
 __global__ void k_reopen(int count, const int* __restrict__ slots, int* done, int* sweeps_done, int* all_done,
                          unsigned long long* vdone) {
     for (int q = threadIdx.x; q < count; q += blockDim.x) {
@@ -744,7 +747,7 @@ __global__ void k_reopen(int count, const int* __restrict__ slots, int* done, in
         sweeps_done[sl] = 0;
         vdone[sl] = 0ull;
     }
-    if (threadIdx.x == 0) *all_done = 0;
+    if (threadIdx.x == 0) all_done[0] = all_done[1] = 0;
 }
 
 }  // namespace
@@ -788,13 +791,15 @@ struct fj_batch {
     std::vector<int> item_group;  // -1 union, else index into M
     double eps = 0, omega = 1, c = 0, sigma = 1, epsp = 0;
     int budget = 256;
+    bool concurrent = true;  // recorded graph: union and multi-vector branches concurrent
     bool has_union = false;
     UnionGroup U;
     std::vector<MrhsGroup> M;
     int nslots = 0;
     std::vector<double> slot_omega;   // relaxation factor per slot (union component or multi-vector item)
     double* d_slot_omega = nullptr;
-    int* upd = nullptr; int* done = nullptr; int* sweeps_done = nullptr; int* all_done = nullptr; int* bad = nullptr;
+    int* upd = nullptr; int* done = nullptr; int* sweeps_done = nullptr; int* bad = nullptr;
+    int* all_done = nullptr;  // [2]: every slot of the union branch / of the multi-vector branch done
     int* vsw = nullptr;  // [nslots][64]: the sweep after which each vector went quiet (0: not yet)
     unsigned long long* vupd = nullptr; unsigned long long* vdone = nullptr;
     fj_solve_stats* stats = nullptr;
@@ -853,7 +858,7 @@ size_t carve_batch(fj_batch* b, const fj_batch_item_desc* items, int32_t num, vo
     int* done = cv.take<int>(nslots + 1);
     int* swd = cv.take<int>(nslots + 1);
     int* vsw = cv.take<int>(64 * (nslots + 1));  // per slot and vector: the sweep after which it was quiet
-    int* alld = cv.take<int>(1);
+    int* alld = cv.take<int>(2);  // per branch: union components, multi-vector items
     int* bad = cv.take<int>(1);
     auto* vupd = cv.take<unsigned long long>(nslots + 1);
     auto* vdone = cv.take<unsigned long long>(nslots + 1);
@@ -947,8 +952,15 @@ void enqueue_bound_copy(fj_batch* b, hipStream_t st, const fj_batch_copy* tab) {
 // start (flags, shift, zero estimate) and sweeps [0, budget); without it,
 // sweeps [first, first + budget) continuing from the state in place (slots
 // reopened by k_reopen).  Then the results of every item.
+// A second stream and two events that let the union and the multi-vector
+// branch of a solve run concurrently (used while recording the graph).
+struct BranchFork {
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+
 fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_out, int first = 0,
-                        bool init = true) {
+                        bool init = true, const BranchFork* fork = nullptr) {
     int launches = 0;
     const int bs = 256;
     UnionGroup& U = b->U;
@@ -979,77 +991,103 @@ fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_o
             launches += 2;
         }
     }
-    int max_cls = b->has_union ? U.g.num_colours : 0;
-    for (auto& G : b->M) max_cls = std::max(max_cls, G.g.num_colours);
     const int last = first + budget;
-    for (int sw = first; sw < last; ++sw) {
-        for (int k = 0; k < max_cls; ++k) {
-            if (b->has_union && k < U.g.num_colours) {
+    // The union's components and the multi-vector items are independent
+    // systems: each branch sweeps its own classes and keeps its own sweep
+    // bookkeeping, so with a side stream the two run concurrently (a fork
+    // before the sweeps, a join after the results); otherwise one after the
+    // other on `st`.  Either way every item's arithmetic is the same.
+    auto union_branch = [&](hipStream_t bs_st) {
+        if (!b->has_union) return;
+        for (int sw = first; sw < last; ++sw) {
+            for (int k = 0; k < U.g.num_colours; ++k) {
                 TileView tv = tile_view(U.g.tiles_p, k);
                 if (tv.ntiles + tv.nchunks > 0) {
                     auto kern = b->nch == 2 ? k_usor_tiles<2> : b->nch == 8 ? k_usor_tiles<8> : k_usor_tiles<4>;
                     hipLaunchKernelGGL(kern, dim3(waves_to_blocks(tv.nchunks + tv.ntiles)), dim3(kBlock), 0,
-                                       st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.hcnt, U.pcomp,
+                                       bs_st, tv, U.g.prow_ptr, U.g.pcol, U.g.pw, SU, U.partial, U.hcnt, U.pcomp,
                                        b->d_slot_omega, b->upd, b->done, b->all_done, b->bad);
                     ++launches;
                 }
             }
-            for (size_t m = 0; m < b->M.size(); ++m) {
-                MrhsGroup& G = b->M[m];
-                if (k >= G.g.num_colours) continue;
-                const int slot = U.ncomp + static_cast<int>(m);
-                MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->slot_omega[slot], 1.0 - 1e-6, epsp, G.k,
-                         b->vdone + slot, b->vupd + slot};
-                TileView tv = tile_view(G.g.tiles_p, k);
-                const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
-                auto kern = b->mu == 4 ? k_msor_class<4> : b->mu == 16 ? k_msor_class<16> : k_msor_class<8>;
-                hipLaunchKernelGGL(kern, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, st,
-                                   tv, rb, re, G.g.prow_ptr, G.g.pcol, G.g.pw, S, G.partial, G.hcnt, b->upd + slot,
-                                   b->done + slot, b->all_done, b->bad);
-                ++launches;
-            }
+            hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, bs_st, 0, U.ncomp, sw, b->upd, b->done,
+                               b->sweeps_done, b->all_done, b->vupd, b->vdone, b->vsw);
+            ++launches;
         }
-        hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, st, b->nslots, sw, b->upd, b->done, b->sweeps_done,
-                           b->all_done, b->vupd, b->vdone, b->vsw);
-        ++launches;
-    }
-    // results
-    if (b->has_union && U.n > 0) {
-        hipLaunchKernelGGL(k_sor_unshift, dim3(g1d(U.n, bs)), dim3(bs), 0, st, U.n, U.g.perm, U.zh, b->c, U.z_out,
+        if (U.n == 0) return;
+        hipLaunchKernelGGL(k_sor_unshift, dim3(g1d(U.n, bs)), dim3(bs), 0, bs_st, U.n, U.g.perm, U.zh, b->c, U.z_out,
                            static_cast<double*>(nullptr));
         TileView ta = tile_view_all(U.g.tiles_a);
         const unsigned nb1 = waves_to_blocks(ta.nchunks + ta.ntiles), nb2 = waves_to_blocks(ta.h1 - ta.h0);
-        hipLaunchKernelGGL(k_urows_tiles<0>, dim3(nb1), dim3(kBlock), 0, st, ta, U.row_ptr, U.col, U.w, U.s_in,
+        hipLaunchKernelGGL(k_urows_tiles<0>, dim3(nb1), dim3(kBlock), 0, bs_st, ta, U.row_ptr, U.col, U.w, U.s_in,
                            U.z_out, U.g.opd, b->c, epsp, U.partial, U.ratio);
-        if (nb2) hipLaunchKernelGGL(k_urows_heavy<0>, dim3(nb2), dim3(kBlock), 0, st, ta, U.s_in, U.z_out, U.g.opd,
-                                    b->c, epsp, U.partial, U.ratio);
-        hipLaunchKernelGGL(k_urows_tiles<1>, dim3(nb1), dim3(kBlock), 0, st, ta, U.row_ptr, U.col, U.w, U.s_in,
+        if (nb2) hipLaunchKernelGGL(k_urows_heavy<0>, dim3(nb2), dim3(kBlock), 0, bs_st, ta, U.s_in, U.z_out,
+                                    U.g.opd, b->c, epsp, U.partial, U.ratio);
+        hipLaunchKernelGGL(k_urows_tiles<1>, dim3(nb1), dim3(kBlock), 0, bs_st, ta, U.row_ptr, U.col, U.w, U.s_in,
                            U.z_out, U.g.opd, b->c, epsp, U.partial, U.drow);
-        if (nb2) hipLaunchKernelGGL(k_urows_heavy<1>, dim3(nb2), dim3(kBlock), 0, st, ta, U.s_in, U.z_out, U.g.opd,
-                                    b->c, epsp, U.partial, U.drow);
-        hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
+        if (nb2) hipLaunchKernelGGL(k_urows_heavy<1>, dim3(nb2), dim3(kBlock), 0, bs_st, ta, U.s_in, U.z_out,
+                                    U.g.opd, b->c, epsp, U.partial, U.drow);
+        hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, bs_st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
                            U.seg, 0);
-        hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
+        hipLaunchKernelGGL(k_useg, dim3(U.ncomp), dim3(256), 0, bs_st, U.d_node_off, U.s_in, U.z_out, U.drow, U.ratio,
                            U.seg, 1);
-        hipLaunchKernelGGL(k_ufinish, dim3(g1d(U.ncomp, 256)), dim3(256), 0, st, U.ncomp, U.d_comp_item, U.comp_dir,
-                           U.d_node_off, U.row_ptr, b->metric_slot, U.seg, b->sweeps_done, 0, last, b->stats,
-                           b->mets);
+        hipLaunchKernelGGL(k_ufinish, dim3(g1d(U.ncomp, 256)), dim3(256), 0, bs_st, U.ncomp, U.d_comp_item,
+                           U.comp_dir, U.d_node_off, U.row_ptr, b->metric_slot, U.seg, b->sweeps_done, 0, last,
+                           b->stats, b->mets);
         launches += 7 + (nb2 ? 2 : 0);
-    }
-    for (size_t m = 0; m < b->M.size(); ++m) {
-        MrhsGroup& G = b->M[m];
-        const int slot = U.ncomp + static_cast<int>(m);
-        hipLaunchKernelGGL(k_munshift, dim3(g1d(G.g.n * G.k, bs)), dim3(bs), 0, st, G.g.n, G.k, G.g.perm, G.zh, b->c,
-                           G.z_out);
-        for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_mresults, dim3(kMBlocks), dim3(kBlock), 0, st, G.g.n, G.k, G.desc.row_ptr,
-                               G.desc.col, G.desc.w, G.g.opd, G.s_in, G.z_out, b->c, epsp, G.means, G.part, pass);
-            hipLaunchKernelGGL(k_mreduce, dim3(1), dim3(64), 0, st, G.k, kMBlocks, G.part, G.tot, G.means, G.g.n,
-                               pass);
+    };
+    auto multi_branch = [&](hipStream_t bs_st) {
+        if (b->M.empty()) return;
+        int max_cls = 0;
+        for (auto& G : b->M) max_cls = std::max(max_cls, G.g.num_colours);
+        for (int sw = first; sw < last; ++sw) {
+            for (int k = 0; k < max_cls; ++k) {
+                for (size_t m = 0; m < b->M.size(); ++m) {
+                    MrhsGroup& G = b->M[m];
+                    if (k >= G.g.num_colours) continue;
+                    const int slot = U.ncomp + static_cast<int>(m);
+                    MState S{G.sp, G.g.popd, G.g.pinv64, G.zh, b->slot_omega[slot], 1.0 - 1e-6, epsp, G.k,
+                             b->vdone + slot, b->vupd + slot};
+                    TileView tv = tile_view(G.g.tiles_p, k);
+                    const int64_t rb = G.g.class_off[k], re = G.g.class_off[k + 1];
+                    auto kern = b->mu == 4 ? k_msor_class<4> : b->mu == 16 ? k_msor_class<16> : k_msor_class<8>;
+                    hipLaunchKernelGGL(kern, dim3(waves_to_blocks(tv.nchunks + (re - rb))), dim3(kBlock), 0, bs_st,
+                                       tv, rb, re, G.g.prow_ptr, G.g.pcol, G.g.pw, S, G.partial, G.hcnt,
+                                       b->upd + slot, b->done + slot, b->all_done + 1, b->bad);
+                    ++launches;
+                }
+            }
+            hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, bs_st, U.ncomp, b->nslots, sw, b->upd, b->done,
+                               b->sweeps_done, b->all_done + 1, b->vupd, b->vdone, b->vsw);
+            ++launches;
         }
-        hipLaunchKernelGGL(k_mfinish, dim3(1), dim3(64), 0, st, G.k, G.item, G.desc.directed, G.g.n, G.g.nnz,
-                           b->h_metric_slot[G.item], G.tot, b->sweeps_done, b->vsw, slot, last, b->stats, b->mets);
-        launches += 6;
+        for (size_t m = 0; m < b->M.size(); ++m) {
+            MrhsGroup& G = b->M[m];
+            const int slot = U.ncomp + static_cast<int>(m);
+            hipLaunchKernelGGL(k_munshift, dim3(g1d(G.g.n * G.k, bs)), dim3(bs), 0, bs_st, G.g.n, G.k, G.g.perm, G.zh,
+                               b->c, G.z_out);
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_mresults, dim3(kMBlocks), dim3(kBlock), 0, bs_st, G.g.n, G.k, G.desc.row_ptr,
+                                   G.desc.col, G.desc.w, G.g.opd, G.s_in, G.z_out, b->c, epsp, G.means, G.part, pass);
+                hipLaunchKernelGGL(k_mreduce, dim3(1), dim3(64), 0, bs_st, G.k, kMBlocks, G.part, G.tot, G.means,
+                                   G.g.n, pass);
+            }
+            hipLaunchKernelGGL(k_mfinish, dim3(1), dim3(64), 0, bs_st, G.k, G.item, G.desc.directed, G.g.n, G.g.nnz,
+                               b->h_metric_slot[G.item], G.tot, b->sweeps_done, b->vsw, slot, last, b->stats,
+                               b->mets);
+            launches += 6;
+        }
+    };
+    if (fork && b->has_union && !b->M.empty()) {
+        FJ_HIP(hipEventRecord(fork->ev_fork, st));
+        FJ_HIP(hipStreamWaitEvent(fork->side, fork->ev_fork, 0));
+        union_branch(st);
+        multi_branch(fork->side);
+        FJ_HIP(hipEventRecord(fork->ev_join, fork->side));
+        FJ_HIP(hipStreamWaitEvent(st, fork->ev_join, 0));
+    } else {
+        union_branch(st);
+        multi_branch(st);
     }
     if (b->bound) {
         enqueue_bound_copy(b, st, b->d_copy_out);
@@ -1267,17 +1305,27 @@ fj_status record_graph(fj_batch* b) {
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     b->graph_nodes = 0;
     hipStream_t cap = nullptr;
-    FJ_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    BranchFork fork;
+    auto release = [&]() {
+        if (cap) (void)hipStreamDestroy(cap);
+        if (fork.side) (void)hipStreamDestroy(fork.side);
+        if (fork.ev_fork) (void)hipEventDestroy(fork.ev_fork);
+        if (fork.ev_join) (void)hipEventDestroy(fork.ev_join);
+    };
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&fork.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork.ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork.ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        (void)hipStreamDestroy(cap);
-        return hip_fail(e, "hipStreamBeginCapture");
+        release();
+        return hip_fail(e, "recording the batch graph");
     }
     int launches = 0;
-    fj_status rc = enqueue_solve(b, cap, b->budget, &launches);
+    fj_status rc = enqueue_solve(b, cap, b->budget, &launches, 0, true, b->concurrent ? &fork : nullptr);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
-    (void)hipStreamDestroy(cap);
+    release();
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
