@@ -153,30 +153,28 @@ __global__ void k_s_final(int nb, int64_t n, const double* __restrict__ part, do
     }
 }
 
-// rs_i = sum_j a_ij s_j over CSR(A) from the FP32 copy: eight lanes per row
-// (lane p takes arcs p, p + 8, ...), eight rows per wave, a fixed-order fold;
-// rows longer than kArcBudget are left to k_nbr_heavy
-__global__ __launch_bounds__(kBlock) void k_nbr_rows(int64_t n, const int32_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
-                                                    const float* __restrict__ s32, float* rs) {
-    const int lane = lane_id(), p = lane & 7;
-    const int64_t groups = (n + 7) / 8;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
-    for (int64_t gi = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave_id(); gi < groups;
-         gi += stride) {
-        const int64_t i = gi * 8 + (lane >> 3);
-        int b = 0, e = 0;
-        if (i < n) {
-            b = row_ptr[i];
-            e = row_ptr[i + 1];
-            if (e - b > kArcBudget) e = b;
-        }
-        float acc = 0.f;
-        for (int k = b + p; k < e; k += 8) acc += (w ? w[k] : 1.0f) * s32[col[k]];
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 64);
-        if (p == 0 && i < n && row_ptr[i + 1] - row_ptr[i] <= kArcBudget) rs[i] = acc;
-    }
+// rs_i = sum_j a_ij s_j over CSR(A) from the FP32 copy of s, by the
+// merge-path tiles of CSR(A): a wave takes a tile of up to 64 light rows and
+// streams its arcs in order, four 64-arc chunks in flight, the per-row sums by
+// a fixed-order segmented scan (FP64, rounded to FP32 once); heavy tiles are
+// left to k_nbr_chunks
+__global__ __launch_bounds__(kBlock) void k_nbr_tiles(TileView tv, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                     const float* __restrict__ s32, float* rs) {
+    __shared__ int s_pre[kWavesPerBlock][65];
+    __shared__ double s_acc[kWavesPerBlock][64];
+    const int wid = wave_id(), lane = lane_id();
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    if (t >= tv.ntiles) return;
+    const int64_t tix = tv.t0 + t;
+    if (tv.tile_heavy[tix] >= 0) return;
+    const int32_t r0 = tv.tile_start[tix];
+    const int nrows = tv.tile_start[tix + 1] - r0;
+    const double sum = tile_row_sums(row_ptr, r0, nrows, s_pre[wid], s_acc[wid], [&](int k) {
+        const double a = w ? static_cast<double>(w[k]) : 1.0;
+        return a * static_cast<double>(s32[col[k]]);
+    });
+    if (lane < nrows) rs[r0 + lane] = static_cast<float>(sum);
 }
 // Heavy rows of CSR(A) (more than kArcBudget arcs) in 256-arc chunks, a wave
 // per chunk: partial sums per chunk, then k_nbr_combine adds a row's chunks in
@@ -229,10 +227,19 @@ __global__ __launch_bounds__(kBlock) void k_agg_rows16(int64_t n, const int32_t*
             if (e - b > kArcBudget) e = b;  // heavy: k_agg16_chunks
         }
         Acc8 acc{};
-        for (int k = b + sub; k < e; k += 4) {
-            const int j = col[k];
-            const float a = w ? w[k] : 1.0f;
-            acc8_add(acc, a, reinterpret_cast<const uint4*>(X)[2 * static_cast<int64_t>(j) + half]);
+        // each lane's next column index loads while its current row is gathered
+        int k = b + sub;
+        int j = k < e ? col[k] : 0;
+        float a = k < e ? (w ? w[k] : 1.0f) : 0.0f;
+        while (k < e) {
+            const uint4 x = reinterpret_cast<const uint4*>(X)[2 * static_cast<int64_t>(j) + half];
+            const int kn = k + 4;
+            const int jn = kn < e ? col[kn] : 0;
+            const float an = kn < e ? (w ? w[kn] : 1.0f) : 0.0f;
+            acc8_add(acc, a, x);
+            k = kn;
+            j = jn;
+            a = an;
         }
 #pragma unroll
         for (int o = 2; o < 8; o <<= 1)
@@ -902,8 +909,9 @@ fj_status net_forward(const fj_graph* g, const double* s, const float* params, d
     hipLaunchKernelGGL(k_s_final, dim3(1), dim3(64), 0, st, kStatBlocks, n, L.stats_part, L.stats);
     const TileView ta = tile_view_all(g->tiles_a);
     // layer 1's message: the neighbour sum of s over CSR(A)
-    hipLaunchKernelGGL(k_nbr_rows, dim3(stride_blocks(g1d(n, 8))), dim3(kBlock), 0, st, n, g->row_ptr, g->col, g->w,
-                       L.s32, L.rs);
+    if (ta.ntiles > 0)
+        hipLaunchKernelGGL(k_nbr_tiles, dim3(waves_to_blocks(ta.ntiles)), dim3(kBlock), 0, st, ta, g->row_ptr, g->col,
+                           g->w, L.s32, L.rs);
     if (ta.h1 > ta.h0) {
         hipLaunchKernelGGL(k_nbr_chunks, dim3(waves_to_blocks(ta.nchunks)), dim3(kBlock), 0, st, ta, g->col, g->w,
                            L.s32, L.cpart);
