@@ -77,8 +77,12 @@ def test_lemma6_one_sided_at_omega_one(prob, eps):
     assert not p["capped"] and not p["diverged"]
     zh = p["z"] + C
     assert np.all(p["r"] >= 0.0)
-    assert np.all(zh <= zt * (1 + 1e-13))
-    assert np.all(zh >= (1 - epsp) * zt * (1 - 1e-13))
+    # the LU reference itself is off by rounding, absolutely: where z = 0
+    # exactly (s_v = 0 and no path to a positive opinion) it can return
+    # -3e-17, below zhat' = c; hence the 1e-15 absolute slack beside the
+    # relative one
+    assert np.all(zh <= zt * (1 + 1e-13) + 1e-15)
+    assert np.all(zh >= (1 - epsp) * zt * (1 - 1e-13) - 1e-15)
 
 
 @SETTINGS
