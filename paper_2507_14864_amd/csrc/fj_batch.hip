@@ -948,10 +948,6 @@ void enqueue_bound_copy(fj_batch* b, hipStream_t st, const fj_batch_copy* tab) {
                        0, st, tab);
 }
 
-// Enqueue a batched solve (capture-safe: kernels only): with `init`, the
-// start (flags, shift, zero estimate) and sweeps [0, budget); without it,
-// sweeps [first, first + budget) continuing from the state in place (slots
-// reopened by k_reopen).  Then the results of every item.
 // A second stream and two events that let the union and the multi-vector
 // branch of a solve run concurrently (used while recording the graph).
 struct BranchFork {
@@ -959,6 +955,11 @@ struct BranchFork {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
+// Enqueue a batched solve (capture-safe: kernels only): with `init`, the
+// start (flags, shift, zero estimate) and sweeps [0, budget); without it,
+// sweeps [first, first + budget) continuing from the state in place (slots
+// reopened by k_reopen).  Then the results of every item.  With `fork`, the
+// multi-vector branch goes to fork->side between a fork and a join on `st`.
 fj_status enqueue_solve(fj_batch* b, hipStream_t st, int budget, int* launches_out, int first = 0,
                         bool init = true, const BranchFork* fork = nullptr) {
     int launches = 0;
