@@ -177,7 +177,10 @@ typedef struct {
                                 row whose bound, plus the rounding of its gathered sum, stays
                                 below its update threshold keeps its value without gathering.
                                 It would not have updated: the result is bit for bit the one
-                                without skipping.  0 selects 0.05; negative: never */
+                                without skipping.  0 selects 0.05 on graphs of at least 2^24
+                                stored arcs and no skipping on smaller ones (their sweeps are
+                                bound by launches, which the bookkeeping only adds to);
+                                positive: that fraction at any size; negative: never */
     fj_metrics_out* measures; /* [host] or NULL: also the Table 1 measures of the returned z, as
                                 fj_metrics gives them (within rounding: the sums run in another
                                 order).  FJ_SCHED_SOR forms D in the gather pass of its final

@@ -19,6 +19,10 @@ constexpr int kStripeStride = 16;  // u64 per stripe line
 constexpr int kMaxColours = 2048;  // colour classes supported by the permutation pass
 // bound skipping starts once a sweep updated fewer than this fraction of the rows
 constexpr double kSkipBelow = 0.05;
+// by default only on graphs with at least this many stored arcs: below it a
+// sweep is bound by its launches, and the per-sweep bookkeeping launch and the
+// heavier kernel variant cost more than the skipped gathers save
+constexpr int64_t kSkipMinArcs = int64_t{1} << 24;
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string& msg);

@@ -1412,7 +1412,8 @@ fj_status solve_sor(const fj_graph* g, const double* s, const fj_solve_opts* o, 
     // in k_sor_class (which keeps the bounds).  Considered from the second sweep of each phase (fixed-point
     // sweeps, FP64 sweeps, each refinement), once a sweep updated fewer than
     // `limit` rows.
-    bool skipping = o->skip_below >= 0.0 && n > 0 && S64.brow != nullptr;
+    bool skipping = o->skip_below >= 0.0 && n > 0 && S64.brow != nullptr &&
+                    (o->skip_below > 0.0 || g->nnz >= kSkipMinArcs);
     for (int k = 0; k < nc && skipping; ++k)
         if (!g->class_packed[k]) skipping = false;
     const double limit = (o->skip_below > 0.0 ? o->skip_below : kSkipBelow) * static_cast<double>(n);

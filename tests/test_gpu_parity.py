@@ -591,8 +591,9 @@ def test_bound_skipping_is_bit_exact(directed, weighted, precision, gather_bits,
     reads, Lemma 4) plus its gather rounding stays below the threshold, so it
     would not have updated: the same z bit for bit, the same sweeps and
     updates, with and without skipping (bounds from the second sweep and
-    skipping from the third with skip_below = 1, and at the default); merged
-    tail included.  On directed graphs the rows to raise come from the
+    skipping from the third with skip_below = 1, and at the default fraction
+    0.05 set explicitly, since by default a graph of under 2^24 arcs does not
+    skip); merged tail included.  On directed graphs the rows to raise come from the
     relabelled CSR(A^T), so a slip there (a missing or misweighted reader)
     would let a row skip an update and change z."""
     fj = fjmod()
@@ -608,7 +609,9 @@ def test_bound_skipping_is_bit_exact(directed, weighted, precision, gather_bits,
     heavy_arcs = int(deg[deg > 256].sum())
     assert heavy_arcs > 0
     assert st0["mirror_fp64_edge_visits"] == st0["mirror_rounds"] * heavy_arcs
-    for below in (1.0, 0.0):
+    zd, std = fj.solve(G, sd, **kw)  # the default: no skipping at this size
+    assert g.nnz < 1 << 24 and std["skipped_rows"] == 0 and torch.equal(z0, zd)
+    for below in (1.0, 0.05):
         z1, st1 = fj.solve(G, sd, skip_below=below, **kw)
         assert torch.equal(z0, z1), below
         assert (st1["rounds"], st1["pushes"], st1["max_ratio"]) == (st0["rounds"], st0["pushes"], st0["max_ratio"])

@@ -4,8 +4,8 @@ Every example draws a graph on 1..48 nodes (directed or undirected, unit or
 U[0.5, 1.5] weights, any density), opinions with zeros among them, a
 schedule and a relaxation factor it supports (colour-ordered sweeps: omega in
 (0, 2) on undirected graphs, (0, 1] on directed ones, where I + L is only
-row diagonally dominant; push rounds: omega in (0, 1]), a precision and eps,
-and checks the result against the dense definition z = (I+L)^{-1} s (Lemma 1,
+row diagonally dominant; push rounds: omega in (0, 1]), a precision, eps
+and a bound-skipping setting (default, forced, never), and checks the result against the dense definition z = (I+L)^{-1} s (Lemma 1,
 LU in the oracle): the entrywise bound of Lemma 7, the relative-error claim,
 the certificate recomputed by the oracle, and the measures returned with the
 solve against the oracle's measures of the same z.  Examples are
@@ -75,18 +75,21 @@ def problems(draw, max_n=48):
     omega = draw(st.floats(0.3, hi))
     precision = draw(st.sampled_from(["fp32", "fp64"]))
     eps = draw(st.sampled_from([1e-3, 1e-5, 1e-7]))
-    return g, s, schedule, omega, precision, eps
+    # bound skipping: the default (off below 2^24 arcs), forced at two
+    # fractions, or never
+    skip_below = draw(st.sampled_from([0.0, 0.05, 1.0, -1.0]))
+    return g, s, schedule, omega, precision, eps, skip_below
 
 
 @given(problems())
 @SETTINGS
 def test_random_small_graphs_against_the_dense_solution(prob):
     import paper_2507_14864_amd as fj
-    g, s, schedule, omega, precision, eps = prob
+    g, s, schedule, omega, precision, eps, skip_below = prob
     zt = oracle.dense_solve(g, s)
     G = fj.Graph.from_host(g, DEV, colour=schedule == "sor")
     z, st_ = fj.solve(G, torch.from_numpy(s).to(DEV), eps=eps, omega=omega, c=C, sigma=SIGMA,
-                      precision=precision, schedule=schedule, measures=True)
+                      precision=precision, schedule=schedule, measures=True, skip_below=skip_below)
     assert st_["certified"] == 1
     zc = z.cpu().numpy()
     epsp = SIGMA * eps / (C + SIGMA)
