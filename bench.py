@@ -288,6 +288,16 @@ def batch_eval(dev, steps, warmup):
     # gathered value bytes: 8 per arc and vector swept (a lower bound on the
     # traffic: column indices, row data and writes come on top)
     gathered = 8 * sum(s["edge_visits"] for s in stats)
+    # all algorithmic bytes, as for the single solve: the multi-vector item per
+    # vector and row swept 24 (s' and zhat' read, zhat' written) and per arc
+    # and vector 8 (the gathered value), and per arc and sweep 4 (the column
+    # index, read once per row for all vectors); a single-vector graph per row
+    # and sweep 36 (row offset 4, s' 8, 1 + d 8, zhat' read and written 16) and
+    # per arc and sweep 12 (+4 with weights)
+    vec_sweeps = stats[0]["edge_visits"] / max(big.nnz, 1)
+    algorithmic = (24 * big.n * vec_sweeps + 8 * stats[0]["edge_visits"] + 4 * big.nnz * stats[0]["rounds"])
+    for g, st in zip(smalls, stats[1:]):
+        algorithmic += 36 * g.n * st["rounds"] + (16 if g.w is not None else 12) * st["edge_visits"]
     out = {"workload": "64 vectors (U[0,1], Beta(2,2), bimodal) on an undirected Chung-Lu graph with 2M nodes / "
                        "20M edge samples, plus 256 graphs of 1k-200k nodes (average degree 8, half directed)",
            "s_per_batch": round(dt, 5), "vector_solves_per_s": round(320 / dt, 1), "eps": 1e-4,
@@ -297,7 +307,9 @@ def batch_eval(dev, steps, warmup):
            "multi_arcs_in_flight": info["multi_arcs_in_flight"], "certified_items": cert, "items": len(stats),
            "max_sweeps_used": max(s["rounds"] for s in stats),
            "gathered_value_bytes": gathered, "gathered_GBs": round(gathered / dt / 1e9, 1),
-           "gathered_hbm_frac": round(gathered / dt / 1e9 / HBM_PEAK_GBS, 4), "ingest_s": round(ingest, 2),
+           "gathered_hbm_frac": round(gathered / dt / 1e9 / HBM_PEAK_GBS, 4),
+           "algorithmic_bytes": int(algorithmic), "algorithmic_GBs": round(algorithmic / dt / 1e9, 1),
+           "algorithmic_hbm_frac": round(algorithmic / dt / 1e9 / HBM_PEAK_GBS, 4), "ingest_s": round(ingest, 2),
            "tune_s": round(tune_s, 2), "steps": steps}
     B.close()  # release the recorded hipGraph while the runtime is up
     del B
