@@ -137,6 +137,63 @@ def test_recorded_graph_replays_match_eager():
                 assert mets_g[i][q] == mets_e[i][q]
 
 
+def test_two_multi_vector_items_in_the_concurrent_graph():
+    """Two multi-vector items (one undirected, one directed and weighted)
+    beside the single-vector union: the recorded graph runs the union and the
+    multi-vector items as two concurrent branches, each with its own sweep
+    bookkeeping over its slots.  Its replays equal an eager batch (one chain
+    on one stream) bit for bit, and sampled vectors of both items meet
+    Lemma 7's bound against the oracle's exact solution."""
+    import paper_2507_14864_amd as fj
+    single, _ = _items()
+    ma = synth.chung_lu(12000, 60000, 2.3, 530)
+    mb = synth.chung_lu(9000, 50000, 2.1, 531, directed=True, weighted=True)
+    ka, kb = 3, 7
+    multi_items = [(ma, ka, "beta"), (mb, kb, "uniform")]
+
+    def make():
+        B = fj.Batch([_dev(g) for g in single] + [_dev(ma), _dev(mb)], [1] * len(single) + [ka, kb], eps=EPS,
+                     omega=1.2)
+        ss = []
+        for i, g in enumerate(single):
+            s = synth.opinions(g.n, "uniform", 900 + i)
+            B.input(i).copy_(torch.from_numpy(s))
+            ss.append(s)
+        sm = []
+        for j, (g, k, kind) in enumerate(multi_items):
+            S = np.stack([synth.opinions(g.n, kind, 950 + 10 * j + q, a=2, b=2) if kind == "beta"
+                          else synth.opinions(g.n, kind, 950 + 10 * j + q) for q in range(k)], axis=1)
+            B.input(len(single) + j).copy_(torch.from_numpy(np.ascontiguousarray(S)))
+            sm.append(S)
+        return B, ss, sm
+
+    B, ss, sm = make()
+    info = B.tune([1.2])  # one candidate: every group at 1.2, then the graph is recorded
+    assert info["graph_nodes"] > 0
+    E, _, _ = make()
+    E.set_omegas(1.2, 1.2, 1.2)  # no recorded graph: the eager sequence
+    stats_e, mets_e = E.solve()
+    nitems = len(single) + 2
+    z_e = [E.output(i).cpu().numpy().copy() for i in range(nitems)]
+    for rep in range(2):
+        stats_g, mets_g = B.solve()
+        for i in range(nitems):
+            assert np.array_equal(B.output(i).cpu().numpy(), z_e[i]), (rep, i)
+            assert stats_g[i]["certified"] == 1 and stats_g[i]["rounds"] == stats_e[i]["rounds"]
+            assert stats_g[i]["edge_visits"] == stats_e[i]["edge_visits"]
+            for q in range(len(mets_g[i])):
+                assert mets_g[i][q] == mets_e[i][q]
+    for j, (g, k, _) in enumerate(multi_items):
+        z = B.output(len(single) + j).cpu().numpy()
+        for q in (0, k - 1):
+            zt = oracle.exact(g, sm[j][:, q])
+            _check(g, sm[j][:, q], z[:, q], zt)
+    zt = oracle.exact(single[1], ss[1])
+    _check(single[1], ss[1], B.output(1).cpu().numpy(), zt)
+    B.close()
+    E.close()
+
+
 def test_batch_rejects_bad_items():
     import paper_2507_14864_amd as fj
     g = synth.chung_lu(1000, 4000, 2.3, 530)
