@@ -383,8 +383,15 @@ struct NetIn {
 
 // X0 of row r: [s, ns, z1, log1p d, 1/(1+d), mean s, 1, 0], in FP32 (the
 // MFMA takes them in BF16)
-__device__ __forceinline__ void features8(const NetIn& I, int64_t r, float* f) {
-    const float sv = static_cast<float>(I.s[r]), o = static_cast<float>(I.opd[r]), d = o - 1.0f, rsv = I.rs[r];
+// a row's inputs to the features: s, 1 + d and the neighbour sum of s
+struct RowIn {
+    float s, opd, rs;
+};
+__device__ __forceinline__ RowIn row_in(const NetIn& I, int64_t r) {
+    return RowIn{static_cast<float>(I.s[r]), static_cast<float>(I.opd[r]), I.rs[r]};
+}
+__device__ __forceinline__ void features8_from(const NetIn& I, const RowIn& x, float* f) {
+    const float sv = x.s, o = x.opd, d = o - 1.0f, rsv = x.rs;
     const float inv = 1.0f / o;
     f[0] = sv;
     f[1] = d > 0.0f ? rsv / d : 0.0f;
@@ -395,6 +402,7 @@ __device__ __forceinline__ void features8(const NetIn& I, int64_t r, float* f) {
     f[6] = 1.0f;
     f[7] = 0.0f;
 }
+__device__ __forceinline__ void features8(const NetIn& I, int64_t r, float* f) { features8_from(I, row_in(I, r), f); }
 
 // Layer 1 of the tile at row0: y (D layout) = X0 W1 + b1, h = BF16 relu(y)
 // (D layout), and h into the wave's LDS tile Hs[row][unit].
@@ -480,11 +488,10 @@ inline unsigned bwd_blocks(int64_t n) {
 // Activations never leave registers.
 // Layer 1 of the tile at row0 in this form: h[t][q] = H1[row li][16t + 4kq + q]
 // (BF16-rounded); y1 before the relu.
-__device__ __forceinline__ void tile_layer1_t(const NetIn& I, const NetW& W, int64_t row0, int li, int kq,
+__device__ __forceinline__ void tile_layer1_t(const NetIn& I, const NetW& W, const RowIn& x, int li, int kq,
                                               float y1[4][4], float h[4][4]) {
-    const int64_t r = min(row0 + li, I.n - 1);
     float f[8];
-    features8(I, r, f);
+    features8_from(I, x, f);
     const bf16x4 b = kq == 0 ? pack4(f[0], f[1], f[2], f[3]) : kq == 1 ? pack4(f[4], f[5], f[6], f[7])
                                                                        : pack4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
@@ -506,11 +513,16 @@ __global__ __launch_bounds__(kBlock) void k_net_l1(NetIn I, uint16_t* __restrict
     __syncthreads();
     const int wid = wave_id(), lane = lane_id(), li = lane & 15, kq = lane >> 4;
     const int64_t tiles = (I.n + 15) / 16;
-    for (int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; tt < tiles;
-         tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
-        const int64_t row0 = tt * 16;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    // each tile's row inputs load while the tile before it computes
+    RowIn x = tt < tiles ? row_in(I, min(tt * 16 + li, I.n - 1)) : RowIn{0.f, 1.f, 0.f};
+    for (; tt < tiles; tt += stride) {
+        const int64_t row0 = tt * 16, tn = tt + stride;
+        const RowIn xn = tn < tiles ? row_in(I, min(tn * 16 + li, I.n - 1)) : RowIn{0.f, 1.f, 0.f};
         float y1[4][4], h[4][4];
-        tile_layer1_t(I, W, row0, li, kq, y1, h);
+        tile_layer1_t(I, W, x, li, kq, y1, h);
+        x = xn;
         f32x4 pt = kZero4;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
@@ -529,16 +541,31 @@ __global__ __launch_bounds__(kBlock) void k_net_l2(NetIn I, const uint16_t* __re
     const double lo = I.stats[1], hi = I.stats[2];
     const float c0 = I.p[kOffC0];
     const int64_t tiles = (I.n + 15) / 16;
-    for (int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid; tt < tiles;
-         tt += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
-        const int64_t row0 = tt * 16;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+    int64_t tt = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wid;
+    // each tile's row inputs and message load while the tile before it computes
+    auto msg = [&](int64_t t) {
+        return *reinterpret_cast<const bf16x4*>(M + min(t * 16 + li, I.n - 1) * kMsg + 4 * kq);
+    };
+    RowIn x = RowIn{0.f, 1.f, 0.f};
+    bf16x4 bm{};
+    if (tt < tiles) {
+        x = row_in(I, min(tt * 16 + li, I.n - 1));
+        bm = msg(tt);
+    }
+    for (; tt < tiles; tt += stride) {
+        const int64_t row0 = tt * 16, tn = tt + stride;
+        RowIn xn = RowIn{0.f, 1.f, 0.f};
+        bf16x4 bmn{};
+        if (tn < tiles) {
+            xn = row_in(I, min(tn * 16 + li, I.n - 1));
+            bmn = msg(tn);
+        }
         float y1[4][4], h[4][4];
-        tile_layer1_t(I, W, row0, li, kq, y1, h);
+        tile_layer1_t(I, W, x, li, kq, y1, h);
         bf16x4 bh[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) bh[ks] = pack4(h[ks][0], h[ks][1], h[ks][2], h[ks][3]);
-        const int64_t r = min(row0 + li, I.n - 1);
-        const bf16x4 bm = *reinterpret_cast<const bf16x4*>(M + r * kMsg + 4 * kq);
         float o = 0.f;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -556,6 +583,8 @@ __global__ __launch_bounds__(kBlock) void k_net_l2(NetIn I, const uint16_t* __re
         o += __shfl_xor(o, 32, 64);
         if (kq == 0 && row0 + li < I.n)
             z0[row0 + li] = lo + (hi - lo) / (1.0 + exp(-static_cast<double>(o + c0)));
+        x = xn;
+        bm = bmn;
     }
 }
 
